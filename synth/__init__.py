@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP-path tests.
+
+This module holds no arithmetic of the method (no transforms of the solver,
+no projection, no mask, no time stepping): only initial velocity fields with
+known closed forms, seeded random fields, wing triangulations in their own
+frame, and the numeric parameters of each workload.  The paper's measured
+wing geometry and flow data are not used; these inputs stand in with the
+shapes of its revolving-wing runs (Sec. 4.2.2, Sec. 5).
+"""
+
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# velocity fields
+# ---------------------------------------------------------------------------
+
+
+def _coords(n, L):
+    nx, ny, nz = n
+    lx, ly, lz = L
+    x = np.arange(nx) * (2.0 * np.pi / nx)   # phase 2 pi x / L
+    y = np.arange(ny) * (2.0 * np.pi / ny)
+    z = np.arange(nz) * (2.0 * np.pi / nz)
+    return x[None, None, :], y[None, :, None], z[:, None, None]
+
+
+def taylor_green_3d(n, L=(2 * np.pi,) * 3):
+    """u = (sin x cos y cos z, -cos x sin y cos z, 0) in phase coordinates 2 pi x_j / L_j."""
+    x, y, z = _coords(n, L)
+    nx, ny, nz = n
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = np.sin(x) * np.cos(y) * np.cos(z)
+    u[1] = -np.cos(x) * np.sin(y) * np.cos(z)
+    return u
+
+
+def taylor_green_2d(n, L=(2 * np.pi,) * 3):
+    """u = (sin x cos y, -cos x sin y, 0), independent of z."""
+    x, y, z = _coords(n, L)
+    nx, ny, nz = n
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = np.sin(x) * np.cos(y) + 0.0 * z
+    u[1] = -np.cos(x) * np.sin(y) + 0.0 * z
+    return u
+
+
+def random_field(shape, seed):
+    """Gaussian white noise (FP64) of any shape."""
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def random_solenoidal(n, L, seed=0, energy=1.0, slope=-11.0 / 6.0):
+    """Random divergence-free, band-limited field with a k^(-5/3) energy spectrum.
+
+    Construction (Rogallo's method, not the solver's projection): every mode
+    with 1 <= |m| and 3|m_j| < N_j gets amplitude |m|^slope along two unit
+    vectors orthogonal to its wave vector (a fixed-axis Craya-Herring frame),
+    with complex Gaussian coefficients from ``default_rng(seed)``.  The real
+    part of the inverse numpy FFT keeps the field divergence-free (each mode
+    and its conjugate partner stay orthogonal to their wave vectors); it is then
+    scaled so that E = <|u|^2>/2 = ``energy``.
+    """
+    nx, ny, nz = n
+    lx, ly, lz = L
+    rng = np.random.default_rng(seed)
+
+    def modes(m):
+        j = np.arange(m)
+        return np.where(j <= m // 2, j, j - m)
+
+    mx = modes(nx)[None, None, :].astype(np.float64)
+    my = modes(ny)[None, :, None].astype(np.float64)
+    mz = modes(nz)[:, None, None].astype(np.float64)
+    kx = np.broadcast_to(2 * np.pi * mx / lx, (nz, ny, nx))
+    ky = np.broadcast_to(2 * np.pi * my / ly, (nz, ny, nx))
+    kz = np.broadcast_to(2 * np.pi * mz / lz, (nz, ny, nx))
+    kvec = np.stack([kx, ky, kz], axis=-1)
+    kmag = np.sqrt(np.sum(kvec * kvec, axis=-1))
+    mmag = np.sqrt(mx * mx + my * my + mz * mz)
+    keep = ((3 * np.abs(mx) < nx) & (3 * np.abs(my) < ny) & (3 * np.abs(mz) < nz) & (mmag >= 1.0))
+
+    # Craya-Herring frame: e1 = k x a / |k x a|, e2 = khat x e1, with a = e_z
+    # unless k is parallel to e_z (then a = e_x).
+    a = np.zeros_like(kvec)
+    par = (np.abs(kx) + np.abs(ky)) == 0.0
+    a[..., 2] = np.where(par, 0.0, 1.0)
+    a[..., 0] = np.where(par, 1.0, 0.0)
+    e1 = np.cross(kvec, a)
+    e1 /= np.maximum(np.linalg.norm(e1, axis=-1, keepdims=True), 1e-300)
+    khat = kvec / np.maximum(kmag[..., None], 1e-300)
+    e2 = np.cross(khat, e1)
+
+    c1 = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    c2 = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    amp = np.where(keep, np.power(np.maximum(mmag, 1.0), slope), 0.0)
+    spec = amp[..., None] * (c1[..., None] * e1 + c2[..., None] * e2)
+    u = np.stack([np.fft.ifftn(spec[..., c]).real for c in range(3)])
+    e = 0.5 * np.mean(np.sum(u * u, axis=0))
+    return u * math.sqrt(energy / e)
+
+
+# ---------------------------------------------------------------------------
+# wing triangulations (wing frame; no pose)
+# ---------------------------------------------------------------------------
+
+
+def grid_triangles(ns, nc):
+    """Triangles of an ns x nc vertex grid (vertex id = j * ns + i, i along span).
+
+    Each quad (i, j)-(i+1, j+1) is split along the diagonal (i, j) -> (i+1, j+1)."""
+    tri = []
+    for j in range(nc - 1):
+        for i in range(ns - 1):
+            v00 = j * ns + i
+            v10 = v00 + 1
+            v01 = v00 + ns
+            v11 = v01 + 1
+            tri.append((v00, v10, v11))
+            tri.append((v00, v11, v01))
+    return np.array(tri, dtype=np.int32)
+
+
+def plate_span_chord(ns, nc, span, chord):
+    """Span coordinate s in [0, span] and chord coordinate c in [-chord/2, chord/2] per vertex."""
+    i = np.arange(ns)
+    j = np.arange(nc)
+    s = np.tile(i * (span / (ns - 1)), nc)
+    c = np.repeat(-0.5 * chord + j * (chord / (nc - 1)), ns)
+    return s, c
+
+
+def flat_rectangle(center, u_axis, v_axis, a, b, ns=2, nc=2):
+    """Vertices (ns*nc, 3) of a flat rectangle of half-sides a (along u_axis) and b (along v_axis)."""
+    center = np.asarray(center, dtype=np.float64)
+    u_axis = np.asarray(u_axis, dtype=np.float64)
+    v_axis = np.asarray(v_axis, dtype=np.float64)
+    s = np.linspace(-a, a, ns)
+    t = np.linspace(-b, b, nc)
+    pts = [center + s[i] * u_axis + t[j] * v_axis for j in range(nc) for i in range(ns)]
+    return np.array(pts), grid_triangles(ns, nc)
+
+
+def random_triangles(nt, lo, hi, size, seed):
+    """A soup of nt random triangles with vertices in a box, for distance tests."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    centers = lo + (hi - lo) * rng.random((nt, 3))
+    x = (centers[:, None, :] + size * (rng.random((nt, 3, 3)) - 0.5)).reshape(-1, 3)
+    tri = np.arange(3 * nt, dtype=np.int32).reshape(nt, 3)
+    return x, tri
+
+
+# ---------------------------------------------------------------------------
+# workload parameters (readings of the paper's setups)
+# ---------------------------------------------------------------------------
+
+PROFILE_COS = 0
+PROFILE_TANH = 1
+
+
+def config0(with_plate):
+    """32^3 Taylor-Green box [0, 2 pi)^3, nu = 0.01, dt = 1e-3, 20 steps; optional static plate."""
+    n = (32, 32, 32)
+    L = (2 * np.pi,) * 3
+    dx = L[0] / n[0]
+    cfg = dict(n=n, L=L, nu=0.01, eta=1e-3, tw=2 * dx, h=dx, profile=PROFILE_TANH,
+               dt=1e-3, steps=20)
+    if with_plate:
+        # 1.0 x 0.3 rectangle, normal e_x, 1.0 along y, 0.3 along z, centred where the
+        # Taylor-Green flow is (1, 0, 0): head-on.
+        x, tri = flat_rectangle((np.pi / 2, np.pi, np.pi), (0, 1, 0), (0, 0, 1), 0.5, 0.15)
+        cfg["wing"] = (x, np.zeros_like(x), tri)
+    return cfg
+
+
+def revolving_plate(n=128, box=12.0, fixed_eta=None, t_ramp=0.4):
+    """Rigid revolving plate (span R = 3, chord 1, alpha = 45 deg) in a cubic box of side 4R.
+
+    Time unit = one revolution: Omega = 2 pi, tip speed 6 pi, Re = Omega R c / nu = 1800
+    gives nu = pi / 300.  eta keeps K_eta = sqrt(nu eta)/dx constant (2.5e-3 at 128^3).
+    """
+    dx = box / n
+    eta = fixed_eta if fixed_eta is not None else 2.5e-3 * (128.0 / n) ** 2
+    ns, nc = 41, 13
+    s, c = plate_span_chord(ns, nc, 3.0, 1.0)
+    return dict(n=(n, n, n), L=(box, box, box), nu=math.pi / 300.0, eta=eta,
+                tw=2 * dx, h=dx, profile=PROFILE_COS,
+                alpha=math.pi / 4, omega=2 * math.pi, t_ramp=t_ramp,
+                axis_point=(box / 2, box / 2, box / 2),
+                span_coord=s, chord_coord=c, tri=grid_triangles(ns, nc),
+                cfl=0.1, c_eta=2.0 / 3.0, dt_max=1e-2)
