@@ -1,0 +1,188 @@
+/*
+ * fsi.h - C ABI of the MI355X (gfx950) penalized pseudo-spectral Navier-Stokes step.
+ *
+ * The library advances the incompressible, volume-penalized Navier-Stokes
+ * equations of Sec. 4.1 (penalized NS equations in rotational form,
+ * Pi = p + |u|^2/2) on a periodic box with a Fourier pseudo-spectral method:
+ *
+ *   du/dt = u x omega - grad Pi + nu lap u - (chi/eta)(u - u_s),   div u = 0,
+ *
+ * with the mask chi rebuilt every step from a triangulated wing mid-surface
+ * (Sec. 4.1, Eq. (mask_function) and the distance function that follows it),
+ * the solid velocity u_s interpolated barycentrically from the mesh vertex
+ * velocities, the Leray projection, an integrating factor for viscosity, a
+ * variable-step Adams-Bashforth scheme (Sec. 4.1, staggered scheme paragraph)
+ * with adaptive dt, and the penalization force integral used for the lift and
+ * drag of Sec. 4.2.2.
+ *
+ * Conventions
+ *  - Every function returns fsi_status (0 = FSI_OK, < 0 = error). Nothing
+ *    throws or longjmps across the ABI. After an error, fsi_last_error()
+ *    returns a message owned by the context (valid until the next call).
+ *  - Argument checks run on the host before any GPU work; a call that fails
+ *    them leaves the context state unchanged.
+ *  - Grid: nx, ny, nz even, each of the form 2^a 3^b 5^c, 8 <= n <= 2048.
+ *    Grid point (i, j, k) sits at (i lx/nx, j ly/ny, k lz/nz).
+ *  - Physical host arrays are C-ordered doubles [comp][nz][ny][nx] (x fastest).
+ *  - Spectral host arrays use the compact dealiased layout: modes with
+ *    3|m_j| < n_j on every axis (2/3 rule), stored [iz][iy][ix] as interleaved
+ *    (re, im) doubles, ix = m_x in [0, Kx], iy/iz in natural order
+ *    (i <= K -> m = i, i > K -> m = i - (2K + 1)), K_j = max{m : 3m < n_j}.
+ *    Coefficients are normalized: f(x) = sum_k fhat_k exp(i k.x) with the
+ *    Hermitian partner modes (m_x < 0) implied.
+ *  - The caller owns every host array it passes; the library copies in and
+ *    out and never keeps a host pointer. The context owns all device memory.
+ *  - Work is queued on the stream given in the descriptor (NULL = default
+ *    stream). Calls documented as "synchronizes" wait for that stream.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef FSI_H
+#define FSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsi_ctx fsi_ctx;
+
+typedef enum {
+  FSI_OK = 0,
+  FSI_EINVAL = -1,      /* invalid argument or descriptor */
+  FSI_ENOMEM = -2,      /* device or host allocation failed */
+  FSI_EDEVICE = -3,     /* HIP runtime error (no device, launch failure, ...) */
+  FSI_EBOUNDS = -4,     /* wing mesh (enlarged by the mask support) leaves the box */
+  FSI_ESTATE = -5,      /* call not valid in the current state */
+  FSI_ENAN = -6,        /* non-finite value detected on the device */
+  FSI_ESTABILITY = -7   /* dt * max(chi) / eta > 1: explicit penalization unstable */
+} fsi_status;
+
+/* Mask profiles: 0 = cosine ramp of Eq. (mask_function), support t_w + h;
+ * 1 = tanh ramp (1 - tanh((delta - t_w)/h))/2, cut to zero at delta >= t_w + 6h. */
+enum { FSI_PROFILE_COS = 0, FSI_PROFILE_TANH = 1 };
+/* Arithmetic of the bulk fields: 0 = FP32 fields and transforms with FP64
+ * reductions and FP64 dt; 1 = FP64 throughout. */
+enum { FSI_PREC_FP32 = 0, FSI_PREC_FP64 = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;   /* grid (see conventions) */
+  double lx, ly, lz;    /* periodic box [0, l)^3, > 0 */
+  double nu;            /* kinematic viscosity, >= 0 */
+  double eta;           /* penalization parameter C_eta of Sec. 4.1, > 0 */
+  double tw;            /* wing half-thickness t_w of Eq. (mask_function), >= 0 */
+  double h;             /* smoothing half-width h of Eq. (mask_function), > 0 */
+  int32_t mask_profile; /* FSI_PROFILE_* */
+  int32_t precision;    /* FSI_PREC_* */
+  int32_t reserved;     /* must be 0 */
+  void* stream;         /* hipStream_t to queue work on; NULL = default stream */
+} fsi_desc;
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int32_t fsi_version(void);
+
+/* Create a context: plans the transforms and allocates every device buffer.
+ * On success *out owns the context; on error *out is NULL. */
+fsi_status fsi_create(const fsi_desc* desc, fsi_ctx** out);
+
+/* Destroy a context (synchronizes its stream first). NULL is accepted. */
+fsi_status fsi_destroy(fsi_ctx* ctx);
+
+/* Message describing the last error on this context ("" if none). Owned by ctx. */
+const char* fsi_last_error(const fsi_ctx* ctx);
+
+/* Message of the last fsi_create failure (thread-local, static storage). */
+const char* fsi_create_error(void);
+
+/* Band sizes: K[0..2] = (Kx, Ky, Kz); compact spectral component length in complex values. */
+fsi_status fsi_band(const fsi_ctx* ctx, int32_t K[3], int64_t* compact_len);
+
+/* Set the velocity from a physical host field u[3][nz][ny][nx]: the field is
+ * transformed, truncated to the 2/3 band and Leray-projected (Sec. 4.1,
+ * div u = 0). Resets the Adams-Bashforth history and the step counter; the
+ * next step is an integrating-factor Euler step. Synchronizes. */
+fsi_status fsi_set_velocity(fsi_ctx* ctx, const double* u_host);
+
+/* Same from a device array u[3][nz][ny][nx] of dtype 0 = float, 1 = double
+ * (borrowed for the duration of the call only). */
+fsi_status fsi_set_velocity_device(fsi_ctx* ctx, const void* u_dev, int32_t dtype);
+
+/* Physical velocity u[3][nz][ny][nx] of the current state. Synchronizes. */
+fsi_status fsi_get_velocity(fsi_ctx* ctx, double* u_host);
+
+/* Compact spectral velocity uhat[3][compact_len] (interleaved re, im). Synchronizes. */
+fsi_status fsi_get_spectrum(fsi_ctx* ctx, double* uhat_host);
+
+/* Wing mid-surface mesh (Sec. 4.1): nv vertices x[nv][3], their velocities
+ * v[nv][3] in the box frame (Eq. (relative_velocities) already applied), nt
+ * triangles tri[nt][3] of 0-based vertex ids. Copied. The mesh enlarged by the
+ * mask support radius must lie in [0, l] on every axis (no periodic wrap),
+ * else FSI_EBOUNDS. nt = 0 clears the wing. */
+fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double* v,
+                        int32_t nt, const int32_t* tri);
+
+/* Mask chi[nz][ny][nx] and solid velocity us[3][nz][ny][nx] built from the
+ * current wing (zero everywhere without a wing). Synchronizes. */
+fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us);
+
+/* One step with a given dt > 0 (queued on the stream, no host sync).
+ * FSI_ESTABILITY if a wing is set and dt > eta. */
+fsi_status fsi_step(fsi_ctx* ctx, double dt);
+
+/* One step with dt computed on the device from the current state:
+ * dt = min(cfl * dx_min / u_max, c_eta * eta, dt_max), the first term taken as
+ * +inf when u_max = 0. Requires cfl > 0, 0 < c_eta <= 1, dt_max > 0. */
+fsi_status fsi_step_adaptive(fsi_ctx* ctx, double cfl, double c_eta, double dt_max);
+
+/* Diagnostics of the last step, evaluated at the start of that step (t^n):
+ * F = force on the body (1/eta) * integral of chi (u - u_s) dV, dt used,
+ * E = kinetic energy (1/2) integral |u|^2 dV, umax = max |u|_2 over the grid
+ * points, t = time after the step, nstep = steps since fsi_set_velocity.
+ * Any pointer may be NULL. Synchronizes; FSI_ENAN if a non-finite value was met. */
+fsi_status fsi_get_step_info(fsi_ctx* ctx, double F[3], double* dt_used, double* E,
+                             double* umax, double* t, int64_t* nstep);
+
+/* Stand-alone transforms on the context's grid, for testing the FFT passes.
+ * r2c: physical f[nz][ny][nx] -> normalized compact band fhat (interleaved).
+ * c2r: compact band fhat -> physical f (real part of the inverse transform,
+ * Hermitian partners implied). Both synchronize. They use internal buffers and
+ * must not be interleaved with a step. */
+fsi_status fsi_fft_r2c(fsi_ctx* ctx, const double* f, double* fhat);
+fsi_status fsi_fft_c2r(fsi_ctx* ctx, const double* fhat, double* f);
+
+/* Save / restore the time-stepping state (velocity, previous nonlinear term,
+ * previous dt, time, step counter) in one of 64 slots held in device memory.
+ * Loading an empty slot is FSI_ESTATE. */
+fsi_status fsi_save_state(fsi_ctx* ctx, int32_t slot);
+fsi_status fsi_load_state(fsi_ctx* ctx, int32_t slot);
+
+/* Wait for all queued work of the context. */
+fsi_status fsi_synchronize(fsi_ctx* ctx);
+
+/* Per-pass timing with HIP events on the context stream (off by default).
+ * fsi_get_pass_times synchronizes, writes the summed milliseconds of each of
+ * the FSI_NPASS passes recorded since timing was enabled or last read, and
+ * the number of steps they cover, then resets the sums. Pass order: mask,
+ * z-inverse+curl, y-inverse, x-fused, reduce, y-forward, z-forward+update. */
+enum { FSI_NPASS = 7 };
+fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on);
+fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps);
+
+/* Rigid revolving-plate pose (Sec. 4.2.2, Eq. (revolving_angle) and
+ * Eq. (relative_velocities) without deformation). Host-only, FP64.
+ * Inputs: nv vertices with span coordinate s[i] (from the rotation axis) and
+ * chord coordinate c[i] (from the mid-chord line), pitch alpha, rotation rate
+ * omega, ramp time t_ramp, law (0 = Omega(t) = omega (1 - cos(pi t/t_ramp))/2
+ * until t_ramp then omega; 1 = phi(t) = omega (tau e^{-t/tau} + t - tau), tau =
+ * t_ramp), axis point axis[3]. At phi = 0 a vertex sits at axis + (s, c cos
+ * alpha, c sin alpha). Outputs x[nv][3], v[nv][3] (v = dphi/dt e_z x (x - axis))
+ * and phi_out[0..1] = (phi, dphi/dt) if non-NULL. */
+fsi_status fsi_plate_pose(int32_t nv, const double* s, const double* c, double t, double alpha,
+                          double omega, double t_ramp, int32_t law, const double axis[3],
+                          double* x, double* v, double* phi_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSI_H */

@@ -1,0 +1,217 @@
+// api.cpp - the extern "C" boundary declared in include/fsi.h.
+#include <math.h>
+#include <string.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "../../include/fsi.h"
+#include "engine.h"
+
+struct fsi_ctx {
+  fsi::EngineBase* eng = nullptr;
+};
+
+namespace {
+thread_local std::string g_create_error;
+
+fsi_status guard(fsi_ctx* c) { return (c && c->eng) ? FSI_OK : FSI_EINVAL; }
+}  // namespace
+
+extern "C" {
+
+int32_t fsi_version(void) { return 100; }
+
+const char* fsi_create_error(void) { return g_create_error.c_str(); }
+
+fsi_status fsi_create(const fsi_desc* desc, fsi_ctx** out) {
+  if (!out) return FSI_EINVAL;
+  *out = nullptr;
+  if (!desc) {
+    g_create_error = "descriptor is NULL";
+    return FSI_EINVAL;
+  }
+  const std::string bad = fsi::check_desc(*desc);
+  if (!bad.empty()) {
+    g_create_error = bad;
+    return FSI_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_create_error = "no HIP device available";
+    return FSI_EDEVICE;
+  }
+  fsi_ctx* c = new (std::nothrow) fsi_ctx();
+  if (!c) return FSI_ENOMEM;
+  c->eng = desc->precision == FSI_PREC_FP64 ? fsi::make_engine_f64() : fsi::make_engine_f32();
+  const fsi_status st = c->eng->init(*desc);
+  if (st != FSI_OK) {
+    g_create_error = c->eng->err;
+    delete c->eng;
+    delete c;
+    return st;
+  }
+  g_create_error.clear();
+  *out = c;
+  return FSI_OK;
+}
+
+fsi_status fsi_destroy(fsi_ctx* ctx) {
+  if (!ctx) return FSI_OK;
+  delete ctx->eng;
+  delete ctx;
+  return FSI_OK;
+}
+
+const char* fsi_last_error(const fsi_ctx* ctx) {
+  if (!ctx || !ctx->eng) return "invalid context";
+  return ctx->eng->err.c_str();
+}
+
+fsi_status fsi_band(const fsi_ctx* ctx, int32_t K[3], int64_t* compact_len) {
+  if (!ctx || !ctx->eng || !K || !compact_len) return FSI_EINVAL;
+  int k[3];
+  long long cl;
+  ctx->eng->band(k, &cl);
+  K[0] = k[0];
+  K[1] = k[1];
+  K[2] = k[2];
+  *compact_len = cl;
+  return FSI_OK;
+}
+
+fsi_status fsi_set_velocity(fsi_ctx* ctx, const double* u_host) {
+  if (guard(ctx) != FSI_OK || !u_host) return FSI_EINVAL;
+  return ctx->eng->set_velocity_host(u_host);
+}
+
+fsi_status fsi_set_velocity_device(fsi_ctx* ctx, const void* u_dev, int32_t dtype) {
+  if (guard(ctx) != FSI_OK || !u_dev) return FSI_EINVAL;
+  return ctx->eng->set_velocity_device(u_dev, dtype);
+}
+
+fsi_status fsi_get_velocity(fsi_ctx* ctx, double* u_host) {
+  if (guard(ctx) != FSI_OK || !u_host) return FSI_EINVAL;
+  return ctx->eng->get_velocity(u_host);
+}
+
+fsi_status fsi_get_spectrum(fsi_ctx* ctx, double* uhat_host) {
+  if (guard(ctx) != FSI_OK || !uhat_host) return FSI_EINVAL;
+  return ctx->eng->get_spectrum(uhat_host);
+}
+
+fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double* v, int32_t nt,
+                        const int32_t* tri) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->set_wing(nv, x, v, nt, tri);
+}
+
+fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us) {
+  if (guard(ctx) != FSI_OK || !chi || !us) return FSI_EINVAL;
+  return ctx->eng->get_mask(chi, us);
+}
+
+fsi_status fsi_step(fsi_ctx* ctx, double dt) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->step(false, dt, 0.0, 0.0, 0.0);
+}
+
+fsi_status fsi_step_adaptive(fsi_ctx* ctx, double cfl, double c_eta, double dt_max) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->step(true, 0.0, cfl, c_eta, dt_max);
+}
+
+fsi_status fsi_get_step_info(fsi_ctx* ctx, double F[3], double* dt_used, double* E, double* umax, double* t,
+                             int64_t* nstep) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  long long ns = 0;
+  const fsi_status st = ctx->eng->step_info(F, dt_used, E, umax, t, &ns);
+  if (nstep) *nstep = ns;
+  return st;
+}
+
+fsi_status fsi_fft_r2c(fsi_ctx* ctx, const double* f, double* fhat) {
+  if (guard(ctx) != FSI_OK || !f || !fhat) return FSI_EINVAL;
+  return ctx->eng->fft_r2c(f, fhat);
+}
+
+fsi_status fsi_fft_c2r(fsi_ctx* ctx, const double* fhat, double* f) {
+  if (guard(ctx) != FSI_OK || !f || !fhat) return FSI_EINVAL;
+  return ctx->eng->fft_c2r(fhat, f);
+}
+
+fsi_status fsi_save_state(fsi_ctx* ctx, int32_t slot) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->save_state(slot);
+}
+
+fsi_status fsi_load_state(fsi_ctx* ctx, int32_t slot) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->load_state(slot);
+}
+
+fsi_status fsi_synchronize(fsi_ctx* ctx) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->synchronize();
+}
+
+fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->set_timing(on != 0);
+}
+
+fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps) {
+  if (guard(ctx) != FSI_OK || !ms) return FSI_EINVAL;
+  int n = 0;
+  const fsi_status st = ctx->eng->pass_times(ms, &n);
+  if (nsteps) *nsteps = n;
+  return st;
+}
+
+// Rigid revolving plate (Sec. 4.2.2): rotation angle from the ramp law or
+// Eq. (revolving_angle); frame velocity Omega e_z x r (Eq. (relative_velocities)
+// with a rigid wing).
+fsi_status fsi_plate_pose(int32_t nv, const double* s, const double* c, double t, double alpha, double omega,
+                          double t_ramp, int32_t law, const double axis[3], double* x, double* v,
+                          double* phi_out) {
+  if (nv < 0 || (nv > 0 && (!s || !c || !x || !v)) || !axis) return FSI_EINVAL;
+  if (!std::isfinite(t) || !std::isfinite(alpha) || !std::isfinite(omega) || !std::isfinite(t_ramp))
+    return FSI_EINVAL;
+  if (law != 0 && law != 1) return FSI_EINVAL;
+  if (law == 1 && !(t_ramp > 0)) return FSI_EINVAL;
+  double phi, rate;
+  if (law == 0) {
+    const double tr = t_ramp > 0 ? t_ramp : 0.0;
+    if (tr == 0.0 || t >= tr) {
+      phi = 0.5 * omega * tr + omega * (t - tr);
+      rate = omega;
+    } else {
+      const double a = M_PI * t / tr;
+      rate = 0.5 * omega * (1.0 - cos(a));
+      phi = 0.5 * omega * (t - (tr / M_PI) * sin(a));
+    }
+  } else {
+    const double e = exp(-t / t_ramp);
+    phi = omega * (t_ramp * e + t - t_ramp);
+    rate = omega * (1.0 - e);
+  }
+  const double cp = cos(phi), sp = sin(phi), ca = cos(alpha), sa = sin(alpha);
+  for (int32_t i = 0; i < nv; ++i) {
+    const double lx = s[i], ly = c[i] * ca, lz = c[i] * sa;
+    const double rx = cp * lx - sp * ly, ry = sp * lx + cp * ly;
+    x[3 * i] = axis[0] + rx;
+    x[3 * i + 1] = axis[1] + ry;
+    x[3 * i + 2] = axis[2] + lz;
+    v[3 * i] = -rate * ry;
+    v[3 * i + 1] = rate * rx;
+    v[3 * i + 2] = 0.0;
+  }
+  if (phi_out) {
+    phi_out[0] = phi;
+    phi_out[1] = rate;
+  }
+  return FSI_OK;
+}
+
+}  // extern "C"

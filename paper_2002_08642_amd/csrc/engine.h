@@ -1,0 +1,42 @@
+// engine.h - the step engine behind the C ABI (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fsi.h"
+
+namespace fsi {
+
+class EngineBase {
+ public:
+  virtual ~EngineBase() {}
+  virtual fsi_status init(const fsi_desc& d) = 0;
+  virtual void band(int K[3], long long* clen) const = 0;
+  virtual fsi_status set_velocity_host(const double* u) = 0;
+  virtual fsi_status set_velocity_device(const void* u, int dtype) = 0;
+  virtual fsi_status get_velocity(double* u) = 0;
+  virtual fsi_status get_spectrum(double* uh) = 0;
+  virtual fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) = 0;
+  virtual fsi_status get_mask(double* chi, double* us) = 0;
+  virtual fsi_status step(bool adaptive, double dt, double cfl, double c_eta, double dt_max) = 0;
+  virtual fsi_status step_info(double F[3], double* dt, double* E, double* umax, double* t, long long* nstep) = 0;
+  virtual fsi_status fft_r2c(const double* f, double* fh) = 0;
+  virtual fsi_status fft_c2r(const double* fh, double* f) = 0;
+  virtual fsi_status save_state(int slot) = 0;
+  virtual fsi_status load_state(int slot) = 0;
+  virtual fsi_status synchronize() = 0;
+  virtual fsi_status set_timing(bool on) = 0;
+  virtual fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) = 0;
+  std::string err;
+};
+
+EngineBase* make_engine_f32();
+EngineBase* make_engine_f64();
+
+// Validates a descriptor; returns an empty string if it is acceptable.
+std::string check_desc(const fsi_desc& d);
+
+}  // namespace fsi

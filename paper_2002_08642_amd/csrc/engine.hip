@@ -1,0 +1,871 @@
+// engine.hip - host orchestration of the penalized pseudo-spectral step.
+//
+// Owns the device buffers, the transform plans and the time-stepping state,
+// and queues the passes of one step on the context stream (Sec. 4.1: the
+// fluid is advanced with the mask and solid velocity of the current wing
+// position, then the Adams-Bashforth update is applied).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "launch.h"
+
+namespace fsi {
+
+#define FSI_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+      return FSI_EDEVICE;                                                      \
+    }                                                                          \
+  } while (0)
+
+#define FSI_TRY(expr)              \
+  do {                             \
+    fsi_status s_ = (expr);        \
+    if (s_ != FSI_OK) return s_;   \
+  } while (0)
+
+static bool factor_ok(int n) {
+  if (n < 8 || n > 2048 || (n & 1)) return false;
+  int m = n;
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+static bool make_plan(int n, FftPlan& p) {
+  p.n = n;
+  p.nst = 0;
+  int m = n;
+  for (int r : {8, 4, 2, 5, 3}) {
+    while (m % r == 0) {
+      if (p.nst >= kMaxStages) return false;
+      p.radix[p.nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+static int band_k(int n) { return (n - 1) / 3; }  // largest m with 3m < n
+
+std::string check_desc(const fsi_desc& d) {
+  if (!factor_ok(d.nx) || !factor_ok(d.ny) || !factor_ok(d.nz))
+    return "grid sizes must be even, 8..2048 and of the form 2^a 3^b 5^c";
+  if (!(d.lx > 0) || !(d.ly > 0) || !(d.lz > 0) || !std::isfinite(d.lx) || !std::isfinite(d.ly) || !std::isfinite(d.lz))
+    return "box lengths must be positive and finite";
+  if (!(d.nu >= 0) || !std::isfinite(d.nu)) return "nu must be >= 0";
+  if (!(d.eta > 0) || !std::isfinite(d.eta)) return "eta must be > 0";
+  if (!(d.tw >= 0) || !std::isfinite(d.tw)) return "tw must be >= 0";
+  if (!(d.h > 0) || !std::isfinite(d.h)) return "h must be > 0";
+  if (d.mask_profile != FSI_PROFILE_COS && d.mask_profile != FSI_PROFILE_TANH) return "unknown mask profile";
+  if (d.precision != FSI_PREC_FP32 && d.precision != FSI_PREC_FP64) return "unknown precision";
+  if (d.reserved != 0) return "reserved field must be 0";
+  return "";
+}
+
+template <typename T>
+class Engine : public EngineBase {
+ public:
+  ~Engine() override { release(); }
+
+  fsi_status init(const fsi_desc& dd) override {
+    d = dd;
+    s = (hipStream_t)d.stream;
+    nx = d.nx;
+    ny = d.ny;
+    nz = d.nz;
+    Kx = band_k(nx);
+    Ky = band_k(ny);
+    Kz = band_k(nz);
+    kx1 = Kx + 1;
+    nby = 2 * Ky + 1;
+    nbz = 2 * Kz + 1;
+    C1 = (long long)nby * kx1;
+    clen = (long long)nbz * C1;
+    Alen = (long long)nz * C1;
+    Blen = (long long)nz * ny * kx1;
+    npts = (long long)nx * ny * nz;
+    dxs[0] = d.lx / nx;
+    dxs[1] = d.ly / ny;
+    dxs[2] = d.lz / nz;
+    dV = dxs[0] * dxs[1] * dxs[2];
+    dx_min = std::min(dxs[0], std::min(dxs[1], dxs[2]));
+    rsup = d.tw + (d.mask_profile == FSI_PROFILE_COS ? 1.0 : 6.0) * d.h;
+    if (!make_plan(nx, px) || !make_plan(ny, py) || !make_plan(nz, pz)) {
+      err = "cannot factor grid";
+      return FSI_EINVAL;
+    }
+    for (int n : {ny, nz}) {
+      if (col_width<T>(n) == 0) {
+        err = "grid too long for the column passes in this precision";
+        return FSI_EINVAL;
+      }
+    }
+    const int L = xpass_lines<T>(nx);
+    if ((long long)nx * 3 * L > (long long)XMaxE<T>::value * kNT || ((long long)ny * nz) % L != 0) {
+      err = "nx too long for the x pass in this precision";
+      return FSI_EINVAL;
+    }
+    ngroups = (int)(((long long)ny * nz) / L);
+    npart = std::min(ngroups, 4096);
+
+    FSI_TRY(alloc(&uh, 3 * clen));
+    FSI_TRY(alloc(&nh, 3 * clen));
+    FSI_TRY(alloc(&A, 6 * Alen));
+    FSI_TRY(alloc(&B, 6 * Blen));
+    FSI_TRY(alloc(&partials, (long long)npart * 8));
+    FSI_TRY(alloc(&sc, 1));
+    FSI_HIP(hipHostMalloc((void**)&sc_host, sizeof(DevScalars), hipHostMallocDefault));
+    FSI_TRY(make_twiddles(nx, &twx));
+    FSI_TRY(make_twiddles(ny, &twy));
+    FSI_TRY(make_twiddles(nz, &twz));
+    FSI_HIP(hipMemsetAsync(uh, 0, sizeof(cpx<T>) * 3 * clen, s));
+    FSI_HIP(hipMemsetAsync(nh, 0, sizeof(cpx<T>) * 3 * clen, s));
+    FSI_TRY(reset_scalars());
+    FSI_HIP(hipStreamSynchronize(s));
+    slots.resize(64);
+    return FSI_OK;
+  }
+
+  void band(int K[3], long long* cl) const override {
+    K[0] = Kx;
+    K[1] = Ky;
+    K[2] = Kz;
+    *cl = clen;
+  }
+
+  // -- velocity in / out -----------------------------------------------------
+  fsi_status set_velocity_host(const double* u) override {
+    for (long long i = 0; i < 3 * npts; ++i)
+      if (!std::isfinite(u[i])) {
+        err = "non-finite value in the velocity";
+        return FSI_EINVAL;
+      }
+    FSI_TRY(ensure_phys());
+    FSI_TRY(upload_real(u, phys, 3 * npts));
+    return finish_set_velocity();
+  }
+
+  fsi_status set_velocity_device(const void* u, int dtype) override {
+    if (dtype != 0 && dtype != 1) {
+      err = "dtype must be 0 (float) or 1 (double)";
+      return FSI_EINVAL;
+    }
+    FSI_TRY(ensure_phys());
+    if ((dtype == 1) == (sizeof(T) == 8)) {
+      FSI_HIP(hipMemcpyAsync(phys, u, sizeof(T) * 3 * npts, hipMemcpyDeviceToDevice, s));
+    } else {
+      std::vector<double> h(3 * npts);
+      if (dtype == 1) {
+        FSI_HIP(hipMemcpyAsync(h.data(), u, sizeof(double) * 3 * npts, hipMemcpyDeviceToHost, s));
+        FSI_HIP(hipStreamSynchronize(s));
+      } else {
+        std::vector<float> f(3 * npts);
+        FSI_HIP(hipMemcpyAsync(f.data(), u, sizeof(float) * 3 * npts, hipMemcpyDeviceToHost, s));
+        FSI_HIP(hipStreamSynchronize(s));
+        for (long long i = 0; i < 3 * npts; ++i) h[i] = f[i];
+      }
+      FSI_TRY(upload_real(h.data(), phys, 3 * npts));
+    }
+    return finish_set_velocity();
+  }
+
+  fsi_status get_velocity(double* u) override {
+    FSI_TRY(ensure_phys());
+    FSI_TRY(run_inverse(uh, clen, 3, phys));
+    FSI_TRY(download_real(phys, u, 3 * npts));
+    return nan_status();
+  }
+
+  fsi_status get_spectrum(double* out) override {
+    std::vector<cpx<T>> h(3 * clen);
+    FSI_HIP(hipMemcpyAsync(h.data(), uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    for (long long i = 0; i < 3 * clen; ++i) {
+      out[2 * i] = (double)h[i].re;
+      out[2 * i + 1] = (double)h[i].im;
+    }
+    return nan_status();
+  }
+
+  // -- wing --------------------------------------------------------------------
+  fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) override {
+    if (nt < 0 || nv < 0 || (nt > 0 && (nv < 3 || !x || !v || !tri))) {
+      err = "invalid mesh sizes or pointers";
+      return FSI_EINVAL;
+    }
+    if (nt == 0) {
+      wing_nt = 0;
+      bnx = bny = bnz = 0;
+      return FSI_OK;
+    }
+    for (long long i = 0; i < 3LL * nt; ++i)
+      if (tri[i] < 0 || tri[i] >= nv) {
+        err = "triangle vertex id out of range";
+        return FSI_EINVAL;
+      }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (long long i = 0; i < nv; ++i)
+      for (int q = 0; q < 3; ++q) {
+        const double a = x[3 * i + q];
+        if (!std::isfinite(a) || !std::isfinite(v[3 * i + q])) {
+          err = "non-finite vertex position or velocity";
+          return FSI_EINVAL;
+        }
+        lo[q] = std::min(lo[q], a);
+        hi[q] = std::max(hi[q], a);
+      }
+    const double Ls[3] = {d.lx, d.ly, d.lz};
+    const int Ns[3] = {nx, ny, nz};
+    int i0[3], cnt[3];
+    for (int q = 0; q < 3; ++q) {
+      const double a = lo[q] - rsup, b = hi[q] + rsup;
+      if (a < 0.0 || b > Ls[q]) {
+        err = "wing bounding box enlarged by the mask support leaves the box";
+        return FSI_EBOUNDS;
+      }
+      i0[q] = std::max(0, (int)std::floor(a / dxs[q]));
+      const int i1 = std::min(Ns[q] - 1, (int)std::ceil(b / dxs[q]));
+      cnt[q] = std::max(0, i1 - i0[q] + 1);
+    }
+    const long long cells = (long long)cnt[0] * cnt[1] * cnt[2];
+    // stage the mesh through pinned memory
+    const size_t need = sizeof(double) * 6 * (size_t)nv + sizeof(int) * 3 * (size_t)nt;
+    if (need > stage_cap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      if (stage) FSI_HIP(hipHostFree(stage));
+      stage = nullptr;
+      FSI_HIP(hipHostMalloc(&stage, need * 2, hipHostMallocDefault));
+      stage_cap = need * 2;
+    }
+    if (stage_pending) FSI_HIP(hipEventSynchronize(stage_ev));
+    double* sx = (double*)stage;
+    double* sv = sx + 3 * (size_t)nv;
+    int* st = (int*)(sv + 3 * (size_t)nv);
+    memcpy(sx, x, sizeof(double) * 3 * (size_t)nv);
+    memcpy(sv, v, sizeof(double) * 3 * (size_t)nv);
+    memcpy(st, tri, sizeof(int) * 3 * (size_t)nt);
+    if (nv > mesh_vcap || nt > mesh_tcap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      free_dev(dx_);
+      free_dev(dv_);
+      free_dev(dtri_);
+      mesh_vcap = std::max(nv, mesh_vcap) * 2;
+      mesh_tcap = std::max(nt, mesh_tcap) * 2;
+      FSI_TRY(alloc(&dx_, 3LL * mesh_vcap));
+      FSI_TRY(alloc(&dv_, 3LL * mesh_vcap));
+      FSI_TRY(alloc(&dtri_, 3LL * mesh_tcap));
+    }
+    if (cells > box_cap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      free_dev(key1);
+      free_dev(key2);
+      free_dev(chi);
+      free_dev(us);
+      box_cap = cells + cells / 4 + 64;
+      FSI_TRY(alloc(&key1, box_cap));
+      FSI_TRY(alloc(&key2, box_cap));
+      FSI_TRY(alloc(&chi, box_cap));
+      FSI_TRY(alloc(&us, 3 * box_cap));
+    }
+    FSI_HIP(hipMemcpyAsync(dx_, sx, sizeof(double) * 3 * (size_t)nv, hipMemcpyHostToDevice, s));
+    FSI_HIP(hipMemcpyAsync(dv_, sv, sizeof(double) * 3 * (size_t)nv, hipMemcpyHostToDevice, s));
+    FSI_HIP(hipMemcpyAsync(dtri_, st, sizeof(int) * 3 * (size_t)nt, hipMemcpyHostToDevice, s));
+    if (!stage_ev) FSI_HIP(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
+    FSI_HIP(hipEventRecord(stage_ev, s));
+    stage_pending = true;
+    wing_nt = nt;
+    wing_nv = nv;
+    bx0 = i0[0];
+    by0 = i0[1];
+    bz0 = i0[2];
+    bnx = cnt[0];
+    bny = cnt[1];
+    bnz = cnt[2];
+    bcells = cells;
+    return FSI_OK;
+  }
+
+  fsi_status get_mask(double* chi_h, double* us_h) override {
+    memset(chi_h, 0, sizeof(double) * npts);
+    memset(us_h, 0, sizeof(double) * 3 * npts);
+    if (wing_nt == 0 || bcells == 0) return FSI_OK;
+    FSI_TRY(run_mask());
+    std::vector<T> c(bcells), u(3 * bcells);
+    FSI_HIP(hipMemcpyAsync(c.data(), chi, sizeof(T) * bcells, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipMemcpyAsync(u.data(), us, sizeof(T) * 3 * bcells, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < bnz; ++k)
+      for (int j = 0; j < bny; ++j)
+        for (int i = 0; i < bnx; ++i) {
+          const long long cell = ((long long)k * bny + j) * bnx + i;
+          const long long g = ((long long)(k + bz0) * ny + (j + by0)) * nx + (i + bx0);
+          chi_h[g] = (double)c[cell];
+          for (int q = 0; q < 3; ++q) us_h[q * npts + g] = (double)u[q * bcells + cell];
+        }
+    return FSI_OK;
+  }
+
+  // -- one step ------------------------------------------------------------------
+  fsi_status step(bool adaptive, double dt, double cfl, double c_eta, double dt_max) override {
+    if (adaptive) {
+      if (!(cfl > 0) || !(c_eta > 0) || !(dt_max > 0) || !std::isfinite(cfl) || !std::isfinite(dt_max)) {
+        err = "adaptive step needs cfl > 0, c_eta > 0, dt_max > 0";
+        return FSI_EINVAL;
+      }
+      if (c_eta > 1.0) {
+        err = "c_eta > 1 makes the explicit penalization unstable";
+        return FSI_ESTABILITY;
+      }
+    } else {
+      if (!(dt > 0) || !std::isfinite(dt)) {
+        err = "dt must be positive and finite";
+        return FSI_EINVAL;
+      }
+      if (wing_nt > 0 && dt / d.eta > 1.0) {
+        err = "dt * max(chi) / eta > 1: explicit penalization unstable";
+        return FSI_ESTABILITY;
+      }
+    }
+    const int cur = (int)(nstep & 1);
+    hipEvent_t* ev = timing ? next_events() : nullptr;
+    if (ev) FSI_HIP(hipEventRecord(ev[0], s));
+    if (wing_nt > 0 && bcells > 0) FSI_TRY(run_mask());
+    if (ev) FSI_HIP(hipEventRecord(ev[1], s));
+    // P1: z inverse of u and of omega = i k x u
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      a.in = uh;
+      a.in_fs = clen;
+      a.out = A;
+      a.out_fs = Alen;
+      FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[2], s));
+    // P2: y inverse of the six fields
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      a.in = A;
+      a.in_fs = Alen;
+      a.in_bs = C1;
+      a.out = B;
+      a.out_fs = Blen;
+      a.out_bs = (long long)ny * kx1;
+      a.nf = 6;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[3], s));
+    // P3: x C2R, nonlinear + penalization term, diagnostics, x R2C
+    {
+      XArgs<T> a = x_base();
+      a.spec = B;
+      a.sfs = Blen;
+      a.partials = partials;
+      if (wing_nt > 0 && bcells > 0) {
+        a.chi = chi;
+        a.us = us;
+        a.bx0 = bx0;
+        a.by0 = by0;
+        a.bz0 = bz0;
+        a.bnx = bnx;
+        a.bny = bny;
+        a.bnz = bnz;
+        a.bcells = bcells;
+      }
+      a.inv_eta = (T)(1.0 / d.eta);
+      FSI_HIP(launch_xfused<T>(a, npart, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[4], s));
+    // diagnostics and dt_n
+    {
+      FinalArgs f;
+      f.partials = partials;
+      f.np = npart;
+      f.sc = sc;
+      f.cur = cur;
+      f.adaptive = adaptive ? 1 : 0;
+      f.dt_fixed = dt;
+      f.cfl_dx = adaptive ? cfl * dx_min : 0.0;
+      f.cap = adaptive ? std::min(c_eta * d.eta, dt_max) : 0.0;
+      f.dV = dV;
+      f.inv_eta = 1.0 / d.eta;
+      FSI_HIP(launch_finalize(f, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[5], s));
+    // P4: y forward of G, truncated to the y band
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      a.in = B;
+      a.in_fs = Blen;
+      a.in_bs = (long long)ny * kx1;
+      a.out = A;
+      a.out_fs = Alen;
+      a.out_bs = C1;
+      a.nf = 3;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[6], s));
+    // P5: z forward, dealias, Leray projection, integrating-factor AB2
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      a.in = A;
+      a.in_fs = Alen;
+      a.uh = uh;
+      a.nh = nh;
+      a.cfs = clen;
+      a.sc = sc;
+      a.cur = cur;
+      a.first = have_prev ? 0 : 1;
+      a.nu = (T)d.nu;
+      a.scale = (T)(1.0 / (double)npts);
+      FSI_HIP(launch_col<T>(COL_FWD_UPDATE, a, 1, s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[7], s));
+    FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    ++nstep;
+    have_prev = true;
+    return FSI_OK;
+  }
+
+  fsi_status step_info(double F[3], double* dt, double* E, double* umax, double* t, long long* ns) override {
+    FSI_HIP(hipStreamSynchronize(s));
+    if (F) {
+      F[0] = sc_host->info[0];
+      F[1] = sc_host->info[1];
+      F[2] = sc_host->info[2];
+    }
+    if (E) *E = sc_host->info[3];
+    if (umax) *umax = sc_host->info[4];
+    if (dt) *dt = sc_host->info[5];
+    if (t) *t = sc_host->t;
+    if (ns) *ns = nstep;
+    if (sc_host->info[6] != 0.0) {
+      err = "non-finite value met during a step";
+      return FSI_ENAN;
+    }
+    return FSI_OK;
+  }
+
+  // -- stand-alone transforms ---------------------------------------------------
+  fsi_status fft_r2c(const double* f, double* fh) override {
+    FSI_TRY(ensure_phys());
+    FSI_TRY(ensure_cwork());
+    FSI_TRY(upload_real(f, phys, npts));
+    FSI_TRY(run_forward(phys, 1, cwork, COL_FWD_PLAIN));
+    std::vector<cpx<T>> h(clen);
+    FSI_HIP(hipMemcpyAsync(h.data(), cwork, sizeof(cpx<T>) * clen, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    for (long long i = 0; i < clen; ++i) {
+      fh[2 * i] = (double)h[i].re;
+      fh[2 * i + 1] = (double)h[i].im;
+    }
+    return FSI_OK;
+  }
+
+  fsi_status fft_c2r(const double* fh, double* f) override {
+    FSI_TRY(ensure_phys());
+    FSI_TRY(ensure_cwork());
+    std::vector<cpx<T>> h(clen);
+    for (long long i = 0; i < clen; ++i) {
+      h[i].re = (T)fh[2 * i];
+      h[i].im = (T)fh[2 * i + 1];
+    }
+    FSI_HIP(hipMemcpyAsync(cwork, h.data(), sizeof(cpx<T>) * clen, hipMemcpyHostToDevice, s));
+    FSI_TRY(run_inverse(cwork, clen, 1, phys));
+    return download_real(phys, f, npts);
+  }
+
+  // -- state slots ---------------------------------------------------------------
+  fsi_status save_state(int slot) override {
+    if (slot < 0 || slot >= (int)slots.size()) {
+      err = "slot out of range";
+      return FSI_EINVAL;
+    }
+    Slot& sl = slots[slot];
+    if (!sl.uh) {
+      FSI_TRY(alloc(&sl.uh, 3 * clen));
+      FSI_TRY(alloc(&sl.nh, 3 * clen));
+      FSI_TRY(alloc(&sl.sc, 1));
+    }
+    FSI_HIP(hipMemcpyAsync(sl.uh, uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    FSI_HIP(hipMemcpyAsync(sl.nh, nh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    FSI_HIP(hipMemcpyAsync(sl.sc, sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
+    sl.nstep = nstep;
+    sl.have_prev = have_prev;
+    sl.used = true;
+    return FSI_OK;
+  }
+
+  fsi_status load_state(int slot) override {
+    if (slot < 0 || slot >= (int)slots.size()) {
+      err = "slot out of range";
+      return FSI_EINVAL;
+    }
+    Slot& sl = slots[slot];
+    if (!sl.used) {
+      err = "slot is empty";
+      return FSI_ESTATE;
+    }
+    FSI_HIP(hipMemcpyAsync(uh, sl.uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    FSI_HIP(hipMemcpyAsync(nh, sl.nh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    FSI_HIP(hipMemcpyAsync(sc, sl.sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
+    FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    nstep = sl.nstep;
+    have_prev = sl.have_prev;
+    return FSI_OK;
+  }
+
+  fsi_status synchronize() override {
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
+  fsi_status set_timing(bool on) override {
+    FSI_HIP(hipStreamSynchronize(s));
+    timing = on;
+    ev_used = 0;
+    return FSI_OK;
+  }
+
+  fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) override {
+    FSI_HIP(hipStreamSynchronize(s));
+    for (int p = 0; p < FSI_NPASS; ++p) ms[p] = 0.0;
+    for (int k = 0; k < ev_used; ++k) {
+      for (int p = 0; p < FSI_NPASS; ++p) {
+        float e = 0.f;
+        FSI_HIP(hipEventElapsedTime(&e, events[k][p], events[k][p + 1]));
+        ms[p] += e;
+      }
+    }
+    if (nsteps) *nsteps = ev_used;
+    ev_used = 0;
+    return FSI_OK;
+  }
+
+ private:
+  struct Slot {
+    cpx<T>* uh = nullptr;
+    cpx<T>* nh = nullptr;
+    DevScalars* sc = nullptr;
+    long long nstep = 0;
+    bool have_prev = false;
+    bool used = false;
+  };
+
+  template <typename P>
+  fsi_status alloc(P** p, long long count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(P) * (size_t)std::max(count, 1LL));
+    if (e != hipSuccess) {
+      err = std::string("device allocation failed: ") + hipGetErrorString(e);
+      return FSI_ENOMEM;
+    }
+    *p = (P*)q;
+    return FSI_OK;
+  }
+
+  template <typename P>
+  void free_dev(P*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+
+  void release() {
+    if (s || uh) (void)hipStreamSynchronize(s);
+    free_dev(uh);
+    free_dev(nh);
+    free_dev(A);
+    free_dev(B);
+    free_dev(partials);
+    free_dev(sc);
+    free_dev(twx);
+    free_dev(twy);
+    free_dev(twz);
+    free_dev(phys);
+    free_dev(cwork);
+    free_dev(dx_);
+    free_dev(dv_);
+    free_dev(dtri_);
+    free_dev(key1);
+    free_dev(key2);
+    free_dev(chi);
+    free_dev(us);
+    for (Slot& sl : slots) {
+      free_dev(sl.uh);
+      free_dev(sl.nh);
+      free_dev(sl.sc);
+    }
+    if (sc_host) (void)hipHostFree(sc_host);
+    sc_host = nullptr;
+    if (stage) (void)hipHostFree(stage);
+    stage = nullptr;
+    if (stage_ev) (void)hipEventDestroy(stage_ev);
+    stage_ev = nullptr;
+    for (auto& e : events)
+      for (hipEvent_t h : e) (void)hipEventDestroy(h);
+    events.clear();
+  }
+
+  fsi_status make_twiddles(int n, cpx<T>** out) {
+    std::vector<cpx<T>> h(n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < n; ++k) {
+      const long double ang = -2.0L * pi * (long double)k / (long double)n;
+      h[k].re = (T)cosl(ang);
+      h[k].im = (T)sinl(ang);
+    }
+    FSI_TRY(alloc(out, n));
+    FSI_HIP(hipMemcpy(*out, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice));
+    return FSI_OK;
+  }
+
+  fsi_status reset_scalars() {
+    DevScalars z;
+    memset(&z, 0, sizeof(z));
+    *sc_host = z;
+    FSI_HIP(hipMemcpyAsync(sc, sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
+  fsi_status ensure_phys() {
+    if (!phys) FSI_TRY(alloc(&phys, 3 * npts));
+    return FSI_OK;
+  }
+  fsi_status ensure_cwork() {
+    if (!cwork) FSI_TRY(alloc(&cwork, clen));
+    return FSI_OK;
+  }
+
+  fsi_status upload_real(const double* h, T* dptr, long long count) {
+    if (sizeof(T) == sizeof(double)) {
+      FSI_HIP(hipMemcpyAsync(dptr, h, sizeof(double) * count, hipMemcpyHostToDevice, s));
+      FSI_HIP(hipStreamSynchronize(s));
+      return FSI_OK;
+    }
+    std::vector<T> tmp(count);
+    for (long long i = 0; i < count; ++i) tmp[i] = (T)h[i];
+    FSI_HIP(hipMemcpyAsync(dptr, tmp.data(), sizeof(T) * count, hipMemcpyHostToDevice, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
+  fsi_status download_real(const T* dptr, double* h, long long count) {
+    if (sizeof(T) == sizeof(double)) {
+      FSI_HIP(hipMemcpyAsync(h, dptr, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+      FSI_HIP(hipStreamSynchronize(s));
+      return FSI_OK;
+    }
+    std::vector<T> tmp(count);
+    FSI_HIP(hipMemcpyAsync(tmp.data(), dptr, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    for (long long i = 0; i < count; ++i) h[i] = (double)tmp[i];
+    return FSI_OK;
+  }
+
+  ColArgs<T> col_base(const FftPlan& p, const cpx<T>* tw, int n, int K, long long C) {
+    ColArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.C = (int)C;
+    a.n = n;
+    a.K = K;
+    a.nf = 1;
+    a.plan = p;
+    a.tw = tw;
+    a.kx1 = kx1;
+    a.Ky = Ky;
+    a.kfx = (T)(2.0 * M_PI / d.lx);
+    a.kfy = (T)(2.0 * M_PI / d.ly);
+    a.kfz = (T)(2.0 * M_PI / d.lz);
+    a.scale = (T)1;
+    return a;
+  }
+
+  XArgs<T> x_base() {
+    XArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.nlines = ny * nz;
+    a.ny = ny;
+    a.n = nx;
+    a.kx1 = kx1;
+    a.plan = px;
+    a.tw = twx;
+    return a;
+  }
+
+  // compact (nf fields, stride cstride) -> physical (nf fields)
+  fsi_status run_inverse(const cpx<T>* comp, long long cstride, int nf, T* out) {
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      a.in = comp;
+      a.in_fs = cstride;
+      a.out = A;
+      a.out_fs = Alen;
+      a.nf = nf;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      a.in = A;
+      a.in_fs = Alen;
+      a.in_bs = C1;
+      a.out = B;
+      a.out_fs = Blen;
+      a.out_bs = (long long)ny * kx1;
+      a.nf = nf;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
+    }
+    {
+      XArgs<T> a = x_base();
+      a.spec = B;
+      a.sfs = Blen;
+      a.phys = out;
+      a.pfs = npts;
+      FSI_HIP(launch_xplain<T>(X_C2R, nf, a, npart, s));
+    }
+    return FSI_OK;
+  }
+
+  // physical (nf fields) -> compact; mode COL_FWD_PLAIN (nf = 1, into cout) or
+  // COL_FWD_PROJECT (nf = 3, into cout = uh)
+  fsi_status run_forward(T* in, int nf, cpx<T>* cout, int zmode) {
+    {
+      XArgs<T> a = x_base();
+      a.spec = B;
+      a.sfs = Blen;
+      a.phys = in;
+      a.pfs = npts;
+      FSI_HIP(launch_xplain<T>(X_R2C, nf, a, npart, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      a.in = B;
+      a.in_fs = Blen;
+      a.in_bs = (long long)ny * kx1;
+      a.out = A;
+      a.out_fs = Alen;
+      a.out_bs = C1;
+      a.nf = nf;
+      FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      a.in = A;
+      a.in_fs = Alen;
+      a.out = cout;
+      a.out_fs = clen;
+      a.cfs = clen;
+      a.nf = nf;
+      a.scale = (T)(1.0 / (double)npts);
+      FSI_HIP(launch_col<T>(zmode, a, 1, s));
+    }
+    return FSI_OK;
+  }
+
+  fsi_status finish_set_velocity() {
+    FSI_TRY(run_forward(phys, 3, uh, COL_FWD_PROJECT));
+    FSI_HIP(hipMemsetAsync(nh, 0, sizeof(cpx<T>) * 3 * clen, s));
+    nstep = 0;
+    have_prev = false;
+    FSI_TRY(reset_scalars());
+    return FSI_OK;
+  }
+
+  fsi_status run_mask() {
+    MaskArgs<T> m;
+    memset(&m, 0, sizeof(m));
+    m.x = dx_;
+    m.v = dv_;
+    m.tri = dtri_;
+    m.nt = wing_nt;
+    m.key1 = key1;
+    m.key2 = key2;
+    m.chi = chi;
+    m.us = us;
+    m.bx0 = bx0;
+    m.by0 = by0;
+    m.bz0 = bz0;
+    m.bnx = bnx;
+    m.bny = bny;
+    m.bnz = bnz;
+    m.bcells = bcells;
+    m.dx = dxs[0];
+    m.dy = dxs[1];
+    m.dz = dxs[2];
+    m.rsup = rsup;
+    m.tw = d.tw;
+    m.h = d.h;
+    m.profile = d.mask_profile;
+    FSI_HIP(launch_mask<T>(m, s));
+    return FSI_OK;
+  }
+
+  fsi_status nan_status() {
+    if (sc_host && sc_host->info[6] != 0.0) {
+      err = "non-finite value met during a step";
+      return FSI_ENAN;
+    }
+    return FSI_OK;
+  }
+
+  hipEvent_t* next_events() {
+    if (ev_used >= 4096) return nullptr;
+    if (ev_used == (int)events.size()) {
+      std::array<hipEvent_t, FSI_NPASS + 1> e;
+      for (auto& h : e)
+        if (hipEventCreate(&h) != hipSuccess) return nullptr;
+      events.push_back(e);
+    }
+    return events[ev_used++].data();
+  }
+
+  fsi_desc d;
+  hipStream_t s = nullptr;
+  int nx = 0, ny = 0, nz = 0, Kx = 0, Ky = 0, Kz = 0, kx1 = 0, nby = 0, nbz = 0;
+  long long C1 = 0, clen = 0, Alen = 0, Blen = 0, npts = 0;
+  double dxs[3] = {0, 0, 0}, dV = 0, dx_min = 0, rsup = 0;
+  FftPlan px, py, pz;
+  int ngroups = 0, npart = 0;
+  cpx<T>*twx = nullptr, *twy = nullptr, *twz = nullptr;
+  cpx<T>*uh = nullptr, *nh = nullptr, *A = nullptr, *B = nullptr, *cwork = nullptr;
+  T* phys = nullptr;
+  double* partials = nullptr;
+  DevScalars* sc = nullptr;
+  DevScalars* sc_host = nullptr;
+  // wing and mask sub-box
+  int wing_nt = 0, wing_nv = 0, mesh_vcap = 0, mesh_tcap = 0;
+  double *dx_ = nullptr, *dv_ = nullptr;
+  int* dtri_ = nullptr;
+  void* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
+  int bx0 = 0, by0 = 0, bz0 = 0, bnx = 0, bny = 0, bnz = 0;
+  long long bcells = 0, box_cap = 0;
+  unsigned long long *key1 = nullptr, *key2 = nullptr;
+  T *chi = nullptr, *us = nullptr;
+  // stepping
+  long long nstep = 0;
+  bool have_prev = false;
+  std::vector<Slot> slots;
+  // timing
+  bool timing = false;
+  int ev_used = 0;
+  std::vector<std::array<hipEvent_t, FSI_NPASS + 1>> events;
+};
+
+EngineBase* make_engine_f32() { return new Engine<float>(); }
+EngineBase* make_engine_f64() { return new Engine<double>(); }
+
+}  // namespace fsi

@@ -1,0 +1,207 @@
+// fft_lds.h - batched mixed-radix complex FFT held in LDS, for gfx950.
+//
+// A workgroup transforms W interleaved signals of length n stored in LDS as
+// buf[row * W + col] (row = sample index, col = signal).  The transform is a
+// self-sorting (Stockham) decomposition n = R_0 R_1 ... R_{s-1} with radices
+// 2, 3, 4, 5 and 8: stage s (span Ns = R_0 ... R_{s-1}) reads R samples spaced
+// n/R apart, multiplies sample r by w^(r (j mod Ns) n/(Ns R)) with
+// w = exp(-2 pi i / n), applies a radix-R DFT and writes the outputs spaced Ns
+// apart from (j div Ns) Ns R + (j mod Ns).  Every stage first loads all its
+// butterflies into registers, then (after a barrier) writes back, so one LDS
+// buffer suffices.  Consecutive threads handle consecutive signals, so LDS
+// rows are touched in contiguous runs of W complex values.
+//
+// Twiddles come from a table tw[k] = exp(-2 pi i k / n) computed on the host in
+// extended precision; the inverse transform conjugates them (unnormalized).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsi {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.re = a;
+  r.im = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scl(cpx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.re, -a.im); }
+// multiply by +i (sgn = +1) or -i (sgn = -1)
+template <typename T, int SGN>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+  return SGN > 0 ? mk(-a.im, a.re) : mk(a.im, -a.re);
+}
+
+constexpr int kMaxStages = 16;
+
+// Factorization of one transform length (host fills it; passed by value).
+struct FftPlan {
+  int n;
+  int nst;
+  int radix[kMaxStages];
+};
+
+// Radix-R DFT in place on v[0..R-1]: out_k = sum_r v_r exp(SGN 2 pi i r k / R).
+template <typename T, int R, int SGN>
+struct Bfly;
+
+template <typename T, int SGN>
+struct Bfly<T, 2, SGN> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T, int SGN>
+struct Bfly<T, 4, SGN> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+    cpx<T> t2 = v[1] + v[3], t3 = mul_i<T, SGN>(v[1] - v[3]);
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + t3;
+    v[3] = t1 - t3;
+  }
+};
+
+template <typename T, int SGN>
+struct Bfly<T, 8, SGN> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<T, 4, SGN>::run(e);
+    Bfly<T, 4, SGN>::run(o);
+    const T h = (T)0.70710678118654752440084436210484903928;
+    // o[k] *= exp(SGN i pi k / 4)
+    cpx<T> o1 = mk(h * (o[1].re - SGN * o[1].im), h * (o[1].im + SGN * o[1].re));
+    cpx<T> o2 = mul_i<T, SGN>(o[2]);
+    cpx<T> o3 = mk(h * (-o[3].re - SGN * o[3].im), h * (-o[3].im + SGN * o[3].re));
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
+  }
+};
+
+template <typename T, int SGN>
+struct Bfly<T, 3, SGN> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c = (T)-0.5;
+    const T s = (T)(SGN * 0.86602540378443864676372317075293618347);
+    cpx<T> a = v[1] + v[2];
+    cpx<T> b = v[1] - v[2];
+    cpx<T> m = mk(v[0].re + c * a.re, v[0].im + c * a.im);
+    cpx<T> ib = mk(-s * b.im, s * b.re);  // i s b
+    v[0] = v[0] + a;
+    v[1] = m + ib;
+    v[2] = m - ib;
+  }
+};
+
+template <typename T, int SGN>
+struct Bfly<T, 5, SGN> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c1 = (T)0.30901699437494742410229341718281905886;   // cos(2 pi/5)
+    const T c2 = (T)-0.80901699437494742410229341718281905886;  // cos(4 pi/5)
+    const T s1 = (T)(SGN * 0.95105651629515357211643933337938214340);  // sin(2 pi/5)
+    const T s2 = (T)(SGN * 0.58778525229247312916870595463907276860);  // sin(4 pi/5)
+    cpx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
+    cpx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
+    cpx<T> m1 = mk(v[0].re + c1 * a1.re + c2 * a2.re, v[0].im + c1 * a1.im + c2 * a2.im);
+    cpx<T> m2 = mk(v[0].re + c2 * a1.re + c1 * a2.re, v[0].im + c2 * a1.im + c1 * a2.im);
+    // i (s1 b1 + s2 b2) and i (s2 b1 - s1 b2)
+    cpx<T> n1 = mk(-(s1 * b1.im + s2 * b2.im), s1 * b1.re + s2 * b2.re);
+    cpx<T> n2 = mk(-(s2 * b1.im - s1 * b2.im), s2 * b1.re - s1 * b2.re);
+    v[0] = v[0] + a1 + a2;
+    v[1] = m1 + n1;
+    v[4] = m1 - n1;
+    v[2] = m2 + n2;
+    v[3] = m2 - n2;
+  }
+};
+
+// One Stockham stage over W interleaved signals.  MAXE bounds n*W/NT.
+template <typename T, int R, int W, int NT, int MAXE, bool INV>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<T>* __restrict__ tw) {
+  constexpr int KB = (MAXE + R - 1) / R;
+  constexpr int SGN = INV ? 1 : -1;
+  const int nR = n / R;
+  const int nb = nR * W;
+  const int tstride = n / (Ns * R);
+  cpx<T> v[KB][R];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int q = (int)threadIdx.x + k * NT;
+    if (q < nb) {
+      const int col = q % W, j = q / W;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = buf[(j + r * nR) * W + col];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int q = (int)threadIdx.x + k * NT;
+    if (q < nb) {
+      const int col = q % W, j = q / W;
+      const int jm = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[jm * r * tstride];
+          if (INV) w.im = -w.im;
+          v[k][r] = cmul(v[k][r], w);
+        }
+      }
+      Bfly<T, R, SGN>::run(v[k]);
+      const int d0 = (j - jm) * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(d0 + r * Ns) * W + col] = v[k][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of the W signals in buf (caller has synchronized after filling it;
+// on return the result is in buf and all threads are synchronized).
+template <typename T, int W, int NT, int MAXE, bool INV>
+__device__ void fft_lds(cpx<T>* buf, const FftPlan& p, const cpx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int R = p.radix[s];
+    switch (R) {
+      case 8: fft_stage<T, 8, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 4: fft_stage<T, 4, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 2: fft_stage<T, 2, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 5: fft_stage<T, 5, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      default: fft_stage<T, 3, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace fsi

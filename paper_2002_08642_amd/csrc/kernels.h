@@ -1,0 +1,110 @@
+// kernels.h - device kernels of the penalized pseudo-spectral step (gfx950).
+//
+// Data layout in HBM (C order, x fastest):
+//   compact spectrum  [iz][iy][ix]        ix in [0, Kx], iy, iz in the 2/3 band
+//   z-pass output     [z][iy][ix]         (band in y and x, all z)
+//   y-pass output     [z][y][ix]          (band in x, all y and z)
+//   physical          [z][y][x]
+// The step is five passes over these layouts (z-inverse + curl, y-inverse,
+// fused x pass, y-forward, z-forward + projection + update) plus the mask
+// kernels and the reduction that also produces the adaptive dt.
+#pragma once
+
+#include "fft_lds.h"
+
+namespace fsi {
+
+constexpr int kNT = 256;  // threads per workgroup for every pass
+
+enum ColMode { COL_INV_PLAIN = 0, COL_INV_CURL = 1, COL_FWD_PLAIN = 2, COL_FWD_PROJECT = 3, COL_FWD_UPDATE = 4 };
+enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
+
+// Device scalars shared by the passes of one step.
+struct DevScalars {
+  double dt[2];     // dt_n and dt_{n-1}, indexed by step parity
+  double t;         // time after the last completed step
+  double info[8];   // F[3], E, umax, dt, nonfinite flag, spare
+};
+
+template <typename T>
+struct ColArgs {
+  const cpx<T>* in;
+  cpx<T>* out;
+  long long in_fs, out_fs;  // field strides (complex elements)
+  long long in_bs, out_bs;  // slice strides (blockIdx.y)
+  int C;                    // columns per slice
+  int n;                    // transform length
+  int K;                    // band half width along the transform axis
+  int nf;                   // fields (plain modes)
+  FftPlan plan;
+  const cpx<T>* tw;
+  // spectral bookkeeping for the z passes: column c = iy * kx1 + ix
+  int kx1;
+  int Ky;
+  T kfx, kfy, kfz;  // 2 pi / L per axis
+  T scale;          // factor applied to forward outputs
+  // projection / update (z-forward pass)
+  cpx<T>* uh;
+  cpx<T>* nh;
+  long long cfs;  // compact field stride
+  const DevScalars* sc;
+  int cur;    // parity index of dt_n
+  int first;  // 1: integrating-factor Euler step
+  T nu;
+};
+
+template <typename T>
+struct XArgs {
+  cpx<T>* spec;       // [f][line][kx1]
+  long long sfs;      // field stride of spec
+  T* phys;            // [f][line][n] (plain modes)
+  long long pfs;
+  int nlines;         // ny * nz
+  int ny;
+  int n;              // nx
+  int kx1;            // Kx + 1
+  FftPlan plan;
+  const cpx<T>* tw;
+  // mask sub-box (fused mode); bnx == 0 means no wing
+  const T* chi;
+  const T* us;        // [3][cell]
+  int bx0, by0, bz0, bnx, bny, bnz;
+  long long bcells;
+  T inv_eta;
+  double* partials;   // [gridDim.x][8]
+};
+
+// The mask geometry is evaluated in FP64 in both precisions (it is a small
+// part of the step); chi and u_s are stored in the bulk precision.
+template <typename T>
+struct MaskArgs {
+  const double* x;     // [nv][3]
+  const double* v;     // [nv][3]
+  const int* tri;      // [nt][3]
+  int nt;
+  unsigned long long* key1;  // [cell] (truncated FP32 distance bits << 32) | triangle
+  unsigned long long* key2;  // [cell] (low FP64 mantissa bits << 32) | triangle
+  T* chi;
+  T* us;               // [3][cell]
+  int bx0, by0, bz0, bnx, bny, bnz;
+  long long bcells;
+  double dx, dy, dz;
+  double rsup;         // support radius
+  double tw, h;
+  int profile;
+};
+
+struct FinalArgs {
+  const double* partials;
+  int np;
+  DevScalars* sc;
+  int cur;        // parity index where dt_n is written
+  int adaptive;   // 0: dt_n = dt_fixed
+  double dt_fixed;
+  double cfl_dx;  // cfl * dx_min
+  double cap;     // min(c_eta * eta, dt_max)
+  double dV;
+  double inv_eta;
+};
+
+}  // namespace fsi

@@ -1,0 +1,798 @@
+// kernels.hip - the passes of the penalized pseudo-spectral step for gfx950.
+//
+// Sec. 4.1 (penalized Navier-Stokes in rotational form, Fourier pseudo-spectral
+// discretization): every step evaluates u x omega - (chi/eta)(u - u_s) on the
+// grid, transforms it back, projects it onto divergence-free fields and
+// advances the velocity.  The passes below each make one round trip through
+// HBM and keep the intermediate transforms in LDS.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kernels.h"
+#include "launch.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int band_to_row(int i, int K, int n) { return i <= K ? i : i + n - 2 * K - 1; }
+__device__ __forceinline__ int band_mode(int i, int K) { return i <= K ? i : i - 2 * K - 1; }
+
+template <typename T>
+__device__ __forceinline__ T dev_exp(T a);
+template <>
+__device__ __forceinline__ float dev_exp<float>(float a) { return expf(a); }
+template <>
+__device__ __forceinline__ double dev_exp<double>(double a) { return exp(a); }
+
+template <typename T>
+__device__ __forceinline__ T dev_sqrt(T a);
+template <>
+__device__ __forceinline__ float dev_sqrt<float>(float a) { return sqrtf(a); }
+template <>
+__device__ __forceinline__ double dev_sqrt<double>(double a) { return sqrt(a); }
+
+// Fixed-order workgroup sum of NV doubles; result valid in thread 0.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* red /* [NV][kNT/64] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * (kNT / 64) + wave] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kNT / 64; ++w) s += red[i * (kNT / 64) + w];
+      v[i] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kNT / 64; ++w) v = fmax(v, red[w]);
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// column passes: FFT along the slow axis of a [rows][C] slice, W columns per WG
+// ---------------------------------------------------------------------------
+
+template <typename T, int W, int MAXE, int MODE>
+__global__ __launch_bounds__(kNT) void col_pass(ColArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int RSTEP = kNT / W;
+  constexpr int MAXO = (2 * MAXE) / 3 + 2;  // band rows per thread (2K+1 <= 2n/3 + 1/3)
+  const int tid = threadIdx.x;
+  const int col = tid % W;
+  const int r0 = tid / W;
+  const int c = blockIdx.x * W + col;
+  const bool cok = c < a.C;
+  const int n = a.n, K = a.K, nb = 2 * K + 1;
+  const long long ib = (long long)blockIdx.y * a.in_bs;
+  const long long ob = (long long)blockIdx.y * a.out_bs;
+
+  if constexpr (MODE == COL_INV_PLAIN) {
+    for (int f = 0; f < a.nf; ++f) {
+      const cpx<T>* in = a.in + f * a.in_fs + ib;
+      for (int r = r0; r < n; r += RSTEP) {
+        cpx<T> val = mk<T>(0, 0);
+        if (cok) {
+          if (r <= K) val = in[(long long)r * a.C + c];
+          else if (r >= n - K) val = in[(long long)(r - n + nb) * a.C + c];
+        }
+        buf[r * W + col] = val;
+      }
+      __syncthreads();
+      fft_lds<T, W, kNT, MAXE, true>(buf, a.plan, a.tw);
+      cpx<T>* out = a.out + f * a.out_fs + ob;
+      if (cok)
+        for (int r = r0; r < n; r += RSTEP) out[(long long)r * a.C + c] = buf[r * W + col];
+      __syncthreads();
+    }
+  } else if constexpr (MODE == COL_INV_CURL) {
+    // inputs: the three compact velocity components; outputs u (3) and omega = i k x u (3)
+    cpx<T> ur[3][MAXO];
+    const int ix = c % a.kx1, iy = c / a.kx1;
+    const T kx = a.kfx * (T)ix;
+    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+#pragma unroll
+    for (int k = 0; k < MAXO; ++k) {
+      const int i = r0 + k * RSTEP;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) ur[q][k] = (cok && i < nb) ? a.in[q * a.in_fs + (long long)i * a.C + c] : mk<T>(0, 0);
+    }
+    for (int o = 0; o < 6; ++o) {
+      // zero the gap rows
+      for (int r = r0; r < n; r += RSTEP)
+        if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (i < nb) {
+          const T kz = a.kfz * (T)band_mode(i, K);
+          cpx<T> val;
+          if (o < 3) {
+            val = ur[o][k];
+          } else {
+            cpx<T> t;
+            if (o == 3) t = scl(ur[2][k], ky) - scl(ur[1][k], kz);       // ky uz - kz uy
+            else if (o == 4) t = scl(ur[0][k], kz) - scl(ur[2][k], kx);  // kz ux - kx uz
+            else t = scl(ur[1][k], kx) - scl(ur[0][k], ky);              // kx uy - ky ux
+            val = mk<T>(-t.im, t.re);                                    // i t
+          }
+          buf[band_to_row(i, K, n) * W + col] = val;
+        }
+      }
+      __syncthreads();
+      fft_lds<T, W, kNT, MAXE, true>(buf, a.plan, a.tw);
+      cpx<T>* out = a.out + o * a.out_fs + ob;
+      if (cok)
+        for (int r = r0; r < n; r += RSTEP) out[(long long)r * a.C + c] = buf[r * W + col];
+      __syncthreads();
+    }
+  } else if constexpr (MODE == COL_FWD_PLAIN) {
+    for (int f = 0; f < a.nf; ++f) {
+      const cpx<T>* in = a.in + f * a.in_fs + ib;
+      for (int r = r0; r < n; r += RSTEP) buf[r * W + col] = cok ? in[(long long)r * a.C + c] : mk<T>(0, 0);
+      __syncthreads();
+      fft_lds<T, W, kNT, MAXE, false>(buf, a.plan, a.tw);
+      cpx<T>* out = a.out + f * a.out_fs + ob;
+      if (cok)
+        for (int i = r0; i < nb; i += RSTEP) out[(long long)i * a.C + c] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+      __syncthreads();
+    }
+  } else {
+    // COL_FWD_PROJECT / COL_FWD_UPDATE: three components, then projection (+ update)
+    cpx<T> st[2][MAXO];
+    for (int f = 0; f < 3; ++f) {
+      const cpx<T>* in = a.in + f * a.in_fs + ib;
+      for (int r = r0; r < n; r += RSTEP) buf[r * W + col] = cok ? in[(long long)r * a.C + c] : mk<T>(0, 0);
+      __syncthreads();
+      fft_lds<T, W, kNT, MAXE, false>(buf, a.plan, a.tw);
+      if (f < 2) {
+#pragma unroll
+        for (int k = 0; k < MAXO; ++k) {
+          const int i = r0 + k * RSTEP;
+          if (i < nb) st[f][k] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+        }
+        __syncthreads();
+      }
+    }
+    const int ix = c % a.kx1, iy = c / a.kx1;
+    const T kx = a.kfx * (T)ix;
+    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+    T dtn = 0, dtp = 0, c1 = 0, c2 = 0;
+    if constexpr (MODE == COL_FWD_UPDATE) {
+      const double d_n = a.sc->dt[a.cur];
+      const double d_p = a.sc->dt[a.cur ^ 1];
+      dtn = (T)d_n;
+      dtp = (T)d_p;
+      if (a.first) {
+        c1 = dtn;
+        c2 = 0;
+      } else {
+        const double xi = d_n / d_p;
+        c1 = (T)(d_n * (1.0 + 0.5 * xi));
+        c2 = (T)(d_n * 0.5 * xi);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MAXO; ++k) {
+      const int i = r0 + k * RSTEP;
+      if (cok && i < nb) {
+        const T kz = a.kfz * (T)band_mode(i, K);
+        cpx<T> n0 = st[0][k], n1 = st[1][k];
+        cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+        const T k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > (T)0) {
+          const T ik2 = (T)1 / k2;
+          cpx<T> s = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
+          n0 = n0 - scl(s, kx);
+          n1 = n1 - scl(s, ky);
+          n2 = n2 - scl(s, kz);
+        }
+        const long long idx = (long long)i * a.C + c;
+        if constexpr (MODE == COL_FWD_PROJECT) {
+          a.out[idx] = n0;
+          a.out[a.cfs + idx] = n1;
+          a.out[2 * a.cfs + idx] = n2;
+        } else {
+          const T en = dev_exp<T>(-a.nu * k2 * dtn);
+          cpx<T> nn[3] = {n0, n1, n2};
+          if (a.first) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const cpx<T> u = a.uh[q * a.cfs + idx];
+              a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en);
+              a.nh[q * a.cfs + idx] = nn[q];
+            }
+          } else {
+            const T ee = en * dev_exp<T>(-a.nu * k2 * dtp);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const cpx<T> u = a.uh[q * a.cfs + idx];
+              const cpx<T> np = a.nh[q * a.cfs + idx];
+              a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee);
+              a.nh[q * a.cfs + idx] = nn[q];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x pass: real transforms along x, two real lines packed per complex signal
+// ---------------------------------------------------------------------------
+
+// Fused pass: C2R of (u, omega) for L lines, G = u x omega - (chi/eta)(u - u_s),
+// partial sums of the diagnostics, R2C of G truncated to the x band.
+template <typename T, int L, int MAXE>
+__global__ __launch_bounds__(kNT) void xpass_fused(XArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  __shared__ double red[5 * (kNT / 64)];
+  constexpr int WI = 3 * L;      // inverse: pairs (ux,uy) (uz,wx) (wy,wz) per line
+  constexpr int WF = 3 * L / 2;  // forward: (Gx,Gy) per line, (Gz,Gz') per line pair
+  constexpr int PMAX = (MAXE + 2) / 3;
+  static_assert(L % 2 == 0, "L must be even");
+  const int tid = threadIdx.x;
+  const int n = a.n, K = a.kx1 - 1;
+  const int ngroups = a.nlines / L;
+  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
+
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int line0 = g * L;
+    // 1) Hermitian-extended packed spectra
+    for (int it = tid; it < 3 * L * n; it += kNT) {
+      const int x = it % n, s = it / n;
+      const int l = s / 3, p = s % 3;
+      if (x <= K) {
+        const long long off = (long long)(line0 + l) * a.kx1 + x;
+        cpx<T> A = a.spec[(2 * p) * a.sfs + off];
+        cpx<T> B = a.spec[(2 * p + 1) * a.sfs + off];
+        if (x == 0) {
+          buf[s] = mk<T>(A.re, B.re);
+        } else {
+          buf[x * WI + s] = mk<T>(A.re - B.im, A.im + B.re);
+          buf[(n - x) * WI + s] = mk<T>(A.re + B.im, B.re - A.im);
+        }
+      } else if (x < n - K) {
+        buf[x * WI + s] = mk<T>(0, 0);
+      }
+    }
+    __syncthreads();
+    fft_lds<T, WI, kNT, MAXE, true>(buf, a.plan, a.tw);
+
+    // 2) pointwise nonlinear + penalization term and diagnostics
+    T g0[PMAX], g1[PMAX], g2[PMAX];
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int it = tid + k * kNT;
+      if (it < n * L) {
+        const int x = it % n, l = it / n;
+        const cpx<T> z1 = buf[x * WI + 3 * l], z2 = buf[x * WI + 3 * l + 1], z3 = buf[x * WI + 3 * l + 2];
+        const T ux = z1.re, uy = z1.im, uz = z2.re;
+        const T wx = z2.im, wy = z3.re, wz = z3.im;
+        T gx = uy * wz - uz * wy;
+        T gy = uz * wx - ux * wz;
+        T gz = ux * wy - uy * wx;
+        if (a.bnx > 0) {
+          const int line = line0 + l;
+          const int z = line / a.ny, y = line - z * a.ny;
+          const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
+          if (bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {
+            const long long cell = ((long long)bz * a.bny + by) * a.bnx + bx;
+            const T ch = a.chi[cell];
+            if (ch != (T)0) {
+              const T sx = ux - a.us[cell], sy = uy - a.us[a.bcells + cell], sz = uz - a.us[2 * a.bcells + cell];
+              const T ce = ch * a.inv_eta;
+              gx -= ce * sx;
+              gy -= ce * sy;
+              gz -= ce * sz;
+              aF0 += (double)(ch * sx);
+              aF1 += (double)(ch * sy);
+              aF2 += (double)(ch * sz);
+            }
+          }
+        }
+        const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        aE += u2;
+        aM = fmax(aM, u2);
+        g0[k] = gx;
+        g1[k] = gy;
+        g2[k] = gz;
+      }
+    }
+    __syncthreads();
+    T* bufr = reinterpret_cast<T*>(buf);
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int it = tid + k * kNT;
+      if (it < n * L) {
+        const int x = it % n, l = it / n;
+        buf[x * WF + l] = mk<T>(g0[k], g1[k]);
+        bufr[2 * (x * WF + L + (l >> 1)) + (l & 1)] = g2[k];
+      }
+    }
+    __syncthreads();
+    fft_lds<T, WF, kNT, MAXE, false>(buf, a.plan, a.tw);
+
+    // 3) unpack the two real transforms of each signal, keep kx <= K
+    for (int it = tid; it < 3 * L * a.kx1; it += kNT) {
+      const int k = it % a.kx1, s = it / a.kx1;
+      const int l = s / 3, f = s % 3;
+      const int sig = (f < 2) ? l : L + (l >> 1);
+      const bool second = (f == 1) || (f == 2 && (l & 1));
+      const cpx<T> z = buf[k * WF + sig];
+      const cpx<T> zc = conj(buf[((n - k) % n) * WF + sig]);
+      cpx<T> r;
+      if (!second) r = scl(z + zc, (T)0.5);
+      else {
+        const cpx<T> d = z - zc;
+        r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+      }
+      a.spec[f * a.sfs + (long long)(line0 + l) * a.kx1 + k] = r;
+    }
+    __syncthreads();
+  }
+
+  double v[4] = {aF0, aF1, aF2, aE};
+  block_sum<4>(v, red);
+  __syncthreads();
+  const double m = block_max(aM, red);
+  if (tid == 0) {
+    double* p = a.partials + (long long)blockIdx.x * 8;
+    p[0] = v[0];
+    p[1] = v[1];
+    p[2] = v[2];
+    p[3] = v[3];
+    p[4] = m;
+    p[5] = 0;
+    p[6] = 0;
+    p[7] = 0;
+  }
+}
+
+// Plain real transforms along x for NF fields of L lines: real signal r = l * NF + f,
+// complex signal j packs real signals 2j (real part) and 2j + 1 (imaginary part).
+template <typename T, int NF, int L, int MAXE, int MODE>
+__global__ __launch_bounds__(kNT) void xpass_plain(XArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int S = NF * L / 2;
+  static_assert((NF * L) % 2 == 0, "need an even number of real signals");
+  const int tid = threadIdx.x;
+  const int n = a.n, K = a.kx1 - 1;
+  const int ngroups = a.nlines / L;
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int line0 = g * L;
+    if constexpr (MODE == X_C2R) {
+      for (int it = tid; it < S * n; it += kNT) {
+        const int x = it % n, j = it / n;
+        const int ra = 2 * j, rb = 2 * j + 1;
+        if (x <= K) {
+          const cpx<T> A = a.spec[(ra % NF) * a.sfs + (long long)(line0 + ra / NF) * a.kx1 + x];
+          const cpx<T> B = a.spec[(rb % NF) * a.sfs + (long long)(line0 + rb / NF) * a.kx1 + x];
+          if (x == 0) buf[j] = mk<T>(A.re, B.re);
+          else {
+            buf[x * S + j] = mk<T>(A.re - B.im, A.im + B.re);
+            buf[(n - x) * S + j] = mk<T>(A.re + B.im, B.re - A.im);
+          }
+        } else if (x < n - K) {
+          buf[x * S + j] = mk<T>(0, 0);
+        }
+      }
+      __syncthreads();
+      fft_lds<T, S, kNT, MAXE, true>(buf, a.plan, a.tw);
+      for (int it = tid; it < 2 * S * n; it += kNT) {
+        const int x = it % n, r = it / n;
+        const cpx<T> z = buf[x * S + (r >> 1)];
+        a.phys[(r % NF) * a.pfs + (long long)(line0 + r / NF) * n + x] = (r & 1) ? z.im : z.re;
+      }
+      __syncthreads();
+    } else {
+      T* bufr = reinterpret_cast<T*>(buf);
+      for (int it = tid; it < 2 * S * n; it += kNT) {
+        const int x = it % n, r = it / n;
+        bufr[2 * (x * S + (r >> 1)) + (r & 1)] = a.phys[(r % NF) * a.pfs + (long long)(line0 + r / NF) * n + x];
+      }
+      __syncthreads();
+      fft_lds<T, S, kNT, MAXE, false>(buf, a.plan, a.tw);
+      for (int it = tid; it < 2 * S * a.kx1; it += kNT) {
+        const int k = it % a.kx1, r = it / a.kx1;
+        const cpx<T> z = buf[k * S + (r >> 1)];
+        const cpx<T> zc = conj(buf[((n - k) % n) * S + (r >> 1)]);
+        cpx<T> v;
+        if (!(r & 1)) v = scl(z + zc, (T)0.5);
+        else {
+          const cpx<T> d = z - zc;
+          v = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+        }
+        a.spec[(r % NF) * a.sfs + (long long)(line0 + r / NF) * a.kx1 + k] = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions and adaptive dt
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
+  __shared__ double red[5 * (kNT / 64)];
+  double v[4] = {0, 0, 0, 0};
+  double m = 0;
+  for (int p = threadIdx.x; p < a.np; p += kNT) {
+    const double* q = a.partials + (long long)p * 8;
+    v[0] += q[0];
+    v[1] += q[1];
+    v[2] += q[2];
+    v[3] += q[3];
+    m = fmax(m, q[4]);
+  }
+  block_sum<4>(v, red);
+  __syncthreads();
+  m = block_max(m, red);
+  if (threadIdx.x == 0) {
+    const double umax = sqrt(m);
+    double dt;
+    if (a.adaptive) {
+      dt = a.cap;
+      if (umax > 0.0) dt = fmin(dt, a.cfl_dx / umax);
+    } else {
+      dt = a.dt_fixed;
+    }
+    const double F0 = v[0] * a.dV * a.inv_eta, F1 = v[1] * a.dV * a.inv_eta, F2 = v[2] * a.dV * a.inv_eta;
+    const double E = 0.5 * a.dV * v[3];
+    const bool bad = !isfinite(E) || !isfinite(F0) || !isfinite(F1) || !isfinite(F2) || !isfinite(umax);
+    DevScalars* s = a.sc;
+    s->dt[a.cur] = dt;
+    s->t += dt;
+    s->info[0] = F0;
+    s->info[1] = F1;
+    s->info[2] = F2;
+    s->info[3] = E;
+    s->info[4] = umax;
+    s->info[5] = dt;
+    s->info[6] = bad ? 1.0 : s->info[6];
+    s->info[7] = s->t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// mask: distance keys per triangle, then chi and u_s per cell
+// ---------------------------------------------------------------------------
+
+// Closest point of triangle (a, b, c) to p by Voronoi-region classification
+// (vertex, edge or face region).  Coordinates are relative to a.  Returns the
+// squared distance and the barycentric weights (wa, wb, wc).
+template <typename T>
+__device__ __forceinline__ T closest_on_triangle(T px, T py, T pz, T bx, T by, T bz, T cx, T cy, T cz, T& wa, T& wb,
+                                                 T& wc) {
+  // p, b, c are relative to vertex a
+  const T d1 = bx * px + by * py + bz * pz;
+  const T d2 = cx * px + cy * py + cz * pz;
+  T qx, qy, qz;
+  if (d1 <= (T)0 && d2 <= (T)0) {
+    wa = 1; wb = 0; wc = 0;
+    qx = 0; qy = 0; qz = 0;
+  } else {
+    const T bpx = px - bx, bpy = py - by, bpz = pz - bz;
+    const T d3 = bx * bpx + by * bpy + bz * bpz;
+    const T d4 = cx * bpx + cy * bpy + cz * bpz;
+    const T cpx_ = px - cx, cpy = py - cy, cpz = pz - cz;
+    const T d5 = bx * cpx_ + by * cpy + bz * cpz;
+    const T d6 = cx * cpx_ + cy * cpy + cz * cpz;
+    const T vc = d1 * d4 - d3 * d2;
+    const T vb = d5 * d2 - d1 * d6;
+    const T va = d3 * d6 - d5 * d4;
+    if (d3 >= (T)0 && d4 <= d3) {
+      wa = 0; wb = 1; wc = 0;
+      qx = bx; qy = by; qz = bz;
+    } else if (vc <= (T)0 && d1 >= (T)0 && d3 <= (T)0) {
+      const T t = d1 / (d1 - d3);
+      wa = 1 - t; wb = t; wc = 0;
+      qx = t * bx; qy = t * by; qz = t * bz;
+    } else if (d6 >= (T)0 && d5 <= d6) {
+      wa = 0; wb = 0; wc = 1;
+      qx = cx; qy = cy; qz = cz;
+    } else if (vb <= (T)0 && d2 >= (T)0 && d6 <= (T)0) {
+      const T t = d2 / (d2 - d6);
+      wa = 1 - t; wb = 0; wc = t;
+      qx = t * cx; qy = t * cy; qz = t * cz;
+    } else if (va <= (T)0 && (d4 - d3) >= (T)0 && (d5 - d6) >= (T)0) {
+      const T t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+      wa = 0; wb = 1 - t; wc = t;
+      qx = bx + t * (cx - bx); qy = by + t * (cy - by); qz = bz + t * (cz - bz);
+    } else {
+      const T den = va + vb + vc;
+      if (den > (T)0) {
+        const T vv = vb / den, ww = vc / den;
+        wa = 1 - vv - ww; wb = vv; wc = ww;
+        qx = vv * bx + ww * cx; qy = vv * by + ww * cy; qz = vv * bz + ww * cz;
+      } else {
+        // degenerate triangle: nearest of the three edges
+        T best = (T)INFINITY;
+        wa = 1; wb = 0; wc = 0;
+        qx = 0; qy = 0; qz = 0;
+        const T ex[3][6] = {{0, 0, 0, bx, by, bz}, {bx, by, bz, cx, cy, cz}, {cx, cy, cz, 0, 0, 0}};
+        for (int e = 0; e < 3; ++e) {
+          const T ax_ = ex[e][0], ay_ = ex[e][1], az_ = ex[e][2];
+          const T sx = ex[e][3] - ax_, sy = ex[e][4] - ay_, sz = ex[e][5] - az_;
+          const T ss = sx * sx + sy * sy + sz * sz;
+          T t = ss > (T)0 ? ((px - ax_) * sx + (py - ay_) * sy + (pz - az_) * sz) / ss : (T)0;
+          t = t < (T)0 ? (T)0 : (t > (T)1 ? (T)1 : t);
+          const T hx = ax_ + t * sx - px, hy = ay_ + t * sy - py, hz = az_ + t * sz - pz;
+          const T dd = hx * hx + hy * hy + hz * hz;
+          if (dd < best) {
+            best = dd;
+            qx = ax_ + t * sx; qy = ay_ + t * sy; qz = az_ + t * sz;
+            if (e == 0) { wa = 1 - t; wb = t; wc = 0; }
+            else if (e == 1) { wa = 0; wb = 1 - t; wc = t; }
+            else { wa = t; wb = 0; wc = 1 - t; }
+          }
+        }
+      }
+    }
+  }
+  const T hx = px - qx, hy = py - qy, hz = pz - qz;
+  return hx * hx + hy * hy + hz * hz;
+}
+
+__global__ void fill_keys(unsigned long long* k1, unsigned long long* k2, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    k1[i] = ~0ull;
+    k2[i] = ~0ull;
+  }
+}
+
+// Key of the first pass: the FP64 distance truncated to FP32 (monotone in the
+// distance), triangle id in the low word.  Key of the second pass, among the
+// triangles whose truncated distance equals the minimum: the 29 mantissa bits
+// that the truncation dropped, triangle id in the low word.  Together they select
+// the exact FP64 minimum, ties going to the lowest triangle id.
+__device__ __forceinline__ unsigned trunc_bits(double d) { return __float_as_uint(__double2float_rz(d)); }
+__device__ __forceinline__ unsigned low_bits(double d) {
+  return (unsigned)((unsigned long long)__double_as_longlong(d) & ((1ull << 29) - 1));
+}
+
+template <typename T, int PASS>
+__global__ __launch_bounds__(kNT) void mask_dist(MaskArgs<T> a) {
+  const int t = blockIdx.x;
+  if (t >= a.nt) return;
+  const int ia = a.tri[3 * t], ib = a.tri[3 * t + 1], ic = a.tri[3 * t + 2];
+  const double ax = a.x[3 * ia], ay = a.x[3 * ia + 1], az = a.x[3 * ia + 2];
+  const double bx = a.x[3 * ib] - ax, by = a.x[3 * ib + 1] - ay, bz = a.x[3 * ib + 2] - az;
+  const double cx = a.x[3 * ic] - ax, cy = a.x[3 * ic + 1] - ay, cz = a.x[3 * ic + 2] - az;
+  const double lox = fmin(fmin(0.0, bx), cx) + ax - a.rsup, hix = fmax(fmax(0.0, bx), cx) + ax + a.rsup;
+  const double loy = fmin(fmin(0.0, by), cy) + ay - a.rsup, hiy = fmax(fmax(0.0, by), cy) + ay + a.rsup;
+  const double loz = fmin(fmin(0.0, bz), cz) + az - a.rsup, hiz = fmax(fmax(0.0, bz), cz) + az + a.rsup;
+  // index range, one cell of margin, clipped to the sub-box
+  const int i0 = max((int)floor(lox / a.dx) - 1, a.bx0), i1 = min((int)ceil(hix / a.dx) + 1, a.bx0 + a.bnx - 1);
+  const int j0 = max((int)floor(loy / a.dy) - 1, a.by0), j1 = min((int)ceil(hiy / a.dy) + 1, a.by0 + a.bny - 1);
+  const int k0 = max((int)floor(loz / a.dz) - 1, a.bz0), k1 = min((int)ceil(hiz / a.dz) + 1, a.bz0 + a.bnz - 1);
+  if (i1 < i0 || j1 < j0 || k1 < k0) return;
+  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1, nk = k1 - k0 + 1;
+  const int total = ni * nj * nk;
+  for (int q = threadIdx.x; q < total; q += kNT) {
+    const int ii = i0 + q % ni;
+    const int jj = j0 + (q / ni) % nj;
+    const int kk = k0 + q / (ni * nj);
+    const double px = (double)ii * a.dx - ax, py = (double)jj * a.dy - ay, pz = (double)kk * a.dz - az;
+    double wa, wb, wc;
+    const double d = sqrt(closest_on_triangle<double>(px, py, pz, bx, by, bz, cx, cy, cz, wa, wb, wc));
+    if (d < a.rsup) {
+      const long long cell = ((long long)(kk - a.bz0) * a.bny + (jj - a.by0)) * a.bnx + (ii - a.bx0);
+      const unsigned q1 = trunc_bits(d);
+      if (PASS == 1) {
+        atomicMin(a.key1 + cell, ((unsigned long long)q1 << 32) | (unsigned)t);
+      } else if ((unsigned)(a.key1[cell] >> 32) == q1) {
+        atomicMin(a.key2 + cell, ((unsigned long long)low_bits(d) << 32) | (unsigned)t);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double profile_chi(double d, double tw, double h, int profile) {
+  if (profile == 0) {
+    if (d <= tw - h) return 1.0;
+    if (d >= tw + h) return 0.0;
+    return 0.5 * (1.0 + cos(3.14159265358979323846 * (d - tw + h) / (2.0 * h)));
+  }
+  return 0.5 * (1.0 - tanh((d - tw) / h));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void mask_eval(MaskArgs<T> a) {
+  for (long long cell = (long long)blockIdx.x * kNT + threadIdx.x; cell < a.bcells; cell += (long long)gridDim.x * kNT) {
+    const unsigned long long key = a.key2[cell];
+    double ch = 0, u0 = 0, u1 = 0, u2 = 0;
+    if (key != ~0ull) {
+      const int t = (int)(key & 0xffffffffull);
+      const int bx = (int)(cell % a.bnx);
+      const int by = (int)((cell / a.bnx) % a.bny);
+      const int bz = (int)(cell / ((long long)a.bnx * a.bny));
+      const int ia = a.tri[3 * t], ib = a.tri[3 * t + 1], ic = a.tri[3 * t + 2];
+      const double ax = a.x[3 * ia], ay = a.x[3 * ia + 1], az = a.x[3 * ia + 2];
+      const double px = (double)(bx + a.bx0) * a.dx - ax, py = (double)(by + a.by0) * a.dy - ay,
+                   pz = (double)(bz + a.bz0) * a.dz - az;
+      double wa, wb, wc;
+      const double d = sqrt(closest_on_triangle<double>(px, py, pz, a.x[3 * ib] - ax, a.x[3 * ib + 1] - ay,
+                                                        a.x[3 * ib + 2] - az, a.x[3 * ic] - ax, a.x[3 * ic + 1] - ay,
+                                                        a.x[3 * ic + 2] - az, wa, wb, wc));
+      if (d < a.rsup) {
+        ch = profile_chi(d, a.tw, a.h, a.profile);
+        if (ch != 0.0) {
+          u0 = wa * a.v[3 * ia] + wb * a.v[3 * ib] + wc * a.v[3 * ic];
+          u1 = wa * a.v[3 * ia + 1] + wb * a.v[3 * ib + 1] + wc * a.v[3 * ic + 1];
+          u2 = wa * a.v[3 * ia + 2] + wb * a.v[3 * ib + 2] + wc * a.v[3 * ic + 2];
+        }
+      }
+    }
+    a.chi[cell] = (T)ch;
+    a.us[cell] = (T)u0;
+    a.us[a.bcells + cell] = (T)u1;
+    a.us[2 * a.bcells + cell] = (T)u2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+template <typename K>
+static hipError_t set_lds(K kernel, size_t lds) {
+  if (lds > 65536) return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+template <typename T, int W, int MAXE>
+static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStream_t s) {
+  dim3 grid((a.C + W - 1) / W, slices);
+  const size_t lds = (size_t)a.n * W * sizeof(cpx<T>);
+  hipError_t e = hipSuccess;
+#define FSI_COL_CASE(M)                                                        \
+  case M:                                                                      \
+    e = set_lds(col_pass<T, W, MAXE, M>, lds);                                 \
+    if (e != hipSuccess) return e;                                             \
+    hipLaunchKernelGGL((col_pass<T, W, MAXE, M>), grid, dim3(kNT), lds, s, a); \
+    break;
+  switch (mode) {
+    FSI_COL_CASE(COL_INV_PLAIN)
+    FSI_COL_CASE(COL_INV_CURL)
+    FSI_COL_CASE(COL_FWD_PLAIN)
+    FSI_COL_CASE(COL_FWD_PROJECT)
+    FSI_COL_CASE(COL_FWD_UPDATE)
+    default: return hipErrorInvalidValue;
+  }
+#undef FSI_COL_CASE
+  return hipGetLastError();
+}
+
+template <typename T>
+int col_width(int n) {
+  const int cap = (int)(ColMaxE<T>::value * kNT);
+  int w = 64;
+  while (w > 4 && n * w > cap) w >>= 1;
+  return n * w <= cap ? w : 0;
+}
+
+template <typename T>
+hipError_t launch_col(int mode, const ColArgs<T>& a, int slices, hipStream_t s) {
+  constexpr int M = ColMaxE<T>::value;
+  switch (col_width<T>(a.n)) {
+    case 64: return launch_col_w<T, 64, M>(mode, a, slices, s);
+    case 32: return launch_col_w<T, 32, M>(mode, a, slices, s);
+    case 16: return launch_col_w<T, 16, M>(mode, a, slices, s);
+    case 8: return launch_col_w<T, 8, M>(mode, a, slices, s);
+    case 4: return launch_col_w<T, 4, M>(mode, a, slices, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+int xpass_lines(int n) {
+  // four lines per workgroup while the 12 packed signals fit the LDS budget
+  return (n * 12 * (int)sizeof(cpx<T>) <= 65536) ? 4 : 2;
+}
+
+template <typename T, int L, int MAXE>
+static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.n * 3 * L * sizeof(cpx<T>);
+  hipError_t e = set_lds(xpass_fused<T, L, MAXE>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((xpass_fused<T, L, MAXE>), dim3(grid), dim3(kNT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s) {
+  if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4, XMaxE<T>::value>(a, grid, s);
+  return launch_xfused_l<T, 2, XMaxE<T>::value>(a, grid, s);
+}
+
+template <typename T, int NF, int L, int MAXE>
+static hipError_t launch_xplain_l(int mode, const XArgs<T>& a, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.n * (NF * L / 2) * sizeof(cpx<T>);
+  hipError_t e;
+  if (mode == X_C2R) {
+    e = set_lds(xpass_plain<T, NF, L, MAXE, X_C2R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((xpass_plain<T, NF, L, MAXE, X_C2R>), dim3(grid), dim3(kNT), lds, s, a);
+  } else {
+    e = set_lds(xpass_plain<T, NF, L, MAXE, X_R2C>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((xpass_plain<T, NF, L, MAXE, X_R2C>), dim3(grid), dim3(kNT), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xplain(int mode, int nf, const XArgs<T>& a, int grid, hipStream_t s) {
+  constexpr int M = XMaxE<T>::value;
+  const int L = xpass_lines<T>(a.n);
+  if (nf == 1) return L == 4 ? launch_xplain_l<T, 1, 4, M>(mode, a, grid, s) : launch_xplain_l<T, 1, 2, M>(mode, a, grid, s);
+  if (nf == 3) return L == 4 ? launch_xplain_l<T, 3, 4, M>(mode, a, grid, s) : launch_xplain_l<T, 3, 2, M>(mode, a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s) {
+  long long blocks = (a.bcells + kNT - 1) / kNT;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(fill_keys, dim3((unsigned)blocks), dim3(kNT), 0, s, a.key1, a.key2, a.bcells);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.nt > 0) {
+    hipLaunchKernelGGL((mask_dist<T, 1>), dim3(a.nt), dim3(kNT), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mask_dist<T, 2>), dim3(a.nt), dim3(kNT), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(mask_eval<T>, dim3((unsigned)blocks), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+template int col_width<float>(int);
+template int col_width<double>(int);
+template int xpass_lines<float>(int);
+template int xpass_lines<double>(int);
+template hipError_t launch_col<float>(int, const ColArgs<float>&, int, hipStream_t);
+template hipError_t launch_col<double>(int, const ColArgs<double>&, int, hipStream_t);
+template hipError_t launch_xfused<float>(const XArgs<float>&, int, hipStream_t);
+template hipError_t launch_xfused<double>(const XArgs<double>&, int, hipStream_t);
+template hipError_t launch_xplain<float>(int, int, const XArgs<float>&, int, hipStream_t);
+template hipError_t launch_xplain<double>(int, int, const XArgs<double>&, int, hipStream_t);
+template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);
+template hipError_t launch_mask<double>(const MaskArgs<double>&, hipStream_t);
+
+}  // namespace fsi

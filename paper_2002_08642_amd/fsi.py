@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libfsi.so (include/fsi.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The library must be built (``python -m paper_2002_08642_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly if it is missing.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsi.so")
+
+FSI_OK = 0
+STATUS = {
+    0: "FSI_OK", -1: "FSI_EINVAL", -2: "FSI_ENOMEM", -3: "FSI_EDEVICE", -4: "FSI_EBOUNDS",
+    -5: "FSI_ESTATE", -6: "FSI_ENAN", -7: "FSI_ESTABILITY",
+}
+PROFILE_COS = 0
+PROFILE_TANH = 1
+PREC_FP32 = 0
+PREC_FP64 = 1
+NPASS = 7
+PASS_NAMES = ["mask", "z_inverse_curl", "y_inverse", "x_fused", "reduce_dt", "y_forward", "z_forward_update"]
+
+# every symbol declared in include/fsi.h
+EXPORTS = [
+    "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
+    "fsi_set_velocity", "fsi_set_velocity_device", "fsi_get_velocity", "fsi_get_spectrum",
+    "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
+    "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
+    "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose",
+]
+
+
+class FsiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+        ("nu", ctypes.c_double), ("eta", ctypes.c_double),
+        ("tw", ctypes.c_double), ("h", ctypes.c_double),
+        ("mask_profile", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfsi.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is not built; run paper_2002_08642_amd.build.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    I32 = ctypes.c_int32
+    lib.fsi_version.restype = I32
+    lib.fsi_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(P)]
+    lib.fsi_destroy.argtypes = [P]
+    lib.fsi_last_error.argtypes = [P]
+    lib.fsi_last_error.restype = ctypes.c_char_p
+    lib.fsi_create_error.restype = ctypes.c_char_p
+    lib.fsi_band.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_int64)]
+    lib.fsi_set_velocity.argtypes = [P, D]
+    lib.fsi_set_velocity_device.argtypes = [P, P, I32]
+    lib.fsi_get_velocity.argtypes = [P, D]
+    lib.fsi_get_spectrum.argtypes = [P, D]
+    lib.fsi_set_wing.argtypes = [P, I32, D, D, I32, ctypes.POINTER(I32)]
+    lib.fsi_get_mask.argtypes = [P, D, D]
+    lib.fsi_step.argtypes = [P, ctypes.c_double]
+    lib.fsi_step_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.fsi_get_step_info.argtypes = [P, D, D, D, D, D, ctypes.POINTER(ctypes.c_int64)]
+    lib.fsi_fft_r2c.argtypes = [P, D, D]
+    lib.fsi_fft_c2r.argtypes = [P, D, D]
+    lib.fsi_save_state.argtypes = [P, I32]
+    lib.fsi_load_state.argtypes = [P, I32]
+    lib.fsi_synchronize.argtypes = [P]
+    lib.fsi_set_timing.argtypes = [P, I32]
+    lib.fsi_get_pass_times.argtypes = [P, D, ctypes.POINTER(I32)]
+    lib.fsi_plate_pose.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, I32, D, D, D, D]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype if name in (
+            "fsi_last_error", "fsi_create_error", "fsi_version") else ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def plate_pose(s, c, t, alpha, omega, t_ramp, axis, law=0):
+    """Rigid revolving-plate vertex positions and velocities (fsi_plate_pose)."""
+    lib = load_library()
+    s = _f64(s)
+    c = _f64(c)
+    nv = s.shape[0]
+    x = np.zeros((nv, 3))
+    v = np.zeros((nv, 3))
+    ph = np.zeros(2)
+    ax = _f64(axis)
+    rc = lib.fsi_plate_pose(nv, _dptr(s), _dptr(c), t, alpha, omega, t_ramp, law, _dptr(ax),
+                            _dptr(x), _dptr(v), _dptr(ph))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_plate_pose")
+    return x, v, ph
+
+
+class Solver:
+    """One context of the penalized pseudo-spectral step (see include/fsi.h)."""
+
+    def __init__(self, n, L, nu, eta, tw=0.0, h=1.0, profile=PROFILE_COS, precision=PREC_FP32, stream=None):
+        self.lib = load_library()
+        self.n = tuple(int(a) for a in n)
+        nx, ny, nz = self.n
+        d = Desc(nx, ny, nz, float(L[0]), float(L[1]), float(L[2]), float(nu), float(eta), float(tw),
+                 float(h), int(profile), int(precision), 0, stream)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.fsi_create(ctypes.byref(d), ctypes.byref(ctx))
+        if rc != FSI_OK:
+            raise FsiError(rc, self.lib.fsi_create_error().decode())
+        self.ctx = ctx
+        K = (ctypes.c_int32 * 3)()
+        cl = ctypes.c_int64()
+        self._check(self.lib.fsi_band(self.ctx, K, ctypes.byref(cl)))
+        self.K = (K[0], K[1], K[2])
+        self.compact_len = cl.value
+
+    def _check(self, rc):
+        if rc != FSI_OK:
+            raise FsiError(rc, self.lib.fsi_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.fsi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape3(self):
+        nx, ny, nz = self.n
+        return (nz, ny, nx)
+
+    @property
+    def compact_shape(self):
+        Kx, Ky, Kz = self.K
+        return (2 * Kz + 1, 2 * Ky + 1, Kx + 1)
+
+    def set_velocity(self, u):
+        u = _f64(u, (3,) + self.shape3)
+        self._check(self.lib.fsi_set_velocity(self.ctx, _dptr(u)))
+
+    def set_velocity_device(self, ptr, dtype):
+        self._check(self.lib.fsi_set_velocity_device(self.ctx, ctypes.c_void_p(ptr), int(dtype)))
+
+    def velocity(self):
+        u = np.zeros((3,) + self.shape3)
+        self._check(self.lib.fsi_get_velocity(self.ctx, _dptr(u)))
+        return u
+
+    def spectrum(self):
+        out = np.zeros((3,) + self.compact_shape + (2,))
+        self._check(self.lib.fsi_get_spectrum(self.ctx, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def set_wing(self, x, v, tri):
+        x = _f64(x)
+        v = _f64(v)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nv = x.shape[0] if x.ndim == 2 else 0
+        nt = tri.shape[0] if tri.ndim == 2 else 0
+        self._check(self.lib.fsi_set_wing(self.ctx, nv, _dptr(x), _dptr(v), nt,
+                                          tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+    def clear_wing(self):
+        self._check(self.lib.fsi_set_wing(self.ctx, 0, None, None, 0, None))
+
+    def mask(self):
+        chi = np.zeros(self.shape3)
+        us = np.zeros((3,) + self.shape3)
+        self._check(self.lib.fsi_get_mask(self.ctx, _dptr(chi), _dptr(us)))
+        return chi, us
+
+    def step(self, dt):
+        self._check(self.lib.fsi_step(self.ctx, float(dt)))
+
+    def step_adaptive(self, cfl, c_eta, dt_max):
+        self._check(self.lib.fsi_step_adaptive(self.ctx, float(cfl), float(c_eta), float(dt_max)))
+
+    def info(self):
+        F = np.zeros(3)
+        v = np.zeros(4)
+        ns = ctypes.c_int64()
+        rc = self.lib.fsi_get_step_info(self.ctx, _dptr(F), _dptr(v[0:1]), _dptr(v[1:2]), _dptr(v[2:3]),
+                                        _dptr(v[3:4]), ctypes.byref(ns))
+        self._check(rc)
+        return {"F": F, "dt": float(v[0]), "E": float(v[1]), "umax": float(v[2]), "t": float(v[3]),
+                "nstep": int(ns.value)}
+
+    def fft_r2c(self, f):
+        f = _f64(f, self.shape3)
+        out = np.zeros(self.compact_shape + (2,))
+        self._check(self.lib.fsi_fft_r2c(self.ctx, _dptr(f), _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def fft_c2r(self, fh):
+        fh = np.asarray(fh, dtype=np.complex128).reshape(self.compact_shape)
+        buf = np.ascontiguousarray(np.stack([fh.real, fh.imag], axis=-1))
+        f = np.zeros(self.shape3)
+        self._check(self.lib.fsi_fft_c2r(self.ctx, _dptr(buf), _dptr(f)))
+        return f
+
+    def save(self, slot):
+        self._check(self.lib.fsi_save_state(self.ctx, int(slot)))
+
+    def load(self, slot):
+        self._check(self.lib.fsi_load_state(self.ctx, int(slot)))
+
+    def synchronize(self):
+        self._check(self.lib.fsi_synchronize(self.ctx))
+
+    def set_timing(self, on):
+        self._check(self.lib.fsi_set_timing(self.ctx, 1 if on else 0))
+
+    def pass_times(self):
+        ms = np.zeros(NPASS)
+        n = ctypes.c_int32()
+        self._check(self.lib.fsi_get_pass_times(self.ctx, _dptr(ms), ctypes.byref(n)))
+        return dict(zip(PASS_NAMES, ms)), int(n.value)

@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads and exports every function declared in include/fsi.h;
+descriptor validation fails before any device call; the host kinematics
+entry point agrees with the oracle's revolving-plate pose (Sec. 4.2.2)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2002_08642_amd import fsi
+from oracle import kinematics
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fsi.h")).read()
+    decl = r"^\s*(?:fsi_status|int32_t|const char\s*\*)\s*(fsi_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fsi.load_library()
+    names = header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(fsi.EXPORTS) == names
+    assert lib.fsi_version() >= 100
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(33, 32, 32)), dict(n=(14, 32, 32)), dict(n=(4, 32, 32)), dict(L=(0.0, 1, 1)),
+    dict(eta=0.0), dict(h=0.0), dict(nu=-1.0), dict(profile=7), dict(precision=3),
+])
+def test_descriptor_validation_happens_before_device_use(bad):
+    kw = dict(n=(32, 32, 32), L=(1.0, 1.0, 1.0), nu=0.01, eta=1e-3, tw=0.0, h=1.0, profile=0, precision=0)
+    kw.update(bad)
+    with pytest.raises(fsi.FsiError) as e:
+        fsi.Solver(kw["n"], kw["L"], kw["nu"], kw["eta"], kw["tw"], kw["h"], kw["profile"], kw["precision"])
+    assert e.value.code == -1
+
+
+def test_null_arguments_are_rejected():
+    lib = fsi.load_library()
+    assert lib.fsi_create(None, None) == -1
+    assert lib.fsi_step(None, ctypes.c_double(1e-3)) == -1
+    assert lib.fsi_destroy(None) == 0
+
+
+@pytest.mark.parametrize("law", [0, 1])
+def test_plate_pose_matches_oracle_kinematics(law):
+    cfg = synth.revolving_plate()
+    s, c = cfg["span_coord"], cfg["chord_coord"]
+    for t in (0.0, 0.13, 0.4, 0.77):
+        x, v, ph = fsi.plate_pose(s, c, t, cfg["alpha"], cfg["omega"], cfg["t_ramp"], cfg["axis_point"], law)
+        xo, vo = kinematics.plate_pose(s, c, t, cfg["alpha"], cfg["omega"], cfg["t_ramp"], cfg["axis_point"], law)
+        assert np.max(np.abs(x - xo)) < 1e-13
+        assert np.max(np.abs(v - vo)) < 1e-12
+        phi, rate = kinematics.angle_and_rate(t, cfg["omega"], cfg["t_ramp"], law)
+        assert ph[0] == pytest.approx(phi, abs=1e-14) and ph[1] == pytest.approx(rate, abs=1e-13)
