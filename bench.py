@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the penalized pseudo-spectral Navier-Stokes step on one MI355X.
+
+Workload (512^3 by default): periodic box of side 12 (four plate spans), a
+random divergence-free velocity field with a k^(-5/3) spectrum and unit
+energy, and the rigid revolving plate (span 3, chord 1, 45 deg pitch,
+41 x 13 vertices = 960 triangles) turning at full speed Omega = 2 pi; nu =
+pi/300 (Re = 1800), eta = 2.5e-3 (128/N)^2, cosine mask with t_w = 2 dx,
+h = dx; adaptive dt (CFL 0.1, C_eta 2/3, dt_max 1e-2).  One step = host pose
+of the plate at t^n, mesh upload, mask rebuild, the five transform passes,
+reductions and device-side dt, and the read-back of dt / forces that the next
+pose needs.
+
+Prints one JSON line: Mpts/s (FP32 bulk with FP64 reductions) with the FP64
+run beside it, the roofline of the dominant kernel (HIP events on the library
+stream, algorithmic bytes of that pass), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(n):
+    import synth
+    cfg = synth.revolving_plate(n=n, t_ramp=0.0)
+    return cfg
+
+
+def algorithmic_bytes(n, wsize, cells):
+    """Bytes each pass must move (unpadded layouts), per launch."""
+    K = (n - 1) // 3
+    kx1, nb = K + 1, 2 * K + 1
+    c = 2 * wsize  # complex value
+    compact = nb * nb * kx1 * c
+    zslab = n * nb * kx1 * c       # [z][iy][ix]
+    yslab = n * n * kx1 * c        # [z][y][ix]
+    return {
+        "z_inverse_curl": 3 * compact + 6 * zslab,
+        "y_inverse": 6 * zslab + 6 * yslab,
+        "x_fused": 9 * yslab + 4 * cells * wsize,
+        "y_forward": 3 * yslab + 3 * zslab,
+        "z_forward_update": 3 * zslab + 12 * compact,
+    }
+
+
+def step_model_bytes(n, wsize):
+    """Whole-step pass model (one HBM round trip per axis pass, 5 fields after z)."""
+    K = (n - 1) // 3
+    kx1, nb = K + 1, 2 * K + 1
+    c = 2 * wsize
+    compact = nb * nb * kx1 * c
+    zslab = n * nb * kx1 * c
+    yslab = n * n * kx1 * c
+    return (3 * compact + 5 * zslab) + (5 * zslab + 6 * yslab) + 9 * yslab + (3 * yslab + 3 * zslab) \
+        + (3 * zslab + 12 * compact)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_lds.h", "kernels.h", "launch.h", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2002_08642_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(n, prec, steps, warmup, timing):
+    from paper_2002_08642_amd import fsi
+    import synth
+    cfg = workload(n)
+    s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
+    s.set_spectrum(synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0))
+    t = 0.0
+
+    def one_step(t):
+        x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], t, cfg["alpha"], cfg["omega"],
+                                 0.0, cfg["axis_point"])
+        s.set_wing(x, v, cfg["tri"])
+        s.step_adaptive(cfg["cfl"], cfg["c_eta"], cfg["dt_max"])
+        info = s.info()
+        return t + info["dt"], info
+
+    for _ in range(warmup):
+        t, info = one_step(t)
+    s.synchronize()
+    sync_torch()
+    s.set_timing(timing)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t, info = one_step(t)
+    s.synchronize()
+    sync_torch()
+    el = time.perf_counter() - t0
+    passes, nrec = s.pass_times() if timing else ({}, 0)
+    s.set_timing(False)
+    per_pass = {k: v / max(nrec, 1) for k, v in passes.items()}
+    return el / steps, per_pass, info
+
+
+_torch = None
+
+
+def sync_torch():
+    global _torch
+    if _torch is None:
+        try:
+            import torch
+            _torch = torch if torch.cuda.is_available() else False
+        except Exception:
+            _torch = False
+    if _torch:
+        _torch.cuda.synchronize()
+
+
+def cpu_baseline(n_sample):
+    import numpy as np
+    import synth
+    from oracle import ns, kinematics
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 0) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    cfg = workload(n_sample)
+    o = ns.OracleNS(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"])
+    o.set_velocity(synth.random_solenoidal(cfg["n"], cfg["L"], seed=0))
+    nsteps = 3
+    t = 0.0
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        x, v = kinematics.plate_pose(cfg["span_coord"], cfg["chord_coord"], t, cfg["alpha"], cfg["omega"], 0.0,
+                                     cfg["axis_point"])
+        o.set_wing(x, v, cfg["tri"])
+        t += o.step(cfl=cfg["cfl"], c_eta=cfg["c_eta"], dt_max=cfg["dt_max"])["dt"]
+    el = (time.perf_counter() - t0) / nsteps
+    return {"value": n_sample ** 3 / el / 1e6, "unit": "Mpts/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d full oracle steps (mask, naive matrix DFTs, update) of the same workload recipe at "
+                      "%d^3, %.1f s each; the 512^3 oracle step needs ~40 GB and minutes" % (nsteps, n_sample, el)}
+
+
+def load_traffic(n, dominant, wsize):
+    path = os.path.join(ROOT, "profiles", "pmc_%d_fp32.json" % n)
+    if wsize != 4 or not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        if d.get("source_hash") != kernel_source_hash():
+            return None
+        k = d["kernels"].get(dominant)
+        if not k:
+            return None
+        return k["bytes_per_dispatch"]
+    except Exception:
+        return None
+
+
+def calibrate_copy():
+    """A plain 1 GiB device copy, for scaling the HBM byte counters under rocprofv3."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--fp64-steps", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    from paper_2002_08642_amd import fsi
+    fsi.load_library()
+    if args.calibrate_copy:
+        calibrate_copy()
+
+    n = args.n
+    ms32, pass32, info32 = run_gpu(n, fsi.PREC_FP32, args.steps, args.warmup, True)
+    ms64, pass64, _ = (None, {}, None)
+    if args.fp64_steps > 0:
+        ms64, pass64, _ = run_gpu(n, fsi.PREC_FP64, args.fp64_steps, 2, True)
+
+    dominant = max(pass32, key=pass32.get)
+    cfg = workload(n)
+    # sub-box cells of the mask (chi + 3 u_s read by the fused x pass)
+    dx = cfg["L"][0] / n
+    cells = 0
+    try:
+        x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], 0.0, cfg["alpha"], cfg["omega"], 0.0,
+                                 cfg["axis_point"])
+        r = cfg["tw"] + cfg["h"]
+        span = (x.max(axis=0) + r) - (x.min(axis=0) - r)
+        cells = int(math.prod(int(math.ceil(sv / dx)) + 2 for sv in span))
+    except Exception:
+        pass
+    algo = algorithmic_bytes(n, 4, cells)
+    t_dom = pass32[dominant] * 1e-3
+    achieved = algo.get(dominant, 0) / t_dom / 1e9 if dominant in algo else None
+    traffic = load_traffic(n, dominant, 4)
+    model = step_model_bytes(n, 4)
+    value = n ** 3 / (ms32) / 1e6
+    out = {
+        "metric": "Mpts/s per full NS step at %d^3 (FP32 bulk, FP64 reductions)" % n,
+        "value": round(value, 1),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "revolving rigid plate in k^-5/3 turbulence, %d^3 periodic box" % n,
+                   "grid": [n, n, n], "box": cfg["L"][0], "triangles": int(len(cfg["tri"])),
+                   "nu": cfg["nu"], "eta": cfg["eta"], "dt": "adaptive (CFL 0.1, C_eta 2/3)",
+                   "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": None if achieved is None else round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes": algo.get(dominant),
+            "launch_ms": round(pass32[dominant], 4),
+        },
+        "step_roofline": {
+            "model_bytes": model,
+            "frac": round(model / ms32 / 1e9 / HBM_PEAK_GBS, 4),
+            "pass_ms": {k: round(v, 4) for k, v in pass32.items()},
+        },
+        "fp64": None if ms64 is None else {
+            "value": round(n ** 3 / ms64 / 1e6, 1), "unit": "Mpts/s", "ms_per_step": round(ms64 * 1e3, 4),
+            "steps": args.fp64_steps,
+            "step_roofline_frac": round(step_model_bytes(n, 8) / ms64 / 1e9 / HBM_PEAK_GBS, 4),
+            "pass_ms": {k: round(v, 4) for k, v in pass64.items()},
+        },
+        "last_step": {"dt": info32["dt"], "umax": info32["umax"], "E": info32["E"],
+                      "F": [float(f) for f in info32["F"]]},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -107,6 +107,13 @@ fsi_status fsi_set_velocity(fsi_ctx* ctx, const double* u_host);
  * (borrowed for the duration of the call only). */
 fsi_status fsi_set_velocity_device(fsi_ctx* ctx, const void* u_dev, int32_t dtype);
 
+/* Set the velocity from its compact spectrum uhat[3][compact_len] (interleaved
+ * re, im; layout of the conventions above). The field is taken through the
+ * physical grid (imaginary parts that a real field cannot carry on the kx = 0
+ * plane are dropped) and Leray-projected; resets the Adams-Bashforth history
+ * like fsi_set_velocity. Synchronizes. */
+fsi_status fsi_set_spectrum(fsi_ctx* ctx, const double* uhat_host);
+
 /* Physical velocity u[3][nz][ny][nx] of the current state. Synchronizes. */
 fsi_status fsi_get_velocity(fsi_ctx* ctx, double* u_host);
 

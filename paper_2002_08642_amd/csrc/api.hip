@@ -91,6 +91,11 @@ fsi_status fsi_set_velocity_device(fsi_ctx* ctx, const void* u_dev, int32_t dtyp
   return ctx->eng->set_velocity_device(u_dev, dtype);
 }
 
+fsi_status fsi_set_spectrum(fsi_ctx* ctx, const double* uhat_host) {
+  if (guard(ctx) != FSI_OK || !uhat_host) return FSI_EINVAL;
+  return ctx->eng->set_spectrum(uhat_host);
+}
+
 fsi_status fsi_get_velocity(fsi_ctx* ctx, double* u_host) {
   if (guard(ctx) != FSI_OK || !u_host) return FSI_EINVAL;
   return ctx->eng->get_velocity(u_host);

@@ -17,6 +17,7 @@ class EngineBase {
   virtual void band(int K[3], long long* clen) const = 0;
   virtual fsi_status set_velocity_host(const double* u) = 0;
   virtual fsi_status set_velocity_device(const void* u, int dtype) = 0;
+  virtual fsi_status set_spectrum(const double* uh) = 0;
   virtual fsi_status get_velocity(double* u) = 0;
   virtual fsi_status get_spectrum(double* uh) = 0;
   virtual fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) = 0;

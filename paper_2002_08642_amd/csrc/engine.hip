@@ -88,12 +88,17 @@ class Engine : public EngineBase {
     Ky = band_k(ny);
     Kz = band_k(nz);
     kx1 = Kx + 1;
+    {
+      const int line = 128 / (int)sizeof(cpx<T>);  // complex values per 128-byte line
+      kxp = (kx1 + line - 1) / line * line;
+    }
     nby = 2 * Ky + 1;
     nbz = 2 * Kz + 1;
-    C1 = (long long)nby * kx1;
+    C1 = (long long)nby * kxp;
     clen = (long long)nbz * C1;
+    clen_ext = (long long)nbz * nby * kx1;
     Alen = (long long)nz * C1;
-    Blen = (long long)nz * ny * kx1;
+    Blen = (long long)nz * ny * kxp;
     npts = (long long)nx * ny * nz;
     dxs[0] = d.lx / nx;
     dxs[1] = d.ly / ny;
@@ -112,7 +117,7 @@ class Engine : public EngineBase {
       }
     }
     const int L = xpass_lines<T>(nx);
-    if ((long long)nx * 3 * L > (long long)XMaxE<T>::value * kNT || ((long long)ny * nz) % L != 0) {
+    if (L == 0 || ((long long)ny * nz) % L != 0) {
       err = "nx too long for the x pass in this precision";
       return FSI_EINVAL;
     }
@@ -141,7 +146,7 @@ class Engine : public EngineBase {
     K[0] = Kx;
     K[1] = Ky;
     K[2] = Kz;
-    *cl = clen;
+    *cl = clen_ext;
   }
 
   // -- velocity in / out -----------------------------------------------------
@@ -180,6 +185,21 @@ class Engine : public EngineBase {
     return finish_set_velocity();
   }
 
+  fsi_status set_spectrum(const double* in) override {
+    for (long long i = 0; i < 6 * clen_ext; ++i)
+      if (!std::isfinite(in[i])) {
+        err = "non-finite value in the spectrum";
+        return FSI_EINVAL;
+      }
+    FSI_TRY(ensure_phys());
+    std::vector<cpx<T>> h(3 * clen);
+    memset(h.data(), 0, sizeof(cpx<T>) * 3 * clen);
+    for (int q = 0; q < 3; ++q) pad(in + 2 * q * clen_ext, h.data() + q * clen);
+    FSI_HIP(hipMemcpyAsync(uh, h.data(), sizeof(cpx<T>) * 3 * clen, hipMemcpyHostToDevice, s));
+    FSI_TRY(run_inverse(uh, clen, 3, phys));
+    return finish_set_velocity();
+  }
+
   fsi_status get_velocity(double* u) override {
     FSI_TRY(ensure_phys());
     FSI_TRY(run_inverse(uh, clen, 3, phys));
@@ -191,10 +211,7 @@ class Engine : public EngineBase {
     std::vector<cpx<T>> h(3 * clen);
     FSI_HIP(hipMemcpyAsync(h.data(), uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToHost, s));
     FSI_HIP(hipStreamSynchronize(s));
-    for (long long i = 0; i < 3 * clen; ++i) {
-      out[2 * i] = (double)h[i].re;
-      out[2 * i + 1] = (double)h[i].im;
-    }
+    for (int q = 0; q < 3; ++q) unpad(h.data() + q * clen, out + 2 * q * clen_ext);
     return nan_status();
   }
 
@@ -344,7 +361,7 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[1], s));
     // P1: z inverse of u and of omega = i k x u
     {
-      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = uh;
       a.in_fs = clen;
       a.out = A;
@@ -354,13 +371,13 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[2], s));
     // P2: y inverse of the six fields
     {
-      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = A;
       a.in_fs = Alen;
       a.in_bs = C1;
       a.out = B;
       a.out_fs = Blen;
-      a.out_bs = (long long)ny * kx1;
+      a.out_bs = (long long)ny * kxp;
       a.nf = 6;
       FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
     }
@@ -404,10 +421,10 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[5], s));
     // P4: y forward of G, truncated to the y band
     {
-      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = B;
       a.in_fs = Blen;
-      a.in_bs = (long long)ny * kx1;
+      a.in_bs = (long long)ny * kxp;
       a.out = A;
       a.out_fs = Alen;
       a.out_bs = C1;
@@ -418,7 +435,7 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[6], s));
     // P5: z forward, dealias, Leray projection, integrating-factor AB2
     {
-      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = A;
       a.in_fs = Alen;
       a.uh = uh;
@@ -466,10 +483,7 @@ class Engine : public EngineBase {
     std::vector<cpx<T>> h(clen);
     FSI_HIP(hipMemcpyAsync(h.data(), cwork, sizeof(cpx<T>) * clen, hipMemcpyDeviceToHost, s));
     FSI_HIP(hipStreamSynchronize(s));
-    for (long long i = 0; i < clen; ++i) {
-      fh[2 * i] = (double)h[i].re;
-      fh[2 * i + 1] = (double)h[i].im;
-    }
+    unpad(h.data(), fh);
     return FSI_OK;
   }
 
@@ -477,10 +491,8 @@ class Engine : public EngineBase {
     FSI_TRY(ensure_phys());
     FSI_TRY(ensure_cwork());
     std::vector<cpx<T>> h(clen);
-    for (long long i = 0; i < clen; ++i) {
-      h[i].re = (T)fh[2 * i];
-      h[i].im = (T)fh[2 * i + 1];
-    }
+    memset(h.data(), 0, sizeof(cpx<T>) * clen);
+    pad(fh, h.data());
     FSI_HIP(hipMemcpyAsync(cwork, h.data(), sizeof(cpx<T>) * clen, hipMemcpyHostToDevice, s));
     FSI_TRY(run_inverse(cwork, clen, 1, phys));
     return download_real(phys, f, npts);
@@ -639,6 +651,26 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // packed [iz][iy][kx1] interleaved doubles -> padded [iz][iy][kxp]
+  void pad(const double* in, cpx<T>* h) const {
+    for (long long r = 0; r < (long long)nbz * nby; ++r)
+      for (int ix = 0; ix < kx1; ++ix) {
+        const long long e = r * kx1 + ix;
+        h[r * kxp + ix].re = (T)in[2 * e];
+        h[r * kxp + ix].im = (T)in[2 * e + 1];
+      }
+  }
+
+  // padded [iz][iy][kxp] -> packed [iz][iy][kx1] interleaved doubles
+  void unpad(const cpx<T>* h, double* out) const {
+    for (long long r = 0; r < (long long)nbz * nby; ++r)
+      for (int ix = 0; ix < kx1; ++ix) {
+        const long long e = r * kx1 + ix;
+        out[2 * e] = (double)h[r * kxp + ix].re;
+        out[2 * e + 1] = (double)h[r * kxp + ix].im;
+      }
+  }
+
   fsi_status ensure_phys() {
     if (!phys) FSI_TRY(alloc(&phys, 3 * npts));
     return FSI_OK;
@@ -674,10 +706,13 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
-  ColArgs<T> col_base(const FftPlan& p, const cpx<T>* tw, int n, int K, long long C) {
+  // C: columns to transform; ld: row pitch (both in complex elements)
+  ColArgs<T> col_base(const FftPlan& p, const cpx<T>* tw, int n, int K, long long C, long long ld) {
     ColArgs<T> a;
     memset(&a, 0, sizeof(a));
     a.C = (int)C;
+    a.ld = (int)ld;
+    a.kxp = kxp;
     a.n = n;
     a.K = K;
     a.nf = 1;
@@ -699,6 +734,7 @@ class Engine : public EngineBase {
     a.ny = ny;
     a.n = nx;
     a.kx1 = kx1;
+    a.ld = kxp;
     a.plan = px;
     a.tw = twx;
     return a;
@@ -707,7 +743,7 @@ class Engine : public EngineBase {
   // compact (nf fields, stride cstride) -> physical (nf fields)
   fsi_status run_inverse(const cpx<T>* comp, long long cstride, int nf, T* out) {
     {
-      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = comp;
       a.in_fs = cstride;
       a.out = A;
@@ -716,13 +752,13 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
     }
     {
-      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = A;
       a.in_fs = Alen;
       a.in_bs = C1;
       a.out = B;
       a.out_fs = Blen;
-      a.out_bs = (long long)ny * kx1;
+      a.out_bs = (long long)ny * kxp;
       a.nf = nf;
       FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
     }
@@ -749,10 +785,10 @@ class Engine : public EngineBase {
       FSI_HIP(launch_xplain<T>(X_R2C, nf, a, npart, s));
     }
     {
-      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1);
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = B;
       a.in_fs = Blen;
-      a.in_bs = (long long)ny * kx1;
+      a.in_bs = (long long)ny * kxp;
       a.out = A;
       a.out_fs = Alen;
       a.out_bs = C1;
@@ -760,7 +796,7 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
     }
     {
-      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1);
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = A;
       a.in_fs = Alen;
       a.out = cout;
@@ -832,8 +868,8 @@ class Engine : public EngineBase {
 
   fsi_desc d;
   hipStream_t s = nullptr;
-  int nx = 0, ny = 0, nz = 0, Kx = 0, Ky = 0, Kz = 0, kx1 = 0, nby = 0, nbz = 0;
-  long long C1 = 0, clen = 0, Alen = 0, Blen = 0, npts = 0;
+  int nx = 0, ny = 0, nz = 0, Kx = 0, Ky = 0, Kz = 0, kx1 = 0, kxp = 0, nby = 0, nbz = 0;
+  long long C1 = 0, clen = 0, clen_ext = 0, Alen = 0, Blen = 0, npts = 0;
   double dxs[3] = {0, 0, 0}, dV = 0, dx_min = 0, rsup = 0;
   FftPlan px, py, pz;
   int ngroups = 0, npart = 0;

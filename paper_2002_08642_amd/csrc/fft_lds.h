@@ -1,7 +1,8 @@
 // fft_lds.h - batched mixed-radix complex FFT held in LDS, for gfx950.
 //
 // A workgroup transforms W interleaved signals of length n stored in LDS as
-// buf[row * W + col] (row = sample index, col = signal).  The transform is a
+// buf[row * RS + col] (row = sample index, col = signal, RS >= W a row stride
+// that may be padded against LDS bank conflicts).  The transform is a
 // self-sorting (Stockham) decomposition n = R_0 R_1 ... R_{s-1} with radices
 // 2, 3, 4, 5 and 8: stage s (span Ns = R_0 ... R_{s-1}) reads R samples spaced
 // n/R apart, multiplies sample r by w^(r (j mod Ns) n/(Ns R)) with
@@ -48,6 +49,14 @@ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.re, -a.im); }
 template <typename T, int SGN>
 __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
   return SGN > 0 ? mk(-a.im, a.re) : mk(a.im, -a.re);
+}
+
+// Returns x through an empty asm statement so that the compiler treats it as a
+// fresh value: address arithmetic derived from it is recomputed inside loops
+// instead of being hoisted and kept live in registers for the whole kernel.
+__device__ __forceinline__ int opaque(int x) {
+  __asm__ volatile("" : "+v"(x));
+  return x;
 }
 
 constexpr int kMaxStages = 16;
@@ -144,28 +153,32 @@ struct Bfly<T, 5, SGN> {
   }
 };
 
-// One Stockham stage over W interleaved signals.  MAXE bounds n*W/NT.
-template <typename T, int R, int W, int NT, int MAXE, bool INV>
-__device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<T>* __restrict__ tw) {
+// One Stockham stage over W interleaved signals with LDS row stride RS >= W.
+// MAXE bounds n*W/NT.  tw may live in LDS or global memory.
+template <typename T, int R, int W, int RS, int NT, int MAXE, bool INV>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<T>* tw) {
   constexpr int KB = (MAXE + R - 1) / R;
   constexpr int SGN = INV ? 1 : -1;
   const int nR = n / R;
   const int nb = nR * W;
   const int tstride = n / (Ns * R);
+  // An opaque copy of the thread id keeps the compiler from hoisting the LDS
+  // addresses of every radix variant out of the stage loop (that costs ~100 VGPRs).
+  const int tid = opaque((int)threadIdx.x);
   cpx<T> v[KB][R];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const int q = (int)threadIdx.x + k * NT;
+    const int q = tid + k * NT;
     if (q < nb) {
       const int col = q % W, j = q / W;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = buf[(j + r * nR) * W + col];
+      for (int r = 0; r < R; ++r) v[k][r] = buf[(j + r * nR) * RS + col];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const int q = (int)threadIdx.x + k * NT;
+    const int q = tid + k * NT;
     if (q < nb) {
       const int col = q % W, j = q / W;
       const int jm = j % Ns;
@@ -180,7 +193,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<
       Bfly<T, R, SGN>::run(v[k]);
       const int d0 = (j - jm) * R + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(d0 + r * Ns) * W + col] = v[k][r];
+      for (int r = 0; r < R; ++r) buf[(d0 + r * Ns) * RS + col] = v[k][r];
     }
   }
   __syncthreads();
@@ -188,17 +201,17 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<
 
 // Full transform of the W signals in buf (caller has synchronized after filling it;
 // on return the result is in buf and all threads are synchronized).
-template <typename T, int W, int NT, int MAXE, bool INV>
-__device__ void fft_lds(cpx<T>* buf, const FftPlan& p, const cpx<T>* __restrict__ tw) {
+template <typename T, int W, int RS, int NT, int MAXE, bool INV>
+__device__ void fft_lds(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.radix[s];
     switch (R) {
-      case 8: fft_stage<T, 8, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
-      case 4: fft_stage<T, 4, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
-      case 2: fft_stage<T, 2, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
-      case 5: fft_stage<T, 5, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
-      default: fft_stage<T, 3, W, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 8: fft_stage<T, 8, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 4: fft_stage<T, 4, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 2: fft_stage<T, 2, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      case 5: fft_stage<T, 5, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
+      default: fft_stage<T, 3, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
     }
     Ns *= R;
   }

@@ -5,6 +5,8 @@
 //   z-pass output     [z][iy][ix]         (band in y and x, all z)
 //   y-pass output     [z][y][ix]          (band in x, all y and z)
 //   physical          [z][y][x]
+// The ix axis of the spectral layouts is padded to a pitch kxp of whole
+// 128-byte lines, so that every row segment a workgroup moves is line aligned.
 // The step is five passes over these layouts (z-inverse + curl, y-inverse,
 // fused x pass, y-forward, z-forward + projection + update) plus the mask
 // kernels and the reduction that also produces the adaptive dt.
@@ -14,7 +16,7 @@
 
 namespace fsi {
 
-constexpr int kNT = 256;  // threads per workgroup for every pass
+constexpr int kNT = 256;  // threads per workgroup of the mask and reduction kernels
 
 enum ColMode { COL_INV_PLAIN = 0, COL_INV_CURL = 1, COL_FWD_PLAIN = 2, COL_FWD_PROJECT = 3, COL_FWD_UPDATE = 4 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
@@ -33,13 +35,16 @@ struct ColArgs {
   long long in_fs, out_fs;  // field strides (complex elements)
   long long in_bs, out_bs;  // slice strides (blockIdx.y)
   int C;                    // columns per slice
+  int ld;                   // row pitch of in and out (complex elements)
   int n;                    // transform length
   int K;                    // band half width along the transform axis
   int nf;                   // fields (plain modes)
   FftPlan plan;
   const cpx<T>* tw;
-  // spectral bookkeeping for the z passes: column c = iy * kx1 + ix
+  // spectral bookkeeping: column c = iy * kxp + ix, valid while ix < kx1
+  // (kxp pads the x band to whole 128-byte lines)
   int kx1;
+  int kxp;
   int Ky;
   T kfx, kfy, kfz;  // 2 pi / L per axis
   T scale;          // factor applied to forward outputs
@@ -55,8 +60,9 @@ struct ColArgs {
 
 template <typename T>
 struct XArgs {
-  cpx<T>* spec;       // [f][line][kx1]
+  cpx<T>* spec;       // [f][line][ld], kx1 valid entries per line
   long long sfs;      // field stride of spec
+  int ld;             // line pitch of spec (>= kx1, whole 128-byte lines)
   T* phys;            // [f][line][n] (plain modes)
   long long pfs;
   int nlines;         // ny * nz

@@ -35,8 +35,8 @@ template <>
 __device__ __forceinline__ double dev_sqrt<double>(double a) { return sqrt(a); }
 
 // Fixed-order workgroup sum of NV doubles; result valid in thread 0.
-template <int NV>
-__device__ void block_sum(double (&v)[NV], double* red /* [NV][kNT/64] */) {
+template <int NV, int NT>
+__device__ void block_sum(double (&v)[NV], double* red /* [NV][NT/64] */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -45,19 +45,20 @@ __device__ void block_sum(double (&v)[NV], double* red /* [NV][kNT/64] */) {
   }
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[i * (kNT / 64) + wave] = v[i];
+    for (int i = 0; i < NV; ++i) red[i * (NT / 64) + wave] = v[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double s = 0.0;
-      for (int w = 0; w < kNT / 64; ++w) s += red[i * (kNT / 64) + w];
+      for (int w = 0; w < NT / 64; ++w) s += red[i * (NT / 64) + w];
       v[i] = s;
     }
   }
 }
 
+template <int NT>
 __device__ __forceinline__ double block_max(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -65,7 +66,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 0; w < kNT / 64; ++w) v = fmax(v, red[w]);
+    for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[w]);
   }
   return v;
 }
@@ -73,165 +74,197 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // ---------------------------------------------------------------------------
 // column passes: FFT along the slow axis of a [rows][C] slice, W columns per WG
 // ---------------------------------------------------------------------------
+//
+// LDS holds the W columns of the slice (n rows, row stride W) followed by the
+// twiddle table of the axis.  Global loads are issued in unrolled batches
+// into registers before they are written to LDS, so that each thread keeps
+// all of its row loads in flight at once.
 
-template <typename T, int W, int MAXE, int MODE>
-__global__ __launch_bounds__(kNT) void col_pass(ColArgs<T> a) {
+template <typename T, int W, int NT, int MAXE, int MODE>
+__global__ __launch_bounds__(NT) void col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  constexpr int RSTEP = kNT / W;
+  constexpr int RSTEP = NT / W;
   constexpr int MAXO = (2 * MAXE) / 3 + 2;  // band rows per thread (2K+1 <= 2n/3 + 1/3)
   const int tid = threadIdx.x;
   const int col = tid % W;
   const int r0 = tid / W;
   const int c = blockIdx.x * W + col;
-  const bool cok = c < a.C;
+  const bool cok = c < a.C && (c % a.kxp) < a.kx1;
   const int n = a.n, K = a.K, nb = 2 * K + 1;
   const long long ib = (long long)blockIdx.y * a.in_bs;
   const long long ob = (long long)blockIdx.y * a.out_bs;
+  cpx<T>* tws = buf + n * W;
+  for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
 
-  if constexpr (MODE == COL_INV_PLAIN) {
-    for (int f = 0; f < a.nf; ++f) {
-      const cpx<T>* in = a.in + f * a.in_fs + ib;
-      for (int r = r0; r < n; r += RSTEP) {
-        cpx<T> val = mk<T>(0, 0);
-        if (cok) {
-          if (r <= K) val = in[(long long)r * a.C + c];
-          else if (r >= n - K) val = in[(long long)(r - n + nb) * a.C + c];
-        }
-        buf[r * W + col] = val;
+  if constexpr (MODE == COL_INV_PLAIN || MODE == COL_INV_CURL) {
+    // COL_INV_CURL: outputs u (3) and omega = i k x u (3) from the three compact
+    // components; each output loads the one or two components it needs (the
+    // repeated loads of a workgroup's columns are served by L2 / MALL).
+    const int nout = (MODE == COL_INV_CURL) ? 6 : a.nf;
+    for (int o = 0; o < nout; ++o) {
+      const int tid = opaque((int)threadIdx.x);
+      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+      const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+      int qa = o, qb = -1;  // components read: val = i (ka * u[qa] - kb * u[qb]) for o >= 3
+      if (MODE == COL_INV_CURL && o >= 3) {
+        qa = (o == 3) ? 2 : (o == 4) ? 0 : 1;
+        qb = (o == 3) ? 1 : (o == 4) ? 2 : 0;
       }
-      __syncthreads();
-      fft_lds<T, W, kNT, MAXE, true>(buf, a.plan, a.tw);
-      cpx<T>* out = a.out + f * a.out_fs + ob;
-      if (cok)
-        for (int r = r0; r < n; r += RSTEP) out[(long long)r * a.C + c] = buf[r * W + col];
-      __syncthreads();
-    }
-  } else if constexpr (MODE == COL_INV_CURL) {
-    // inputs: the three compact velocity components; outputs u (3) and omega = i k x u (3)
-    cpx<T> ur[3][MAXO];
-    const int ix = c % a.kx1, iy = c / a.kx1;
-    const T kx = a.kfx * (T)ix;
-    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+      const cpx<T>* ina = a.in + (MODE == COL_INV_CURL ? qa : o) * a.in_fs + ib;
+      const cpx<T>* inb = a.in + (qb >= 0 ? qb : 0) * a.in_fs + ib;
+      cpx<T> ua[MAXO], ub[MAXO];
 #pragma unroll
-    for (int k = 0; k < MAXO; ++k) {
-      const int i = r0 + k * RSTEP;
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        ua[k] = (cok && i < nb) ? ina[(long long)i * a.ld + c] : mk<T>(0, 0);
+        if (MODE == COL_INV_CURL) ub[k] = (qb >= 0 && cok && i < nb) ? inb[(long long)i * a.ld + c] : mk<T>(0, 0);
+      }
+      T ka = 0, kb = 0;  // per-column factors; the kz factor is applied per row
+      bool kza = false, kzb = false;
+      if (MODE == COL_INV_CURL && o >= 3) {
+        const int ix = c % a.kxp, iy = c / a.kxp;
+        const T kx = a.kfx * (T)ix;
+        const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+        // o = 3: ky uz - kz uy;  o = 4: kz ux - kx uz;  o = 5: kx uy - ky ux
+        ka = (o == 3) ? ky : (o == 5) ? kx : (T)0;
+        kza = (o == 4);
+        kb = (o == 4) ? kx : (o == 5) ? ky : (T)0;
+        kzb = (o == 3);
+      }
 #pragma unroll
-      for (int q = 0; q < 3; ++q) ur[q][k] = (cok && i < nb) ? a.in[q * a.in_fs + (long long)i * a.C + c] : mk<T>(0, 0);
-    }
-    for (int o = 0; o < 6; ++o) {
-      // zero the gap rows
-      for (int r = r0; r < n; r += RSTEP)
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
         if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+      }
 #pragma unroll
       for (int k = 0; k < MAXO; ++k) {
         const int i = r0 + k * RSTEP;
         if (i < nb) {
-          const T kz = a.kfz * (T)band_mode(i, K);
-          cpx<T> val;
-          if (o < 3) {
-            val = ur[o][k];
-          } else {
-            cpx<T> t;
-            if (o == 3) t = scl(ur[2][k], ky) - scl(ur[1][k], kz);       // ky uz - kz uy
-            else if (o == 4) t = scl(ur[0][k], kz) - scl(ur[2][k], kx);  // kz ux - kx uz
-            else t = scl(ur[1][k], kx) - scl(ur[0][k], ky);              // kx uy - ky ux
-            val = mk<T>(-t.im, t.re);                                    // i t
+          cpx<T> val = ua[k];
+          if (MODE == COL_INV_CURL && o >= 3) {
+            const T kz = a.kfz * (T)band_mode(i, K);
+            const cpx<T> t = scl(ua[k], kza ? kz : ka) - scl(ub[k], kzb ? kz : kb);
+            val = mk<T>(-t.im, t.re);  // i t
           }
           buf[band_to_row(i, K, n) * W + col] = val;
         }
       }
       __syncthreads();
-      fft_lds<T, W, kNT, MAXE, true>(buf, a.plan, a.tw);
+      fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
       cpx<T>* out = a.out + o * a.out_fs + ob;
-      if (cok)
-        for (int r = r0; r < n; r += RSTEP) out[(long long)r * a.C + c] = buf[r * W + col];
-      __syncthreads();
-    }
-  } else if constexpr (MODE == COL_FWD_PLAIN) {
-    for (int f = 0; f < a.nf; ++f) {
-      const cpx<T>* in = a.in + f * a.in_fs + ib;
-      for (int r = r0; r < n; r += RSTEP) buf[r * W + col] = cok ? in[(long long)r * a.C + c] : mk<T>(0, 0);
-      __syncthreads();
-      fft_lds<T, W, kNT, MAXE, false>(buf, a.plan, a.tw);
-      cpx<T>* out = a.out + f * a.out_fs + ob;
-      if (cok)
-        for (int i = r0; i < nb; i += RSTEP) out[(long long)i * a.C + c] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+      if (cok) {
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          if (r < n) out[(long long)r * a.ld + c] = buf[r * W + col];
+        }
+      }
       __syncthreads();
     }
   } else {
-    // COL_FWD_PROJECT / COL_FWD_UPDATE: three components, then projection (+ update)
+    // forward modes: all n rows in, band rows out
+    const int nfield = (MODE == COL_FWD_PLAIN) ? a.nf : 3;
     cpx<T> st[2][MAXO];
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < nfield; ++f) {
+      const int tid = opaque((int)threadIdx.x);
+      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const cpx<T>* in = a.in + f * a.in_fs + ib;
-      for (int r = r0; r < n; r += RSTEP) buf[r * W + col] = cok ? in[(long long)r * a.C + c] : mk<T>(0, 0);
+      cpx<T> tmp[MAXE];
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        tmp[k] = (cok && r < n) ? in[(long long)r * a.ld + c] : mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        if (r < n) buf[r * W + col] = tmp[k];
+      }
       __syncthreads();
-      fft_lds<T, W, kNT, MAXE, false>(buf, a.plan, a.tw);
-      if (f < 2) {
+      fft_lds<T, W, W, NT, MAXE, false>(buf, a.plan, tws);
+      if (MODE == COL_FWD_PLAIN) {
+        cpx<T>* out = a.out + f * a.out_fs + ob;
+        if (cok) {
+#pragma unroll
+          for (int k = 0; k < MAXO; ++k) {
+            const int i = r0 + k * RSTEP;
+            if (i < nb) out[(long long)i * a.ld + c] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          }
+        }
+        __syncthreads();
+      } else if (f < 2) {
 #pragma unroll
         for (int k = 0; k < MAXO; ++k) {
           const int i = r0 + k * RSTEP;
-          if (i < nb) st[f][k] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          if (i < nb) {
+            // no run-time register index (it would spill to scratch)
+            const cpx<T> val = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+            if (f == 0) st[0][k] = val;
+            else st[1][k] = val;
+          }
         }
         __syncthreads();
       }
     }
-    const int ix = c % a.kx1, iy = c / a.kx1;
-    const T kx = a.kfx * (T)ix;
-    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
-    T dtn = 0, dtp = 0, c1 = 0, c2 = 0;
-    if constexpr (MODE == COL_FWD_UPDATE) {
-      const double d_n = a.sc->dt[a.cur];
-      const double d_p = a.sc->dt[a.cur ^ 1];
-      dtn = (T)d_n;
-      dtp = (T)d_p;
-      if (a.first) {
-        c1 = dtn;
-        c2 = 0;
-      } else {
-        const double xi = d_n / d_p;
-        c1 = (T)(d_n * (1.0 + 0.5 * xi));
-        c2 = (T)(d_n * 0.5 * xi);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < MAXO; ++k) {
-      const int i = r0 + k * RSTEP;
-      if (cok && i < nb) {
-        const T kz = a.kfz * (T)band_mode(i, K);
-        cpx<T> n0 = st[0][k], n1 = st[1][k];
-        cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
-        const T k2 = kx * kx + ky * ky + kz * kz;
-        if (k2 > (T)0) {
-          const T ik2 = (T)1 / k2;
-          cpx<T> s = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
-          n0 = n0 - scl(s, kx);
-          n1 = n1 - scl(s, ky);
-          n2 = n2 - scl(s, kz);
-        }
-        const long long idx = (long long)i * a.C + c;
-        if constexpr (MODE == COL_FWD_PROJECT) {
-          a.out[idx] = n0;
-          a.out[a.cfs + idx] = n1;
-          a.out[2 * a.cfs + idx] = n2;
+    if constexpr (MODE == COL_FWD_PROJECT || MODE == COL_FWD_UPDATE) {
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+      T dtn = 0, dtp = 0, c1 = 0, c2 = 0;
+      if constexpr (MODE == COL_FWD_UPDATE) {
+        const double d_n = a.sc->dt[a.cur];
+        const double d_p = a.sc->dt[a.cur ^ 1];
+        dtn = (T)d_n;
+        dtp = (T)d_p;
+        if (a.first) {
+          c1 = dtn;
+          c2 = 0;
         } else {
-          const T en = dev_exp<T>(-a.nu * k2 * dtn);
-          cpx<T> nn[3] = {n0, n1, n2};
-          if (a.first) {
+          const double xi = d_n / d_p;
+          c1 = (T)(d_n * (1.0 + 0.5 * xi));
+          c2 = (T)(d_n * 0.5 * xi);
+        }
+      }
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              const cpx<T> u = a.uh[q * a.cfs + idx];
-              a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en);
-              a.nh[q * a.cfs + idx] = nn[q];
-            }
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (cok && i < nb) {
+          const T kz = a.kfz * (T)band_mode(i, K);
+          cpx<T> n0 = st[0][k], n1 = st[1][k];
+          cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          const T k2 = kx * kx + ky * ky + kz * kz;
+          if (k2 > (T)0) {
+            const T ik2 = (T)1 / k2;
+            cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
+            n0 = n0 - scl(sp, kx);
+            n1 = n1 - scl(sp, ky);
+            n2 = n2 - scl(sp, kz);
+          }
+          const long long idx = (long long)i * a.ld + c;
+          if constexpr (MODE == COL_FWD_PROJECT) {
+            a.out[idx] = n0;
+            a.out[a.cfs + idx] = n1;
+            a.out[2 * a.cfs + idx] = n2;
           } else {
-            const T ee = en * dev_exp<T>(-a.nu * k2 * dtp);
+            const T en = dev_exp<T>(-a.nu * k2 * dtn);
+            const cpx<T> nn[3] = {n0, n1, n2};
+            if (a.first) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              const cpx<T> u = a.uh[q * a.cfs + idx];
-              const cpx<T> np = a.nh[q * a.cfs + idx];
-              a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee);
-              a.nh[q * a.cfs + idx] = nn[q];
+              for (int q = 0; q < 3; ++q) {
+                const cpx<T> u = a.uh[q * a.cfs + idx];
+                a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en);
+                a.nh[q * a.cfs + idx] = nn[q];
+              }
+            } else {
+              const T ee = en * dev_exp<T>(-a.nu * k2 * dtp);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                const cpx<T> u = a.uh[q * a.cfs + idx];
+                const cpx<T> np = a.nh[q * a.cfs + idx];
+                a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee);
+                a.nh[q * a.cfs + idx] = nn[q];
+              }
             }
           }
         }
@@ -243,54 +276,85 @@ __global__ __launch_bounds__(kNT) void col_pass(ColArgs<T> a) {
 // ---------------------------------------------------------------------------
 // x pass: real transforms along x, two real lines packed per complex signal
 // ---------------------------------------------------------------------------
+//
+// LDS holds n rows of packed signals with a padded row stride (odd number of
+// complex values against bank conflicts), then the twiddle table.
+
+template <int W>
+struct PadStride {
+  static constexpr int value = (W % 2 == 0) ? W + 1 : W;
+};
 
 // Fused pass: C2R of (u, omega) for L lines, G = u x omega - (chi/eta)(u - u_s),
 // partial sums of the diagnostics, R2C of G truncated to the x band.
-template <typename T, int L, int MAXE>
-__global__ __launch_bounds__(kNT) void xpass_fused(XArgs<T> a) {
+template <typename T, int L, int NT, int MAXE>
+__global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  __shared__ double red[5 * (kNT / 64)];
+  __shared__ double red[5 * (NT / 64)];
   constexpr int WI = 3 * L;      // inverse: pairs (ux,uy) (uz,wx) (wy,wz) per line
   constexpr int WF = 3 * L / 2;  // forward: (Gx,Gy) per line, (Gz,Gz') per line pair
+  constexpr int RI = PadStride<WI>::value;
+  constexpr int RF = PadStride<WF>::value;
   constexpr int PMAX = (MAXE + 2) / 3;
+  constexpr int FI = MAXE / 3 + 2;  // band items (3 L (K+1)) per thread
   static_assert(L % 2 == 0, "L must be even");
   const int tid = threadIdx.x;
   const int n = a.n, K = a.kx1 - 1;
   const int ngroups = a.nlines / L;
+  const int nitems = 3 * L * a.kx1;
+  cpx<T>* tws = buf + n * RI;
+  for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
 
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int tid = opaque((int)threadIdx.x);
     const int line0 = g * L;
-    // 1) Hermitian-extended packed spectra
-    for (int it = tid; it < 3 * L * n; it += kNT) {
-      const int x = it % n, s = it / n;
-      const int l = s / 3, p = s % 3;
-      if (x <= K) {
-        const long long off = (long long)(line0 + l) * a.kx1 + x;
-        cpx<T> A = a.spec[(2 * p) * a.sfs + off];
-        cpx<T> B = a.spec[(2 * p + 1) * a.sfs + off];
-        if (x == 0) {
-          buf[s] = mk<T>(A.re, B.re);
-        } else {
-          buf[x * WI + s] = mk<T>(A.re - B.im, A.im + B.re);
-          buf[(n - x) * WI + s] = mk<T>(A.re + B.im, B.re - A.im);
+    // 1) Hermitian-extended packed spectra: batched loads, then LDS writes
+    {
+      cpx<T> A[FI], B[FI];
+#pragma unroll
+      for (int k = 0; k < FI; ++k) {
+        const int it = tid + k * NT;
+        if (it < nitems) {
+          const int x = it % a.kx1, s = it / a.kx1;
+          const int l = s / 3, p = s - 3 * (s / 3);
+          const long long off = (long long)(line0 + l) * a.ld + x;
+          A[k] = a.spec[(2 * p) * a.sfs + off];
+          B[k] = a.spec[(2 * p + 1) * a.sfs + off];
         }
-      } else if (x < n - K) {
-        buf[x * WI + s] = mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < FI; ++k) {
+        const int it = tid + k * NT;
+        if (it < nitems) {
+          const int x = it % a.kx1, s = it / a.kx1;
+          if (x == 0) {
+            buf[s] = mk<T>(A[k].re, B[k].re);
+          } else {
+            buf[x * RI + s] = mk<T>(A[k].re - B[k].im, A[k].im + B[k].re);
+            buf[(n - x) * RI + s] = mk<T>(A[k].re + B[k].im, B[k].re - A[k].im);
+          }
+        }
+      }
+      const int gap = n - 2 * K - 1;
+      for (int it = tid; it < WI * gap; it += NT) {
+        const int s = it % WI, x = K + 1 + it / WI;
+        buf[x * RI + s] = mk<T>(0, 0);
       }
     }
     __syncthreads();
-    fft_lds<T, WI, kNT, MAXE, true>(buf, a.plan, a.tw);
+    fft_lds<T, WI, RI, NT, MAXE, true>(buf, a.plan, tws);
 
     // 2) pointwise nonlinear + penalization term and diagnostics
     T g0[PMAX], g1[PMAX], g2[PMAX];
+    const int tid2 = opaque((int)threadIdx.x);
 #pragma unroll
     for (int k = 0; k < PMAX; ++k) {
-      const int it = tid + k * kNT;
+      const int it = tid2 + k * NT;
       if (it < n * L) {
         const int x = it % n, l = it / n;
-        const cpx<T> z1 = buf[x * WI + 3 * l], z2 = buf[x * WI + 3 * l + 1], z3 = buf[x * WI + 3 * l + 2];
+        const cpx<T> z1 = buf[x * RI + 3 * l], z2 = buf[x * RI + 3 * l + 1], z3 = buf[x * RI + 3 * l + 2];
         const T ux = z1.re, uy = z1.im, uz = z2.re;
         const T wx = z2.im, wy = z3.re, wz = z3.im;
         T gx = uy * wz - uz * wy;
@@ -327,39 +391,44 @@ __global__ __launch_bounds__(kNT) void xpass_fused(XArgs<T> a) {
     T* bufr = reinterpret_cast<T*>(buf);
 #pragma unroll
     for (int k = 0; k < PMAX; ++k) {
-      const int it = tid + k * kNT;
+      const int it = tid2 + k * NT;
       if (it < n * L) {
         const int x = it % n, l = it / n;
-        buf[x * WF + l] = mk<T>(g0[k], g1[k]);
-        bufr[2 * (x * WF + L + (l >> 1)) + (l & 1)] = g2[k];
+        buf[x * RF + l] = mk<T>(g0[k], g1[k]);
+        bufr[2 * (x * RF + L + (l >> 1)) + (l & 1)] = g2[k];
       }
     }
     __syncthreads();
-    fft_lds<T, WF, kNT, MAXE, false>(buf, a.plan, a.tw);
+    fft_lds<T, WF, RF, NT, MAXE, false>(buf, a.plan, tws);
 
     // 3) unpack the two real transforms of each signal, keep kx <= K
-    for (int it = tid; it < 3 * L * a.kx1; it += kNT) {
-      const int k = it % a.kx1, s = it / a.kx1;
-      const int l = s / 3, f = s % 3;
-      const int sig = (f < 2) ? l : L + (l >> 1);
-      const bool second = (f == 1) || (f == 2 && (l & 1));
-      const cpx<T> z = buf[k * WF + sig];
-      const cpx<T> zc = conj(buf[((n - k) % n) * WF + sig]);
-      cpx<T> r;
-      if (!second) r = scl(z + zc, (T)0.5);
-      else {
-        const cpx<T> d = z - zc;
-        r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+    const int tid3 = opaque((int)threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < FI; ++k) {
+      const int it = tid3 + k * NT;
+      if (it < nitems) {
+        const int x = it % a.kx1, s = it / a.kx1;
+        const int l = s / 3, f = s - 3 * (s / 3);
+        const int sig = (f < 2) ? l : L + (l >> 1);
+        const bool second = (f == 1) || (f == 2 && (l & 1));
+        const cpx<T> z = buf[x * RF + sig];
+        const cpx<T> zc = conj(buf[((n - x) % n) * RF + sig]);
+        cpx<T> r;
+        if (!second) r = scl(z + zc, (T)0.5);
+        else {
+          const cpx<T> d = z - zc;
+          r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+        }
+        a.spec[f * a.sfs + (long long)(line0 + l) * a.ld + x] = r;
       }
-      a.spec[f * a.sfs + (long long)(line0 + l) * a.kx1 + k] = r;
     }
     __syncthreads();
   }
 
   double v[4] = {aF0, aF1, aF2, aE};
-  block_sum<4>(v, red);
+  block_sum<4, NT>(v, red);
   __syncthreads();
-  const double m = block_max(aM, red);
+  const double m = block_max<NT>(aM, red);
   if (tid == 0) {
     double* p = a.partials + (long long)blockIdx.x * 8;
     p[0] = v[0];
@@ -375,60 +444,63 @@ __global__ __launch_bounds__(kNT) void xpass_fused(XArgs<T> a) {
 
 // Plain real transforms along x for NF fields of L lines: real signal r = l * NF + f,
 // complex signal j packs real signals 2j (real part) and 2j + 1 (imaginary part).
-template <typename T, int NF, int L, int MAXE, int MODE>
-__global__ __launch_bounds__(kNT) void xpass_plain(XArgs<T> a) {
+template <typename T, int NF, int L, int NT, int MAXE, int MODE>
+__global__ __launch_bounds__(NT) void xpass_plain(XArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int S = NF * L / 2;
+  constexpr int RSS = PadStride<S>::value;
   static_assert((NF * L) % 2 == 0, "need an even number of real signals");
   const int tid = threadIdx.x;
   const int n = a.n, K = a.kx1 - 1;
   const int ngroups = a.nlines / L;
+  cpx<T>* tws = buf + n * RSS;
+  for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int line0 = g * L;
     if constexpr (MODE == X_C2R) {
-      for (int it = tid; it < S * n; it += kNT) {
+      for (int it = tid; it < S * n; it += NT) {
         const int x = it % n, j = it / n;
         const int ra = 2 * j, rb = 2 * j + 1;
         if (x <= K) {
-          const cpx<T> A = a.spec[(ra % NF) * a.sfs + (long long)(line0 + ra / NF) * a.kx1 + x];
-          const cpx<T> B = a.spec[(rb % NF) * a.sfs + (long long)(line0 + rb / NF) * a.kx1 + x];
+          const cpx<T> A = a.spec[(ra % NF) * a.sfs + (long long)(line0 + ra / NF) * a.ld + x];
+          const cpx<T> B = a.spec[(rb % NF) * a.sfs + (long long)(line0 + rb / NF) * a.ld + x];
           if (x == 0) buf[j] = mk<T>(A.re, B.re);
           else {
-            buf[x * S + j] = mk<T>(A.re - B.im, A.im + B.re);
-            buf[(n - x) * S + j] = mk<T>(A.re + B.im, B.re - A.im);
+            buf[x * RSS + j] = mk<T>(A.re - B.im, A.im + B.re);
+            buf[(n - x) * RSS + j] = mk<T>(A.re + B.im, B.re - A.im);
           }
         } else if (x < n - K) {
-          buf[x * S + j] = mk<T>(0, 0);
+          buf[x * RSS + j] = mk<T>(0, 0);
         }
       }
       __syncthreads();
-      fft_lds<T, S, kNT, MAXE, true>(buf, a.plan, a.tw);
-      for (int it = tid; it < 2 * S * n; it += kNT) {
+      fft_lds<T, S, RSS, NT, MAXE, true>(buf, a.plan, tws);
+      for (int it = tid; it < 2 * S * n; it += NT) {
         const int x = it % n, r = it / n;
-        const cpx<T> z = buf[x * S + (r >> 1)];
+        const cpx<T> z = buf[x * RSS + (r >> 1)];
         a.phys[(r % NF) * a.pfs + (long long)(line0 + r / NF) * n + x] = (r & 1) ? z.im : z.re;
       }
       __syncthreads();
     } else {
       T* bufr = reinterpret_cast<T*>(buf);
-      for (int it = tid; it < 2 * S * n; it += kNT) {
+      for (int it = tid; it < 2 * S * n; it += NT) {
         const int x = it % n, r = it / n;
-        bufr[2 * (x * S + (r >> 1)) + (r & 1)] = a.phys[(r % NF) * a.pfs + (long long)(line0 + r / NF) * n + x];
+        bufr[2 * (x * RSS + (r >> 1)) + (r & 1)] = a.phys[(r % NF) * a.pfs + (long long)(line0 + r / NF) * n + x];
       }
       __syncthreads();
-      fft_lds<T, S, kNT, MAXE, false>(buf, a.plan, a.tw);
-      for (int it = tid; it < 2 * S * a.kx1; it += kNT) {
+      fft_lds<T, S, RSS, NT, MAXE, false>(buf, a.plan, tws);
+      for (int it = tid; it < 2 * S * a.kx1; it += NT) {
         const int k = it % a.kx1, r = it / a.kx1;
-        const cpx<T> z = buf[k * S + (r >> 1)];
-        const cpx<T> zc = conj(buf[((n - k) % n) * S + (r >> 1)]);
+        const cpx<T> z = buf[k * RSS + (r >> 1)];
+        const cpx<T> zc = conj(buf[((n - k) % n) * RSS + (r >> 1)]);
         cpx<T> v;
         if (!(r & 1)) v = scl(z + zc, (T)0.5);
         else {
           const cpx<T> d = z - zc;
           v = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
         }
-        a.spec[(r % NF) * a.sfs + (long long)(line0 + r / NF) * a.kx1 + k] = v;
+        a.spec[(r % NF) * a.sfs + (long long)(line0 + r / NF) * a.ld + k] = v;
       }
       __syncthreads();
     }
@@ -451,9 +523,9 @@ __global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
     v[3] += q[3];
     m = fmax(m, q[4]);
   }
-  block_sum<4>(v, red);
+  block_sum<4, kNT>(v, red);
   __syncthreads();
-  m = block_max(m, red);
+  m = block_max<kNT>(m, red);
   if (threadIdx.x == 0) {
     const double umax = sqrt(m);
     double dt;
@@ -667,16 +739,16 @@ static hipError_t set_lds(K kernel, size_t lds) {
   return hipSuccess;
 }
 
-template <typename T, int W, int MAXE>
+template <typename T, int W, int NT, int MAXE>
 static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStream_t s) {
   dim3 grid((a.C + W - 1) / W, slices);
-  const size_t lds = (size_t)a.n * W * sizeof(cpx<T>);
+  const size_t lds = (size_t)a.n * (W + 1) * sizeof(cpx<T>);
   hipError_t e = hipSuccess;
-#define FSI_COL_CASE(M)                                                        \
-  case M:                                                                      \
-    e = set_lds(col_pass<T, W, MAXE, M>, lds);                                 \
-    if (e != hipSuccess) return e;                                             \
-    hipLaunchKernelGGL((col_pass<T, W, MAXE, M>), grid, dim3(kNT), lds, s, a); \
+#define FSI_COL_CASE(M)                                                           \
+  case M:                                                                         \
+    e = set_lds(col_pass<T, W, NT, MAXE, M>, lds);                                \
+    if (e != hipSuccess) return e;                                                \
+    hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M>), grid, dim3(NT), lds, s, a); \
     break;
   switch (mode) {
     FSI_COL_CASE(COL_INV_PLAIN)
@@ -692,7 +764,7 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
 
 template <typename T>
 int col_width(int n) {
-  const int cap = (int)(ColMaxE<T>::value * kNT);
+  const int cap = ColCfg<T>::MAXE * ColCfg<T>::NT;
   int w = 64;
   while (w > 4 && n * w > cap) w >>= 1;
   return n * w <= cap ? w : 0;
@@ -700,60 +772,65 @@ int col_width(int n) {
 
 template <typename T>
 hipError_t launch_col(int mode, const ColArgs<T>& a, int slices, hipStream_t s) {
-  constexpr int M = ColMaxE<T>::value;
+  constexpr int M = ColCfg<T>::MAXE, NT = ColCfg<T>::NT;
   switch (col_width<T>(a.n)) {
-    case 64: return launch_col_w<T, 64, M>(mode, a, slices, s);
-    case 32: return launch_col_w<T, 32, M>(mode, a, slices, s);
-    case 16: return launch_col_w<T, 16, M>(mode, a, slices, s);
-    case 8: return launch_col_w<T, 8, M>(mode, a, slices, s);
-    case 4: return launch_col_w<T, 4, M>(mode, a, slices, s);
+    case 64: return launch_col_w<T, 64, NT, M>(mode, a, slices, s);
+    case 32: return launch_col_w<T, 32, NT, M>(mode, a, slices, s);
+    case 16: return launch_col_w<T, 16, NT, M>(mode, a, slices, s);
+    case 8: return launch_col_w<T, 8, NT, M>(mode, a, slices, s);
+    case 4: return launch_col_w<T, 4, NT, M>(mode, a, slices, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 int xpass_lines(int n) {
-  // four lines per workgroup while the 12 packed signals fit the LDS budget
-  return (n * 12 * (int)sizeof(cpx<T>) <= 65536) ? 4 : 2;
+  // four lines per workgroup when their 12 packed signals fit the register bound
+  // and 64 KB of LDS, else two
+  const bool regs = n * 12 <= XCfg<T, 4>::MAXE * XCfg<T, 4>::NT;
+  const bool lds = n * (PadStride<12>::value + 1) * (int)sizeof(cpx<T>) <= 65536;
+  if (regs && lds) return 4;
+  return (n * 6 <= XCfg<T, 2>::MAXE * XCfg<T, 2>::NT) ? 2 : 0;
 }
 
-template <typename T, int L, int MAXE>
+template <typename T, int L>
 static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.n * 3 * L * sizeof(cpx<T>);
-  hipError_t e = set_lds(xpass_fused<T, L, MAXE>, lds);
+  constexpr int NT = XCfg<T, L>::NT, M = XCfg<T, L>::MAXE;
+  const size_t lds = (size_t)a.n * (PadStride<3 * L>::value + 1) * sizeof(cpx<T>);
+  hipError_t e = set_lds(xpass_fused<T, L, NT, M>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((xpass_fused<T, L, MAXE>), dim3(grid), dim3(kNT), lds, s, a);
+  hipLaunchKernelGGL((xpass_fused<T, L, NT, M>), dim3(grid), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s) {
-  if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4, XMaxE<T>::value>(a, grid, s);
-  return launch_xfused_l<T, 2, XMaxE<T>::value>(a, grid, s);
+  if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4>(a, grid, s);
+  return launch_xfused_l<T, 2>(a, grid, s);
 }
 
-template <typename T, int NF, int L, int MAXE>
+template <typename T, int NF, int L>
 static hipError_t launch_xplain_l(int mode, const XArgs<T>& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.n * (NF * L / 2) * sizeof(cpx<T>);
+  constexpr int NT = XCfg<T, L>::NT, M = XCfg<T, L>::MAXE;
+  const size_t lds = (size_t)a.n * (PadStride<NF * L / 2>::value + 1) * sizeof(cpx<T>);
   hipError_t e;
   if (mode == X_C2R) {
-    e = set_lds(xpass_plain<T, NF, L, MAXE, X_C2R>, lds);
+    e = set_lds(xpass_plain<T, NF, L, NT, M, X_C2R>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((xpass_plain<T, NF, L, MAXE, X_C2R>), dim3(grid), dim3(kNT), lds, s, a);
+    hipLaunchKernelGGL((xpass_plain<T, NF, L, NT, M, X_C2R>), dim3(grid), dim3(NT), lds, s, a);
   } else {
-    e = set_lds(xpass_plain<T, NF, L, MAXE, X_R2C>, lds);
+    e = set_lds(xpass_plain<T, NF, L, NT, M, X_R2C>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((xpass_plain<T, NF, L, MAXE, X_R2C>), dim3(grid), dim3(kNT), lds, s, a);
+    hipLaunchKernelGGL((xpass_plain<T, NF, L, NT, M, X_R2C>), dim3(grid), dim3(NT), lds, s, a);
   }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xplain(int mode, int nf, const XArgs<T>& a, int grid, hipStream_t s) {
-  constexpr int M = XMaxE<T>::value;
   const int L = xpass_lines<T>(a.n);
-  if (nf == 1) return L == 4 ? launch_xplain_l<T, 1, 4, M>(mode, a, grid, s) : launch_xplain_l<T, 1, 2, M>(mode, a, grid, s);
-  if (nf == 3) return L == 4 ? launch_xplain_l<T, 3, 4, M>(mode, a, grid, s) : launch_xplain_l<T, 3, 2, M>(mode, a, grid, s);
+  if (nf == 1) return L == 4 ? launch_xplain_l<T, 1, 4>(mode, a, grid, s) : launch_xplain_l<T, 1, 2>(mode, a, grid, s);
+  if (nf == 3) return L == 4 ? launch_xplain_l<T, 3, 4>(mode, a, grid, s) : launch_xplain_l<T, 3, 2>(mode, a, grid, s);
   return hipErrorInvalidValue;
 }
 

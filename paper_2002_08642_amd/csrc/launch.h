@@ -7,29 +7,37 @@
 
 namespace fsi {
 
-// Upper bound of (transform length x signals) / threads held per thread in a
-// pass: 64 KB of LDS per workgroup for the column passes in both precisions.
+// Workgroup size and per-thread element bound (transform length x signals /
+// threads) of the column passes: 64 KB of LDS data per workgroup.
 template <typename T>
-struct ColMaxE;
+struct ColCfg;
 template <>
-struct ColMaxE<float> {
-  static constexpr int value = 32;
+struct ColCfg<float> {
+  static constexpr int NT = 512, MAXE = 16;
 };
 template <>
-struct ColMaxE<double> {
-  static constexpr int value = 16;
+struct ColCfg<double> {
+  static constexpr int NT = 512, MAXE = 8;
 };
 
-// Same bound for the x pass (the packed signals of 2 or 4 lines).
-template <typename T>
-struct XMaxE;
+// Same for the x pass, per number L of lines per workgroup (3L packed signals).
+template <typename T, int L>
+struct XCfg;
 template <>
-struct XMaxE<float> {
-  static constexpr int value = 40;
+struct XCfg<float, 4> {
+  static constexpr int NT = 512, MAXE = 12;
 };
 template <>
-struct XMaxE<double> {
-  static constexpr int value = 20;
+struct XCfg<float, 2> {
+  static constexpr int NT = 512, MAXE = 20;
+};
+template <>
+struct XCfg<double, 4> {
+  static constexpr int NT = 512, MAXE = 6;
+};
+template <>
+struct XCfg<double, 2> {
+  static constexpr int NT = 512, MAXE = 10;
 };
 
 // Columns per workgroup of a column pass of length n (0 if n is too long).

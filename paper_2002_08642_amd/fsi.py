@@ -28,7 +28,7 @@ PASS_NAMES = ["mask", "z_inverse_curl", "y_inverse", "x_fused", "reduce_dt", "y_
 # every symbol declared in include/fsi.h
 EXPORTS = [
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
-    "fsi_set_velocity", "fsi_set_velocity_device", "fsi_get_velocity", "fsi_get_spectrum",
+    "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
     "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose",
@@ -75,6 +75,7 @@ def load_library():
     lib.fsi_band.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_int64)]
     lib.fsi_set_velocity.argtypes = [P, D]
     lib.fsi_set_velocity_device.argtypes = [P, P, I32]
+    lib.fsi_set_spectrum.argtypes = [P, D]
     lib.fsi_get_velocity.argtypes = [P, D]
     lib.fsi_get_spectrum.argtypes = [P, D]
     lib.fsi_set_wing.argtypes = [P, I32, D, D, I32, ctypes.POINTER(I32)]
@@ -177,6 +178,11 @@ class Solver:
 
     def set_velocity_device(self, ptr, dtype):
         self._check(self.lib.fsi_set_velocity_device(self.ctx, ctypes.c_void_p(ptr), int(dtype)))
+
+    def set_spectrum(self, uh):
+        uh = np.asarray(uh, dtype=np.complex128).reshape((3,) + self.compact_shape)
+        buf = np.ascontiguousarray(np.stack([uh.real, uh.imag], axis=-1))
+        self._check(self.lib.fsi_set_spectrum(self.ctx, _dptr(buf)))
 
     def velocity(self):
         u = np.zeros((3,) + self.shape3)

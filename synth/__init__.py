@@ -101,6 +101,59 @@ def random_solenoidal(n, L, seed=0, energy=1.0, slope=-11.0 / 6.0):
     return u * math.sqrt(energy / e)
 
 
+def _band_modes(K):
+    return np.concatenate([np.arange(K + 1), np.arange(-K, 0)])
+
+
+def random_solenoidal_compact(n, L, seed=0, energy=1.0, slope=-11.0 / 6.0):
+    """Compact-band spectrum (3, 2Kz+1, 2Ky+1, Kx+1) of a random solenoidal field.
+
+    Same construction as ``random_solenoidal`` (Craya-Herring frame, amplitude
+    |m|^slope, complex Gaussian coefficients), written directly in the compact
+    layout of the library (iz, iy in natural band order, ix = m_x >= 0,
+    K_j = max{m : 3m < n_j}); the kx = 0 plane is made Hermitian and the field is
+    scaled so that E = <|u|^2>/2 = ``energy`` (Parseval on the half spectrum).
+    """
+    nx, ny, nz = n
+    lx, ly, lz = L
+    Kx, Ky, Kz = (nx - 1) // 3, (ny - 1) // 3, (nz - 1) // 3
+    rng = np.random.default_rng(seed)
+    mz = _band_modes(Kz).astype(np.float64)[:, None, None]
+    my = _band_modes(Ky).astype(np.float64)[None, :, None]
+    mx = np.arange(Kx + 1, dtype=np.float64)[None, None, :]
+    shape = (2 * Kz + 1, 2 * Ky + 1, Kx + 1)
+    kx = np.broadcast_to(2 * np.pi * mx / lx, shape)
+    ky = np.broadcast_to(2 * np.pi * my / ly, shape)
+    kz = np.broadcast_to(2 * np.pi * mz / lz, shape)
+    mmag = np.sqrt(mx * mx + my * my + mz * mz)
+    kmag = np.sqrt(kx * kx + ky * ky + kz * kz)
+    par = (kx == 0.0) & (ky == 0.0)
+    # e1 = k x a / |k x a| with a = e_z (e_x when k is parallel to e_z)
+    e1x = np.where(par, 0.0, ky)
+    e1y = np.where(par, kz, -kx)
+    e1z = np.zeros(shape)
+    nrm = np.maximum(np.sqrt(e1x * e1x + e1y * e1y), 1e-300)
+    e1x, e1y = e1x / nrm, e1y / nrm
+    inv = 1.0 / np.maximum(kmag, 1e-300)
+    hx, hy, hz = kx * inv, ky * inv, kz * inv
+    e2x = hy * e1z - hz * e1y
+    e2y = hz * e1x - hx * e1z
+    e2z = hx * e1y - hy * e1x
+    amp = np.where(mmag >= 1.0, np.power(np.maximum(mmag, 1.0), slope), 0.0)
+    c1 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    c2 = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    uh = np.stack([amp * (c1 * e1x + c2 * e2x), amp * (c1 * e1y + c2 * e2y), amp * (c1 * e1z + c2 * e2z)])
+    # Hermitian kx = 0 plane: u(0, -my, -mz) = conj u(0, my, mz)
+    iz = (-np.arange(2 * Kz + 1)) % (2 * Kz + 1)
+    iy = (-np.arange(2 * Ky + 1)) % (2 * Ky + 1)
+    p0 = uh[:, :, :, 0]
+    uh[:, :, :, 0] = 0.5 * (p0 + np.conj(p0[:, iz][:, :, iy]))
+    w = np.ones(Kx + 1)
+    w[1:] = 2.0
+    e = 0.5 * float(np.sum(w * np.sum(np.abs(uh) ** 2, axis=(0, 1, 2))))
+    return uh * np.sqrt(energy / e)
+
+
 # ---------------------------------------------------------------------------
 # wing triangulations (wing frame; no pose)
 # ---------------------------------------------------------------------------

@@ -57,3 +57,25 @@ def test_set_get_velocity_projects_and_dealiases(prec):
     ref = dft.inverse_real(uh)
     assert rel_max(s.velocity(), ref) < 4 * TOL[prec]
     assert rel_max(s.spectrum(), full_to_compact(uh, n)) < 4 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_set_spectrum_round_trip(prec):
+    n = (48, 40, 36)
+    L = (2.0, 1.5, 1.25)
+    s = fsi.Solver(n, L, 0.0, 1.0, precision=prec)
+    uh = synth.random_solenoidal_compact(n, L, seed=9)
+    s.set_spectrum(uh)
+    assert rel_max(s.spectrum(), uh) < 4 * TOL[prec]
+    # the physical field is the oracle's inverse of the Hermitian extension
+    full = np.zeros((3, 36, 40, 48), dtype=np.complex128)
+    Kx, Ky, Kz = s.K
+    mz = np.concatenate([np.arange(Kz + 1), np.arange(-Kz, 0)])
+    my = np.concatenate([np.arange(Ky + 1), np.arange(-Ky, 0)])
+    for a, zz in enumerate(mz):
+        for b, yy in enumerate(my):
+            full[:, zz % 36, yy % 40, :Kx + 1] = uh[:, a, b, :]
+            full[:, (-zz) % 36, (-yy) % 40, (48 - np.arange(1, Kx + 1)) % 48] = np.conj(uh[:, a, b, 1:])
+    ref = dft.inverse_real(full)
+    assert rel_max(s.velocity(), ref) < 4 * TOL[prec]
+    assert abs(0.5 * np.mean(np.sum(ref ** 2, axis=0)) - 1.0) < 1e-12
