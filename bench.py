@@ -112,6 +112,8 @@ _torch = None
 
 def sync_torch():
     global _torch
+    if os.environ.get("FSI_BENCH_NO_TORCH"):
+        return
     if _torch is None:
         try:
             import torch
@@ -166,14 +168,18 @@ def load_traffic(n, dominant, wsize):
 
 
 def calibrate_copy():
-    """A plain 1 GiB device copy, for scaling the HBM byte counters under rocprofv3."""
-    import torch
-    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    torch.cuda.synchronize()
-    b.copy_(a)
-    torch.cuda.synchronize()
+    """A plain 1 GiB device-to-device copy (the runtime's copy kernel), for scaling
+    the HBM byte counters read under rocprofv3."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    nbytes = 1 << 30
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMemcpy(b, a, ctypes.c_size_t(nbytes), 3) == 0  # hipMemcpyDeviceToDevice
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
 
 
 def main():
@@ -185,8 +191,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration under rocprofv3)")
+    ap.add_argument("--no-torch", action="store_true",
+                    help="synchronize through the library only (counter collection runs)")
     args = ap.parse_args()
+    if args.no_torch:
+        os.environ["FSI_BENCH_NO_TORCH"] = "1"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)

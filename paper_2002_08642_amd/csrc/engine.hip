@@ -123,12 +123,13 @@ class Engine : public EngineBase {
     }
     ngroups = (int)(((long long)ny * nz) / L);
     npart = std::min(ngroups, 4096);
+    nfused = xfused_grid(nx, (long long)ny * nz, L);
 
     FSI_TRY(alloc(&uh, 3 * clen));
     FSI_TRY(alloc(&nh, 3 * clen));
     FSI_TRY(alloc(&A, 6 * Alen));
     FSI_TRY(alloc(&B, 6 * Blen));
-    FSI_TRY(alloc(&partials, (long long)npart * 8));
+    FSI_TRY(alloc(&partials, (long long)std::max(npart, nfused) * 8));
     FSI_TRY(alloc(&sc, 1));
     FSI_HIP(hipHostMalloc((void**)&sc_host, sizeof(DevScalars), hipHostMallocDefault));
     FSI_TRY(make_twiddles(nx, &twx));
@@ -400,14 +401,14 @@ class Engine : public EngineBase {
         a.bcells = bcells;
       }
       a.inv_eta = (T)(1.0 / d.eta);
-      FSI_HIP(launch_xfused<T>(a, npart, s));
+      FSI_HIP(launch_xfused<T>(a, nfused, s));
     }
     if (ev) FSI_HIP(hipEventRecord(ev[4], s));
     // diagnostics and dt_n
     {
       FinalArgs f;
       f.partials = partials;
-      f.np = npart;
+      f.np = nfused;
       f.sc = sc;
       f.cur = cur;
       f.adaptive = adaptive ? 1 : 0;
@@ -872,7 +873,7 @@ class Engine : public EngineBase {
   long long C1 = 0, clen = 0, clen_ext = 0, Alen = 0, Blen = 0, npts = 0;
   double dxs[3] = {0, 0, 0}, dV = 0, dx_min = 0, rsup = 0;
   FftPlan px, py, pz;
-  int ngroups = 0, npart = 0;
+  int ngroups = 0, npart = 0, nfused = 0;
   cpx<T>*twx = nullptr, *twy = nullptr, *twz = nullptr;
   cpx<T>*uh = nullptr, *nh = nullptr, *A = nullptr, *B = nullptr, *cwork = nullptr;
   T* phys = nullptr;

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "launch.h"
 
@@ -442,6 +444,227 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// x pass for nx = 512: one wavefront per pair of lines, register-resident FFTs
+// ---------------------------------------------------------------------------
+//
+// A 512-point transform is held by one wavefront, 8 values per lane.  With
+// k = l + 64 r (lane l, register r) and x = x1 + 8 y1 + 64 y2 (lane 8 x1 + y1,
+// register y2), exp(2 pi i k x / 512) splits into three radix-8 DFTs (over r,
+// over the high lane digit, over the low lane digit) separated by two twiddle
+// multiplications and two exchanges through a wave-private LDS buffer.  The
+// inverse maps the natural spectral layout to that permuted physical layout;
+// the forward transform is its exact reverse, so the pointwise work between
+// them is lane-local and no workgroup barrier is needed.
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// exchange slots (padded against LDS bank conflicts): 8 x 72 complex per wave
+__device__ __forceinline__ int xslot1(int x1, int l) { return x1 * 72 + l; }
+__device__ __forceinline__ int xslot2(int x1, int y1, int l1) { return x1 * 72 + y1 * 9 + l1; }
+constexpr int kXBuf = 576;
+
+// inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1
+template <typename T>
+__device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tIB, const cpx<T>* tC) {
+  const int hi = lane >> 3, lo = lane & 7;
+  Bfly<T, 8, 1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tIB[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot1(j, lane)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot1(hi, lo + 8 * j)];
+  wave_sync();
+  Bfly<T, 8, 1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], conj(tC[64 * j + lane]));
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot2(hi, j, lo)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot2(hi, lo, j)];
+  wave_sync();
+  Bfly<T, 8, 1>::run(v);
+}
+
+// forward: v[y2] = g[x1 + 8 y1 + 64 y2]  ->  v[r] = G[lane + 64 r] (unnormalized)
+template <typename T>
+__device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tC, const cpx<T>* tFB) {
+  const int hi = lane >> 3, lo = lane & 7;
+  Bfly<T, 8, -1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tC[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot2(hi, lo, j)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot2(hi, j, lo)];
+  wave_sync();
+  Bfly<T, 8, -1>::run(v);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = cmul(v[j], tFB[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot1(hi, lo + 8 * j)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot1(j, lane)];
+  wave_sync();
+  Bfly<T, 8, -1>::run(v);
+}
+
+// Unpack the transforms X, Y of the two real signals packed in g (natural layout,
+// g[r] = G[lane + 64 r]) and store X to dx, Y to dy for k <= K (K < 192).
+template <typename T>
+__device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, int K, cpx<T>* dx, cpx<T>* dy) {
+  const int src = (64 - lane) & 63;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cpx<T> p;
+    p.re = __shfl(g[7 - r].re, src, 64);
+    p.im = __shfl(g[7 - r].im, src, 64);
+    if (lane == 0) p = g[(8 - r) & 7];
+    const int k = lane + 64 * r;
+    if (k <= K) {
+      const cpx<T> zc = conj(p);
+      const cpx<T> d = g[r] - zc;
+      dx[k] = scl(g[r] + zc, (T)0.5);
+      dy[k] = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+    }
+  }
+}
+
+// One line of the fused pass: C2R of (u, omega), pointwise term and
+// diagnostics, R2C of (Gx, Gy) stored; returns Gz in the physical layout.
+template <typename T>
+__device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int lane, cpx<T>* X, const cpx<T>* tIB,
+                                             const cpx<T>* tC, const cpx<T>* tFB, T (&gz)[8], double& aF0,
+                                             double& aF1, double& aF2, double& aE, double& aM) {
+  constexpr int n = 512, K = 170;  // the 2/3 band of 512 points: 3 * 170 < 512
+  cpx<T> P[3][8];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const cpx<T>* A = a.spec + (2 * p) * a.sfs + (long long)line * a.ld;
+    const cpx<T>* B = a.spec + (2 * p + 1) * a.sfs + (long long)line * a.ld;
+    cpx<T> v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int k = lane + 64 * r;
+      if (k <= K) {
+        const cpx<T> Aa = A[k], Bb = B[k];
+        v[r] = (k == 0) ? mk<T>(Aa.re, Bb.re) : mk<T>(Aa.re - Bb.im, Aa.im + Bb.re);
+      } else if (k >= n - K) {
+        const cpx<T> Aa = A[n - k], Bb = B[n - k];
+        v[r] = mk<T>(Aa.re + Bb.im, Bb.re - Aa.im);
+      } else {
+        v[r] = mk<T>(0, 0);
+      }
+    }
+    inv512<T>(v, X, lane, tIB, tC);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) P[p][j] = v[j];
+    // keep the next signal's loads after this transform (registers, not latency, bound the pass)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // pointwise: G = u x omega - (chi/eta)(u - u_s) and the diagnostics
+  cpx<T> g[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const T ux = P[0][j].re, uy = P[0][j].im, uz = P[1][j].re;
+    const T wx = P[1][j].im, wy = P[2][j].re, wz = P[2][j].im;
+    g[j] = mk<T>(uy * wz - uz * wy, uz * wx - ux * wz);
+    gz[j] = ux * wy - uy * wx;
+    const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+    aE += u2;
+    aM = fmax(aM, u2);
+  }
+  const int z = line / a.ny, y = line - z * a.ny;
+  const int by = y - a.by0, bz = z - a.bz0;
+  if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
+    const long long rowcell = ((long long)bz * a.bny + by) * a.bnx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int bx = (lane >> 3) + 8 * (lane & 7) + 64 * j - a.bx0;
+      if (bx >= 0 && bx < a.bnx) {
+        const long long cell = rowcell + bx;
+        const T ch = a.chi[cell];
+        if (ch != (T)0) {
+          const T sx = P[0][j].re - a.us[cell];
+          const T sy = P[0][j].im - a.us[a.bcells + cell];
+          const T sz = P[1][j].re - a.us[2 * a.bcells + cell];
+          const T ce = ch * a.inv_eta;
+          g[j].re -= ce * sx;
+          g[j].im -= ce * sy;
+          gz[j] -= ce * sz;
+          aF0 += (double)(ch * sx);
+          aF1 += (double)(ch * sy);
+          aF2 += (double)(ch * sz);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  fwd512<T>(g, X, lane, tC, tFB);
+  unpack_store512<T>(g, lane, K, a.spec + (long long)line * a.ld, a.spec + a.sfs + (long long)line * a.ld);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void xpass_wave512(XArgs<T> a) {
+  __shared__ cpx<T> xbuf[4][kXBuf];
+  // per-lane twiddle sets, [j][lane]: exp(+2 pi i lane j / 512), exp(-2 pi i lo j / 64),
+  // exp(-2 pi i (lo + 8 j) hi / 512) with lo = lane & 7, hi = lane >> 3
+  __shared__ cpx<T> tws[3][512];
+  __shared__ double red[5 * 4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cpx<T>* X = xbuf[wv];
+  constexpr int K = 170;
+  for (int i = threadIdx.x; i < 512; i += 256) {
+    const int j = i >> 6, l = i & 63;
+    tws[0][i] = conj(a.tw[(l * j) & 511]);
+    tws[1][i] = a.tw[(8 * (l & 7) * j) & 511];
+    tws[2][i] = a.tw[(((l & 7) + 8 * j) * (l >> 3)) & 511];
+  }
+  __syncthreads();
+  const cpx<T>* tIB = tws[0];
+  const cpx<T>* tC = tws[1];
+  const cpx<T>* tFB = tws[2];
+  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
+  const int npairs = a.nlines / 2;
+#pragma unroll 1
+  for (int pr = blockIdx.x * 4 + wv; pr < npairs; pr += gridDim.x * 4) {
+    T gza[8], gzb[8];
+    const int ln = opaque(lane);
+    wave512_line<T>(a, 2 * pr, ln, X, tIB, tC, tFB, gza, aF0, aF1, aF2, aE, aM);
+    wave512_line<T>(a, 2 * pr + 1, opaque(lane), X, tIB, tC, tFB, gzb, aF0, aF1, aF2, aE, aM);
+    cpx<T> g[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = mk<T>(gza[j], gzb[j]);
+    const int l3 = opaque(lane);
+    fwd512<T>(g, X, l3, tC, tFB);
+    unpack_store512<T>(g, l3, K, a.spec + 2 * a.sfs + (long long)(2 * pr) * a.ld,
+                       a.spec + 2 * a.sfs + (long long)(2 * pr + 1) * a.ld);
+  }
+  double v[4] = {aF0, aF1, aF2, aE};
+  block_sum<4, 256>(v, red);
+  __syncthreads();
+  const double m = block_max<256>(aM, red);
+  if (threadIdx.x == 0) {
+    double* p = a.partials + (long long)blockIdx.x * 8;
+    p[0] = v[0];
+    p[1] = v[1];
+    p[2] = v[2];
+    p[3] = v[3];
+    p[4] = m;
+    p[5] = 0;
+    p[6] = 0;
+    p[7] = 0;
+  }
+}
+
 // Plain real transforms along x for NF fields of L lines: real signal r = l * NF + f,
 // complex signal j packs real signals 2j (real part) and 2j + 1 (imaginary part).
 template <typename T, int NF, int L, int NT, int MAXE, int MODE>
@@ -805,8 +1028,19 @@ static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s) {
+  if (a.n == 512) {
+    hipLaunchKernelGGL(xpass_wave512<T>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4>(a, grid, s);
   return launch_xfused_l<T, 2>(a, grid, s);
+}
+
+// Workgroups of the fused x pass for nlines lines of length n (bounded: each
+// workgroup leaves one row of partial sums).
+int xfused_grid(int n, long long nlines, int lines_per_group) {
+  const long long units = (n == 512) ? nlines / 8 : nlines / lines_per_group;
+  return (int)std::max(1LL, std::min(units, 4096LL));
 }
 
 template <typename T, int NF, int L>

@@ -54,6 +54,7 @@ hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s);
 template <typename T>
 hipError_t launch_xplain(int mode, int nf, const XArgs<T>& a, int grid, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+int xfused_grid(int n, long long nlines, int lines_per_group);
 template <typename T>
 hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
 

@@ -190,3 +190,36 @@ def test_error_paths_on_device():
     with pytest.raises(fsi.FsiError) as e:
         s.set_velocity(bad)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_x_pass_512_parity(prec):
+    # nx = 512 selects the register-resident x pass; thin y, z keep the oracle fast
+    n = (512, 16, 12)
+    L = (8.0, 1.0, 0.75)
+    nu, eta, tw, h = 0.01, 0.05, 0.05, 0.03
+    print("x pass 512", prec, flush=True)
+    o = ons.OracleNS(n, L, nu, eta, tw, h, 0)
+    s = fsi.Solver(n, L, nu, eta, tw, h, 0, prec)
+    u0 = synth.random_solenoidal(n, L, seed=21)
+    o.set_velocity(u0)
+    s.set_velocity(u0)
+    x, tri = synth.flat_rectangle((4.0, 0.5, 0.4), (0, 1, 0), (0, 0, 1), 0.2, 0.15, 5, 4)
+    v = np.tile(np.array([0.3, 0.0, 0.1]), (len(x), 1))
+    o.set_wing(x, v, tri)
+    s.set_wing(x, v, tri)
+    fo, fg = [], []
+    for _ in range(5):
+        d = o.step(dt=0.02)
+        s.step(0.02)
+        i = s.info()
+        fo.append(d["F"])
+        fg.append(i["F"])
+        assert i["umax"] == pytest.approx(d["umax"], rel=VTOL[prec] * 10)
+        assert i["E"] == pytest.approx(d["E"], rel=VTOL[prec] * 10)
+    ev = rel_max(s.velocity(), o.velocity())
+    ef = rel_max(np.array(fg), np.array(fo))
+    print("x pass 512 velocity %.3e force %.3e" % (ev, ef), flush=True)
+    assert np.max(np.abs(np.array(fo))) > 1e-3
+    assert ev < VTOL[prec]
+    assert ef < FTOL[prec]
