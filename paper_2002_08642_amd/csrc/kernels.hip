@@ -83,7 +83,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // all of its row loads in flight at once.
 
 template <typename T, int W, int NT, int MAXE, int MODE>
-__global__ __launch_bounds__(NT) void col_pass(ColArgs<T> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int RSTEP = NT / W;
@@ -101,39 +101,53 @@ __global__ __launch_bounds__(NT) void col_pass(ColArgs<T> a) {
 
   if constexpr (MODE == COL_INV_PLAIN || MODE == COL_INV_CURL) {
     // COL_INV_CURL: outputs u (3) and omega = i k x u (3) from the three compact
-    // components; each output loads the one or two components it needs (the
-    // repeated loads of a workgroup's columns are served by L2 / MALL).
+    // components, produced in the order ux, wy, uz, wx, uy, wz so that two
+    // register sets hold every component while it is needed (four component
+    // loads per workgroup instead of nine).
     const int nout = (MODE == COL_INV_CURL) ? 6 : a.nf;
+    cpx<T> RA[MAXO], RB[MAXO];
+    // component loaded for output o (-1: none) and whether it goes to RB; the load
+    // for output o + 1 is issued right after output o has been written to LDS, so
+    // it is in flight while output o is transformed.
+    auto load_for = [&](int o) {
+      int lq = o, into_b = 0;
+      if (MODE == COL_INV_CURL) {
+        lq = (o == 0) ? 0 : (o == 1) ? 2 : (o == 3) ? 1 : (o == 5) ? 0 : -1;
+        into_b = (o == 1 || o == 5) ? 1 : 0;
+      }
+      if (lq < 0) return;
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + tq % W, rq = tq / W;
+      const bool okq = cq < a.C && (cq % a.kxp) < a.kx1;
+      const cpx<T>* in = a.in + lq * a.in_fs + ib;
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = rq + k * RSTEP;
+        const cpx<T> val = (okq && i < nb) ? in[(long long)i * a.ld + cq] : mk<T>(0, 0);
+        if (into_b) RB[k] = val;
+        else RA[k] = val;
+      }
+    };
+    load_for(0);
     for (int o = 0; o < nout; ++o) {
       const int tid = opaque((int)threadIdx.x);
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
-      int qa = o, qb = -1;  // components read: val = i (ka * u[qa] - kb * u[qb]) for o >= 3
-      if (MODE == COL_INV_CURL && o >= 3) {
-        qa = (o == 3) ? 2 : (o == 4) ? 0 : 1;
-        qb = (o == 3) ? 1 : (o == 4) ? 2 : 0;
-      }
-      const cpx<T>* ina = a.in + (MODE == COL_INV_CURL ? qa : o) * a.in_fs + ib;
-      const cpx<T>* inb = a.in + (qb >= 0 ? qb : 0) * a.in_fs + ib;
-      cpx<T> ua[MAXO], ub[MAXO];
-#pragma unroll
-      for (int k = 0; k < MAXO; ++k) {
-        const int i = r0 + k * RSTEP;
-        ua[k] = (cok && i < nb) ? ina[(long long)i * a.ld + c] : mk<T>(0, 0);
-        if (MODE == COL_INV_CURL) ub[k] = (qb >= 0 && cok && i < nb) ? inb[(long long)i * a.ld + c] : mk<T>(0, 0);
-      }
-      T ka = 0, kb = 0;  // per-column factors; the kz factor is applied per row
-      bool kza = false, kzb = false;
-      if (MODE == COL_INV_CURL && o >= 3) {
+      // output field and combination: o = 0 ux = A; 1 wy = i(kz A - kx B); 2 uz = B;
+      // 3 wx = i(ky B - kz A); 4 uy = A; 5 wz = i(kx A - ky B)
+      const int fo = (MODE == COL_INV_CURL) ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
+      T ka = 0, kb = 0;
+      bool kza = false, kzb = false, cross = false;
+      if (MODE == COL_INV_CURL && (o & 1)) {
         const int ix = c % a.kxp, iy = c / a.kxp;
         const T kx = a.kfx * (T)ix;
         const T ky = a.kfy * (T)band_mode(iy, a.Ky);
-        // o = 3: ky uz - kz uy;  o = 4: kz ux - kx uz;  o = 5: kx uy - ky ux
-        ka = (o == 3) ? ky : (o == 5) ? kx : (T)0;
-        kza = (o == 4);
-        kb = (o == 4) ? kx : (o == 5) ? ky : (T)0;
-        kzb = (o == 3);
+        cross = true;
+        if (o == 1) { kza = true; kb = kx; }
+        else if (o == 3) { kb = ky; kza = true; }
+        else { ka = kx; kb = ky; }
       }
+      const bool useb = (MODE == COL_INV_CURL) && (o == 2 || o == 3);
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
@@ -143,18 +157,21 @@ __global__ __launch_bounds__(NT) void col_pass(ColArgs<T> a) {
       for (int k = 0; k < MAXO; ++k) {
         const int i = r0 + k * RSTEP;
         if (i < nb) {
-          cpx<T> val = ua[k];
-          if (MODE == COL_INV_CURL && o >= 3) {
+          cpx<T> val = useb ? RB[k] : RA[k];
+          if (cross) {
             const T kz = a.kfz * (T)band_mode(i, K);
-            const cpx<T> t = scl(ua[k], kza ? kz : ka) - scl(ub[k], kzb ? kz : kb);
+            // o = 1: kz A - kx B; o = 3: ky B - kz A = -(kz A - ky B); o = 5: kx A - ky B
+            cpx<T> t = scl(RA[k], kza ? kz : ka) - scl(RB[k], kb);
+            if (o == 3) t = mk<T>(-t.re, -t.im);
             val = mk<T>(-t.im, t.re);  // i t
           }
           buf[band_to_row(i, K, n) * W + col] = val;
         }
       }
       __syncthreads();
+      if (o + 1 < nout) load_for(o + 1);
       fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
-      cpx<T>* out = a.out + o * a.out_fs + ob;
+      cpx<T>* out = a.out + fo * a.out_fs + ob;
       if (cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
@@ -538,38 +555,70 @@ __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, 
   }
 }
 
+// Raw spectral values a lane needs for one packed signal of one line: A, B at
+// k = lane + 64 r (r = 0, 1, 2) and at the Hermitian partners n - k of
+// k = lane + 64 r (r = 5, 6, 7); slots outside the 2/3 band are zero.
+template <typename T>
+struct Raw512 {
+  cpx<T> a[6], b[6];
+};
+
+template <typename T>
+__device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int lane, Raw512<T>& w) {
+  constexpr int n = 512, K = 170;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int k = lane + 64 * q;  // direct slots r = q
+    const bool ok = k <= K;
+    w.a[q] = ok ? A[k] : mk<T>(0, 0);
+    w.b[q] = ok ? B[k] : mk<T>(0, 0);
+    const int kp = lane + 64 * (5 + q);  // partner slots r = 5 + q
+    const bool okp = kp >= n - K;
+    w.a[3 + q] = okp ? A[n - kp] : mk<T>(0, 0);
+    w.b[3 + q] = okp ? B[n - kp] : mk<T>(0, 0);
+  }
+}
+
+// Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout v[r] = Z[lane + 64 r].
+template <typename T>
+__device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
+    v[5 + q] = mk<T>(w.a[3 + q].re + w.b[3 + q].im, w.b[3 + q].re - w.a[3 + q].im);
+  }
+  if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
+  v[3] = mk<T>(0, 0);
+  v[4] = mk<T>(0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void load512_sig(const XArgs<T>& a, int line, int p, int lane, Raw512<T>& w) {
+  load512<T>(a.spec + (2 * p) * a.sfs + (long long)line * a.ld, a.spec + (2 * p + 1) * a.sfs + (long long)line * a.ld,
+             lane, w);
+}
+
 // One line of the fused pass: C2R of (u, omega), pointwise term and
 // diagnostics, R2C of (Gx, Gy) stored; returns Gz in the physical layout.
+// On entry pf holds the line's first packed signal; on exit it holds the first
+// signal of line `next` (if next >= 0), loaded while this line is transformed.
 template <typename T>
-__device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int lane, cpx<T>* X, const cpx<T>* tIB,
-                                             const cpx<T>* tC, const cpx<T>* tFB, T (&gz)[8], double& aF0,
-                                             double& aF1, double& aF2, double& aE, double& aM) {
-  constexpr int n = 512, K = 170;  // the 2/3 band of 512 points: 3 * 170 < 512
+__device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int next, int lane, cpx<T>* X,
+                                             const cpx<T>* tIB, const cpx<T>* tC, const cpx<T>* tFB, Raw512<T>& pf,
+                                             T (&gz)[8], double& aF0, double& aF1, double& aF2, double& aE,
+                                             double& aM) {
+  constexpr int K = 170;  // the 2/3 band of 512 points: 3 * 170 < 512
   cpx<T> P[3][8];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    const cpx<T>* A = a.spec + (2 * p) * a.sfs + (long long)line * a.ld;
-    const cpx<T>* B = a.spec + (2 * p + 1) * a.sfs + (long long)line * a.ld;
     cpx<T> v[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int k = lane + 64 * r;
-      if (k <= K) {
-        const cpx<T> Aa = A[k], Bb = B[k];
-        v[r] = (k == 0) ? mk<T>(Aa.re, Bb.re) : mk<T>(Aa.re - Bb.im, Aa.im + Bb.re);
-      } else if (k >= n - K) {
-        const cpx<T> Aa = A[n - k], Bb = B[n - k];
-        v[r] = mk<T>(Aa.re + Bb.im, Bb.re - Aa.im);
-      } else {
-        v[r] = mk<T>(0, 0);
-      }
-    }
+    pack512<T>(pf, lane, v);
+    if (p < 2) load512_sig<T>(a, line, p + 1, lane, pf);  // prefetch: in flight during the transform
     inv512<T>(v, X, lane, tIB, tC);
 #pragma unroll
     for (int j = 0; j < 8; ++j) P[p][j] = v[j];
-    // keep the next signal's loads after this transform (registers, not latency, bound the pass)
-    __builtin_amdgcn_sched_barrier(0);
   }
+  if (next >= 0) load512_sig<T>(a, next, 0, lane, pf);
   // pointwise: G = u x omega - (chi/eta)(u - u_s) and the diagnostics
   cpx<T> g[8];
 #pragma unroll
@@ -634,12 +683,16 @@ __global__ __launch_bounds__(256) void xpass_wave512(XArgs<T> a) {
   const cpx<T>* tFB = tws[2];
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
   const int npairs = a.nlines / 2;
+  Raw512<T> pf;
+  const int pr0 = blockIdx.x * 4 + wv;
+  if (pr0 < npairs) load512_sig<T>(a, 2 * pr0, 0, lane, pf);
 #pragma unroll 1
-  for (int pr = blockIdx.x * 4 + wv; pr < npairs; pr += gridDim.x * 4) {
+  for (int pr = pr0; pr < npairs; pr += gridDim.x * 4) {
     T gza[8], gzb[8];
+    const int nxt = (pr + gridDim.x * 4 < npairs) ? 2 * (pr + gridDim.x * 4) : -1;
     const int ln = opaque(lane);
-    wave512_line<T>(a, 2 * pr, ln, X, tIB, tC, tFB, gza, aF0, aF1, aF2, aE, aM);
-    wave512_line<T>(a, 2 * pr + 1, opaque(lane), X, tIB, tC, tFB, gzb, aF0, aF1, aF2, aE, aM);
+    wave512_line<T>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM);
+    wave512_line<T>(a, 2 * pr + 1, nxt, opaque(lane), X, tIB, tC, tFB, pf, gzb, aF0, aF1, aF2, aE, aM);
     cpx<T> g[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = mk<T>(gza[j], gzb[j]);
