@@ -163,6 +163,40 @@ fsi_status fsi_fft_c2r(fsi_ctx* ctx, const double* fhat, double* f);
 fsi_status fsi_save_state(fsi_ctx* ctx, int32_t slot);
 fsi_status fsi_load_state(fsi_ctx* ctx, int32_t slot);
 
+/* Compact spectrum of the previous nonlinear term N_hat^{n-1}[3][compact_len]
+ * (the Adams-Bashforth history; zero right after fsi_set_velocity). Synchronizes. */
+fsi_status fsi_get_nonlinear(fsi_ctx* ctx, double* nhat_host);
+
+/* ---- adjoint of the step (dt held fixed) --------------------------------
+ * The step maps (u_hat^n, N_hat^{n-1}) to (u_hat^{n+1}, N_hat^n) and yields the
+ * force F^n; its transpose under the inner product Re sum conj(a).b over the
+ * stored compact spectrum is applied by fsi_step_adjoint to the context's
+ * cotangent state (lambda_u, lambda_N), both [3][compact_len] complex.
+ * Transposes used: C2R^T = N^3 m_k R2C (m_k = 1 at kx = 0, else 2),
+ * R2C^T = N^-3 C2R(./m_k), (i k x)^T = i k x, (u x omega)^T, the projection
+ * and integrating factors (real symmetric per mode). */
+
+/* Set the cotangent state (either pointer may be NULL = zero). Synchronizes. */
+fsi_status fsi_adjoint_set(fsi_ctx* ctx, const double* lam_uhat, const double* lam_nprev);
+/* Read the cotangent state (either pointer may be NULL). Synchronizes. */
+fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev);
+
+/* Reverse one step. tape_slot holds the state saved (fsi_save_state) at the
+ * start of the step; the wing of that step must be set (fsi_set_wing); dt is
+ * the step's dt, dt_prev the one before (ignored when first = 1, i.e. the step
+ * was an integrating-factor Euler step). dJdF[3] is the derivative of the
+ * objective with respect to the force F of that step. On return the cotangent
+ * state is (dJ/du_hat^n, dJ/dN_hat^{n-1}) and, if non-NULL, dJdx[nv][3] and
+ * dJdv[nv][3] hold dJ/d(vertex positions, velocities) of that step's mesh
+ * through the mask and the solid velocity. Synchronizes. */
+fsi_status fsi_step_adjoint(fsi_ctx* ctx, int32_t tape_slot, double dt, double dt_prev, int32_t first,
+                            const double dJdF[3], double* dJdx, double* dJdv);
+
+/* Derivatives of fsi_plate_pose's x and v with respect to the pitch alpha
+ * (host, FP64): dxda[nv][3], dvda[nv][3]. */
+fsi_status fsi_plate_pose_dalpha(int32_t nv, const double* s, const double* c, double t, double alpha,
+                                 double omega, double t_ramp, int32_t law, double* dxda, double* dvda);
+
 /* Wait for all queued work of the context. */
 fsi_status fsi_synchronize(fsi_ctx* ctx);
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsi.so")
-SOURCES = ["kernels.hip", "engine.hip", "api.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "engine.hip", "api.hip"]
 ARCH = "gfx950"
 
 

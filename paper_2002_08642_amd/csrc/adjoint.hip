@@ -1,0 +1,377 @@
+// adjoint.hip - reverse (transposed) passes of the penalized pseudo-spectral step.
+//
+// With dt held fixed, one step maps (u_hat^n, N_hat^{n-1}) to
+// (u_hat^{n+1}, N_hat^n) and produces the force F^n (Sec. 4.1 penalized
+// equations, force of Sec. 4.2.2).  Its transpose, under the real inner
+// product on physical arrays and Re sum conj(a) b over the stored half
+// spectrum, is assembled from the same transforms:
+//   C2R^T(lambda) = N^3 m_k R2C_normalized(lambda),
+//   R2C^T(mu)     = N^-3 C2R(mu / m_k),          m_k = 1 at kx = 0, else 2,
+//   (i k x)^T = i k x,  (u x omega)^T: lambda_u = omega x lambda, lambda_omega = lambda x u,
+// and the Leray projection, the 2/3 band and the integrating factors are real
+// symmetric per mode.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "device_util.h"
+#include "kernels.h"
+#include "launch.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------------------
+// spectral part: update transpose and projection
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void adj_spectral(AdjSpecArgs<T> a) {
+  const long long total = (long long)a.nrows * a.kxp;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int ix = (int)(e % a.kxp);
+    if (ix >= a.kx1) continue;
+    const long long row = e / a.kxp;
+    const int iy = (int)(row % a.nby), iz = (int)(row / a.nby);
+    const T kx = a.kfx * (T)ix;
+    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+    const T kz = a.kfz * (T)band_mode(iz, a.Kz);
+    const T k2 = kx * kx + ky * ky + kz * kz;
+    const T en = dev_exp<T>(-a.nu * k2 * (T)a.dt);
+    T an, bn;
+    if (a.first) {
+      an = (T)a.dt;
+      bn = 0;
+    } else {
+      const double xi = a.dt / a.dtp;
+      an = (T)(a.dt * (1.0 + 0.5 * xi));
+      bn = (T)(a.dt * 0.5 * xi);
+    }
+    const T ep = a.first ? (T)0 : dev_exp<T>(-a.nu * k2 * (T)a.dtp);
+    cpx<T> ln[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const cpx<T> lu = a.lu[q * a.cfs + e];
+      const cpx<T> lp = a.lnp[q * a.cfs + e];
+      ln[q] = scl(lu, an * en) + lp;                  // cotangent of N_hat^n
+      a.lnp[q * a.cfs + e] = scl(lu, -bn * en * ep);  // cotangent of N_hat^{n-1}
+      a.lu[q * a.cfs + e] = scl(lu, en);              // update share of u_hat^n
+    }
+    if (k2 > (T)0) {
+      const cpx<T> s = scl(scl(ln[0], kx) + scl(ln[1], ky) + scl(ln[2], kz), (T)1 / k2);
+      ln[0] = ln[0] - scl(s, kx);
+      ln[1] = ln[1] - scl(s, ky);
+      ln[2] = ln[2] - scl(s, kz);
+    }
+    const T sc = (T)(a.invN3 / (ix == 0 ? 1.0 : 2.0));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.mu[q * a.cfs + e] = scl(ln[q], sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused x pass of the reverse step (two lines per workgroup, LDS transforms)
+// ---------------------------------------------------------------------------
+
+template <typename T, int NT, int MAXE>
+__global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int L = 2;
+  constexpr int SI = 9;  // 18 real signals (9 fields x 2 lines) packed in pairs
+  constexpr int SF = 6;  // 12 real signals (6 fields x 2 lines)
+  constexpr int RI = PadStride<SI>::value;
+  constexpr int RF = PadStride<SF>::value;
+  constexpr int PMAX = (2 * MAXE + 8) / 9 + 1;
+  const int n = a.n, K = a.kx1 - 1;
+  const int ngroups = a.nlines / L;
+  cpx<T>* tws = buf + n * RI;
+  for (int i = threadIdx.x; i < n; i += NT) tws[i] = a.tw[i];
+  T* bufr = reinterpret_cast<T*>(buf);
+
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int tid = opaque((int)threadIdx.x);
+    const int line0 = g * L;
+    // 1) C2R of the 9 fields of both lines: real signal r = l * 9 + f, pairs (2j, 2j + 1)
+    for (int it = tid; it < SI * n; it += NT) {
+      const int x = it % n, j = it / n;
+      const int ra = 2 * j, rb = 2 * j + 1;
+      if (x <= K) {
+        const cpx<T> A = a.spec[(ra % 9) * a.sfs + (long long)(line0 + ra / 9) * a.ld + x];
+        const cpx<T> B = a.spec[(rb % 9) * a.sfs + (long long)(line0 + rb / 9) * a.ld + x];
+        if (x == 0) buf[j] = mk<T>(A.re, B.re);
+        else {
+          buf[x * RI + j] = mk<T>(A.re - B.im, A.im + B.re);
+          buf[(n - x) * RI + j] = mk<T>(A.re + B.im, B.re - A.im);
+        }
+      } else if (x < n - K) {
+        buf[x * RI + j] = mk<T>(0, 0);
+      }
+    }
+    __syncthreads();
+    fft_lds<T, SI, RI, NT, MAXE, true>(buf, a.plan, tws);
+
+    // 2) pointwise transpose of G = u x omega - (chi/eta)(u - u_s) and of the force
+    T out[PMAX][6];
+    const int tid2 = opaque((int)threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int it = tid2 + k * NT;
+      if (it < n * L) {
+        const int x = it % n, l = it / n;
+        T f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const int r = l * 9 + q;
+          f[q] = bufr[2 * (x * RI + (r >> 1)) + (r & 1)];
+        }
+        const T ux = f[0], uy = f[1], uz = f[2], wx = f[3], wy = f[4], wz = f[5];
+        const T gx = f[6], gy = f[7], gz = f[8];
+        T lux = wy * gz - wz * gy;  // omega x lambda_G
+        T luy = wz * gx - wx * gz;
+        T luz = wx * gy - wy * gx;
+        const int line = line0 + l;
+        const int z = line / a.ny, y = line - z * a.ny;
+        const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
+        if (a.bnx > 0 && bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {
+          const long long cell = ((long long)bz * a.bny + by) * a.bnx + bx;
+          const T ch = a.chi[cell];
+          const T sx = ux - a.us[cell], sy = uy - a.us[a.bcells + cell], sz = uz - a.us[2 * a.bcells + cell];
+          // lambda_G and the force seed act on (u - u_s) through chi / eta
+          const T hx = (a.g0 - gx) * a.inv_eta, hy = (a.g1 - gy) * a.inv_eta, hz = (a.g2 - gz) * a.inv_eta;
+          lux += ch * hx;
+          luy += ch * hy;
+          luz += ch * hz;
+          a.lchi[cell] = hx * sx + hy * sy + hz * sz;
+          a.lus[cell] = -ch * hx;
+          a.lus[a.bcells + cell] = -ch * hy;
+          a.lus[2 * a.bcells + cell] = -ch * hz;
+        }
+        out[k][0] = lux;
+        out[k][1] = luy;
+        out[k][2] = luz;
+        out[k][3] = gy * uz - gz * uy;  // lambda_G x u
+        out[k][4] = gz * ux - gx * uz;
+        out[k][5] = gx * uy - gy * ux;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int it = tid2 + k * NT;
+      if (it < n * L) {
+        const int x = it % n, l = it / n;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const int r = l * 6 + q;
+          bufr[2 * (x * RF + (r >> 1)) + (r & 1)] = out[k][q];
+        }
+      }
+    }
+    __syncthreads();
+    fft_lds<T, SF, RF, NT, MAXE, false>(buf, a.plan, tws);
+
+    // 3) unpack the 12 real transforms, keep kx <= K
+    const int tid3 = opaque((int)threadIdx.x);
+    for (int it = tid3; it < 2 * SF * a.kx1; it += NT) {
+      const int k = it % a.kx1, r = it / a.kx1;
+      const cpx<T> zz = buf[k * RF + (r >> 1)];
+      const cpx<T> zc = conj(buf[((n - k) % n) * RF + (r >> 1)]);
+      cpx<T> v;
+      if (!(r & 1)) v = scl(zz + zc, (T)0.5);
+      else {
+        const cpx<T> d = zz - zc;
+        v = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+      }
+      a.spec[(r % 6) * a.sfs + (long long)(line0 + r / 6) * a.ld + k] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// mask adjoint: per-triangle vertex cotangents
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double profile_dchi(double d, double tw, double h, int profile) {
+  if (profile == 0) {
+    if (d <= tw - h || d >= tw + h) return 0.0;
+    return -0.5 * sin(3.14159265358979323846 * (d - tw + h) / (2.0 * h)) * 3.14159265358979323846 / (2.0 * h);
+  }
+  const double th = tanh((d - tw) / h);
+  return -0.5 * (1.0 - th * th) / h;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void mask_adj(MaskAdjArgs<T> a) {
+  __shared__ double red[18 * 4];
+  const int t = blockIdx.x;
+  if (t >= a.nt) return;
+  const int iv[3] = {a.tri[3 * t], a.tri[3 * t + 1], a.tri[3 * t + 2]};
+  const double ax = a.x[3 * iv[0]], ay = a.x[3 * iv[0] + 1], az = a.x[3 * iv[0] + 2];
+  const double bx = a.x[3 * iv[1]] - ax, by = a.x[3 * iv[1] + 1] - ay, bz = a.x[3 * iv[1] + 2] - az;
+  const double cx = a.x[3 * iv[2]] - ax, cy = a.x[3 * iv[2] + 1] - ay, cz = a.x[3 * iv[2] + 2] - az;
+  const double lox = fmin(fmin(0.0, bx), cx) + ax - a.rsup, hix = fmax(fmax(0.0, bx), cx) + ax + a.rsup;
+  const double loy = fmin(fmin(0.0, by), cy) + ay - a.rsup, hiy = fmax(fmax(0.0, by), cy) + ay + a.rsup;
+  const double loz = fmin(fmin(0.0, bz), cz) + az - a.rsup, hiz = fmax(fmax(0.0, bz), cz) + az + a.rsup;
+  const int i0 = max((int)floor(lox / a.dx) - 1, a.bx0), i1 = min((int)ceil(hix / a.dx) + 1, a.bx0 + a.bnx - 1);
+  const int j0 = max((int)floor(loy / a.dy) - 1, a.by0), j1 = min((int)ceil(hiy / a.dy) + 1, a.by0 + a.bny - 1);
+  const int k0 = max((int)floor(loz / a.dz) - 1, a.bz0), k1 = min((int)ceil(hiz / a.dz) + 1, a.bz0 + a.bnz - 1);
+  double acc[18];
+#pragma unroll
+  for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+  const double e[2][3] = {{bx, by, bz}, {cx, cy, cz}};
+  if (i1 >= i0 && j1 >= j0 && k1 >= k0) {
+    const int ni = i1 - i0 + 1, nj = j1 - j0 + 1, nk = k1 - k0 + 1;
+    const int total = ni * nj * nk;
+    for (int q = threadIdx.x; q < total; q += 256) {
+      const int ii = i0 + q % ni;
+      const int jj = j0 + (q / ni) % nj;
+      const int kk = k0 + q / (ni * nj);
+      const long long cell = ((long long)(kk - a.bz0) * a.bny + (jj - a.by0)) * a.bnx + (ii - a.bx0);
+      const unsigned long long key = a.key2[cell];
+      if (key == ~0ull || (int)(key & 0xffffffffull) != t) continue;
+      const double p[3] = {(double)ii * a.dx - ax, (double)jj * a.dy - ay, (double)kk * a.dz - az};
+      double w[3];
+      TriRegion rg;
+      const double d2 = closest_on_triangle<double>(p[0], p[1], p[2], bx, by, bz, cx, cy, cz, w[0], w[1], w[2], &rg);
+      const double d = sqrt(d2);
+      if (d >= a.rsup) continue;
+      // closest point relative to vertex a
+      double cp[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cp[c] = w[1] * e[0][c] + w[2] * e[1][c];
+      // distance: d delta / d x_j = -w_j (p - cp) / delta
+      const double gd = (double)a.lchi[cell] * profile_dchi(d, a.tw, a.h, a.profile);
+      if (gd != 0.0 && d > 0.0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[3 * j + c] -= gd * w[j] * (p[c] - cp[c]) / d;
+      }
+      if ((double)a.chi[cell] == 0.0) continue;  // u_s is zero (and constant) there
+      const double lu[3] = {(double)a.lus[cell], (double)a.lus[a.bcells + cell], (double)a.lus[2 * a.bcells + cell]};
+      // velocities: u_s = sum_j w_j v_j
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[9 + 3 * j + c] += w[j] * lu[c];
+      // positions through the barycentric weights of the closest point
+      double vv[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vv[j][c] = a.v[3 * iv[j] + c];
+      if (rg.kind == 0) {
+        // face: (beta, gamma) = M^-1 (e0.d, e1.d), d = p - a
+        const double lb = lu[0] * (vv[1][0] - vv[0][0]) + lu[1] * (vv[1][1] - vv[0][1]) + lu[2] * (vv[1][2] - vv[0][2]);
+        const double lg = lu[0] * (vv[2][0] - vv[0][0]) + lu[1] * (vv[2][1] - vv[0][1]) + lu[2] * (vv[2][2] - vv[0][2]);
+        const double m00 = bx * bx + by * by + bz * bz, m01 = bx * cx + by * cy + bz * cz, m11 = cx * cx + cy * cy + cz * cz;
+        const double det = m00 * m11 - m01 * m01;
+        const double y0 = (m11 * lb - m01 * lg) / det, y1 = (m00 * lg - m01 * lb) / det;
+        const double be = w[1], ga = w[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double ge0 = y0 * p[c] - (2.0 * y0 * be * e[0][c] + (y0 * ga + y1 * be) * e[1][c]);
+          const double ge1 = y1 * p[c] - ((y0 * ga + y1 * be) * e[0][c] + 2.0 * y1 * ga * e[1][c]);
+          const double gdd = y0 * e[0][c] + y1 * e[1][c];
+          acc[3 + c] += ge0;
+          acc[6 + c] += ge1;
+          acc[c] += -ge0 - ge1 - gdd;
+        }
+      } else if (rg.kind == 1) {
+        // edge P0 = vertex i0, P1 = vertex i1, t = (p - P0).s / s.s, s = P1 - P0
+        const double P0[3] = {rg.i0 == 0 ? 0.0 : e[rg.i0 - 1][0], rg.i0 == 0 ? 0.0 : e[rg.i0 - 1][1],
+                              rg.i0 == 0 ? 0.0 : e[rg.i0 - 1][2]};
+        const double P1[3] = {rg.i1 == 0 ? 0.0 : e[rg.i1 - 1][0], rg.i1 == 0 ? 0.0 : e[rg.i1 - 1][1],
+                              rg.i1 == 0 ? 0.0 : e[rg.i1 - 1][2]};
+        double s[3], d0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          s[c] = P1[c] - P0[c];
+          d0[c] = p[c] - P0[c];
+        }
+        const double ss = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+        if (ss > 0.0) {
+          double lt = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) lt += lu[c] * (vv[rg.i1][c] - vv[rg.i0][c]);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double g1 = lt * (d0[c] - 2.0 * rg.t * s[c]) / ss;
+            const double g0 = lt * (-s[c] - d0[c] + 2.0 * rg.t * s[c]) / ss;
+            acc[3 * rg.i1 + c] += g1;
+            acc[3 * rg.i0 + c] += g0;
+          }
+        }
+      }
+    }
+  }
+  // fixed-order workgroup sums
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 18; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[q * 4 + wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 18) {
+    const int q = threadIdx.x;
+    a.tgrad[(long long)t * 18 + q] = ((red[q * 4] + red[q * 4 + 1]) + red[q * 4 + 2]) + red[q * 4 + 3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct XAdjCfg {
+  static constexpr int NT = 512, MAXE = 10;
+};
+
+template <typename T>
+int xadj_supported(int n) {
+  return (n * 9 <= XAdjCfg<T>::MAXE * XAdjCfg<T>::NT) ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s) {
+  long long blocks = ((long long)a.nrows * a.kxp + 255) / 256;
+  blocks = std::max(1LL, std::min(blocks, 16384LL));
+  hipLaunchKernelGGL(adj_spectral<T>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xadj(const XAdjArgs<T>& a, int grid, hipStream_t s) {
+  constexpr int NT = XAdjCfg<T>::NT, M = XAdjCfg<T>::MAXE;
+  const size_t lds = (size_t)a.n * (PadStride<9>::value + 1) * sizeof(cpx<T>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)xpass_adj<T, NT, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((xpass_adj<T, NT, M>), dim3(grid), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mask_adj(const MaskAdjArgs<T>& a, hipStream_t s) {
+  if (a.nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_adj<T>, dim3(a.nt), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adj_spectral<float>(const AdjSpecArgs<float>&, hipStream_t);
+template hipError_t launch_adj_spectral<double>(const AdjSpecArgs<double>&, hipStream_t);
+template hipError_t launch_xadj<float>(const XAdjArgs<float>&, int, hipStream_t);
+template hipError_t launch_xadj<double>(const XAdjArgs<double>&, int, hipStream_t);
+template int xadj_supported<float>(int);
+template int xadj_supported<double>(int);
+template hipError_t launch_mask_adj<float>(const MaskAdjArgs<float>&, hipStream_t);
+template hipError_t launch_mask_adj<double>(const MaskAdjArgs<double>&, hipStream_t);
+
+}  // namespace fsi

@@ -3,8 +3,10 @@
 #include <string.h>
 
 #include <cmath>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/fsi.h"
 #include "engine.h"
@@ -106,6 +108,11 @@ fsi_status fsi_get_spectrum(fsi_ctx* ctx, double* uhat_host) {
   return ctx->eng->get_spectrum(uhat_host);
 }
 
+fsi_status fsi_get_nonlinear(fsi_ctx* ctx, double* nhat_host) {
+  if (guard(ctx) != FSI_OK || !nhat_host) return FSI_EINVAL;
+  return ctx->eng->get_nonlinear(nhat_host);
+}
+
 fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double* v, int32_t nt,
                         const int32_t* tri) {
   if (guard(ctx) != FSI_OK) return FSI_EINVAL;
@@ -154,6 +161,22 @@ fsi_status fsi_save_state(fsi_ctx* ctx, int32_t slot) {
 fsi_status fsi_load_state(fsi_ctx* ctx, int32_t slot) {
   if (guard(ctx) != FSI_OK) return FSI_EINVAL;
   return ctx->eng->load_state(slot);
+}
+
+fsi_status fsi_adjoint_set(fsi_ctx* ctx, const double* lam_uhat, const double* lam_nprev) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->adjoint_set(lam_uhat, lam_nprev);
+}
+
+fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->adjoint_get(lam_uhat, lam_nprev);
+}
+
+fsi_status fsi_step_adjoint(fsi_ctx* ctx, int32_t tape_slot, double dt, double dt_prev, int32_t first,
+                            const double dJdF[3], double* dJdx, double* dJdv) {
+  if (guard(ctx) != FSI_OK || !dJdF) return FSI_EINVAL;
+  return ctx->eng->step_adjoint(tape_slot, dt, dt_prev, first, dJdF, dJdx, dJdv);
 }
 
 fsi_status fsi_synchronize(fsi_ctx* ctx) {
@@ -215,6 +238,32 @@ fsi_status fsi_plate_pose(int32_t nv, const double* s, const double* c, double t
   if (phi_out) {
     phi_out[0] = phi;
     phi_out[1] = rate;
+  }
+  return FSI_OK;
+}
+
+// Derivative of the rigid plate pose with respect to the pitch alpha: the pose
+// x = axis + Rz(phi) (s, c cos alpha, c sin alpha) gives dx/dalpha = Rz(phi)
+// (0, -c sin alpha, c cos alpha) and v = dphi/dt e_z x (x - axis) gives
+// dv/dalpha = dphi/dt e_z x dx/dalpha.
+fsi_status fsi_plate_pose_dalpha(int32_t nv, const double* s, const double* c, double t, double alpha, double omega,
+                                 double t_ramp, int32_t law, double* dxda, double* dvda) {
+  if (nv < 0 || (nv > 0 && (!s || !c || !dxda || !dvda))) return FSI_EINVAL;
+  double ph[2];
+  const double axis0[3] = {0.0, 0.0, 0.0};
+  std::vector<double> xs(3 * (size_t)std::max(nv, 1)), vs(3 * (size_t)std::max(nv, 1));
+  const fsi_status st = fsi_plate_pose(nv, s, c, t, alpha, omega, t_ramp, law, axis0, xs.data(), vs.data(), ph);
+  if (st != FSI_OK) return st;
+  const double cp = cos(ph[0]), sp = sin(ph[0]), ca = cos(alpha), sa = sin(alpha);
+  for (int32_t i = 0; i < nv; ++i) {
+    const double ly = -c[i] * sa, lz = c[i] * ca;
+    const double rx = -sp * ly, ry = cp * ly;
+    dxda[3 * i] = rx;
+    dxda[3 * i + 1] = ry;
+    dxda[3 * i + 2] = lz;
+    dvda[3 * i] = -ph[1] * ry;
+    dvda[3 * i + 1] = ph[1] * rx;
+    dvda[3 * i + 2] = 0.0;
   }
   return FSI_OK;
 }

@@ -20,6 +20,7 @@ class EngineBase {
   virtual fsi_status set_spectrum(const double* uh) = 0;
   virtual fsi_status get_velocity(double* u) = 0;
   virtual fsi_status get_spectrum(double* uh) = 0;
+  virtual fsi_status get_nonlinear(double* nh) = 0;
   virtual fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) = 0;
   virtual fsi_status get_mask(double* chi, double* us) = 0;
   virtual fsi_status step(bool adaptive, double dt, double cfl, double c_eta, double dt_max) = 0;
@@ -29,6 +30,10 @@ class EngineBase {
   virtual fsi_status save_state(int slot) = 0;
   virtual fsi_status load_state(int slot) = 0;
   virtual fsi_status synchronize() = 0;
+  virtual fsi_status adjoint_set(const double* lu, const double* lnp) = 0;
+  virtual fsi_status adjoint_get(double* lu, double* lnp) = 0;
+  virtual fsi_status step_adjoint(int slot, double dt, double dtp, int first, const double dJdF[3], double* dJdx,
+                                  double* dJdv) = 0;
   virtual fsi_status set_timing(bool on) = 0;
   virtual fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) = 0;
   std::string err;

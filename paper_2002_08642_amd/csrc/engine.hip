@@ -216,6 +216,14 @@ class Engine : public EngineBase {
     return nan_status();
   }
 
+  fsi_status get_nonlinear(double* out) override {
+    std::vector<cpx<T>> h(3 * clen);
+    FSI_HIP(hipMemcpyAsync(h.data(), nh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < 3; ++q) unpad(h.data() + q * clen, out + 2 * q * clen_ext);
+    return nan_status();
+  }
+
   // -- wing --------------------------------------------------------------------
   fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) override {
     if (nt < 0 || nv < 0 || (nt > 0 && (nv < 3 || !x || !v || !tri))) {
@@ -273,6 +281,7 @@ class Engine : public EngineBase {
     memcpy(sx, x, sizeof(double) * 3 * (size_t)nv);
     memcpy(sv, v, sizeof(double) * 3 * (size_t)nv);
     memcpy(st, tri, sizeof(int) * 3 * (size_t)nt);
+    tri_host.assign(tri, tri + 3 * (size_t)nt);
     if (nv > mesh_vcap || nt > mesh_tcap) {
       FSI_HIP(hipStreamSynchronize(s));
       free_dev(dx_);
@@ -539,6 +548,232 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // -- adjoint of one step (dt held fixed) -----------------------------------------
+  fsi_status ensure_adjoint() {
+    if (!lu_) {
+      FSI_TRY(alloc(&lu_, 3 * clen));
+      FSI_TRY(alloc(&lnp_, 3 * clen));
+      FSI_TRY(alloc(&mu_, 3 * clen));
+      FSI_TRY(alloc(&A9, 9 * Alen));
+      FSI_TRY(alloc(&B9, 9 * Blen));
+      FSI_HIP(hipMemsetAsync(lu_, 0, sizeof(cpx<T>) * 3 * clen, s));
+      FSI_HIP(hipMemsetAsync(lnp_, 0, sizeof(cpx<T>) * 3 * clen, s));
+      FSI_HIP(hipMemsetAsync(mu_, 0, sizeof(cpx<T>) * 3 * clen, s));
+    }
+    return FSI_OK;
+  }
+
+  fsi_status adjoint_set(const double* lu, const double* lnp) override {
+    FSI_TRY(ensure_adjoint());
+    std::vector<cpx<T>> h(3 * clen);
+    for (int which = 0; which < 2; ++which) {
+      const double* src = which == 0 ? lu : lnp;
+      memset(h.data(), 0, sizeof(cpx<T>) * 3 * clen);
+      if (src)
+        for (int q = 0; q < 3; ++q) pad(src + 2 * q * clen_ext, h.data() + q * clen);
+      FSI_HIP(hipMemcpyAsync(which == 0 ? lu_ : lnp_, h.data(), sizeof(cpx<T>) * 3 * clen, hipMemcpyHostToDevice, s));
+      FSI_HIP(hipStreamSynchronize(s));
+    }
+    return FSI_OK;
+  }
+
+  fsi_status adjoint_get(double* lu, double* lnp) override {
+    FSI_TRY(ensure_adjoint());
+    std::vector<cpx<T>> h(3 * clen);
+    for (int which = 0; which < 2; ++which) {
+      double* dst = which == 0 ? lu : lnp;
+      if (!dst) continue;
+      FSI_HIP(hipMemcpyAsync(h.data(), which == 0 ? lu_ : lnp_, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToHost, s));
+      FSI_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < 3; ++q) unpad(h.data() + q * clen, dst + 2 * q * clen_ext);
+    }
+    return FSI_OK;
+  }
+
+  fsi_status step_adjoint(int slot, double dt, double dtp, int first, const double dJdF[3], double* dJdx,
+                          double* dJdv) override {
+    if (slot < 0 || slot >= (int)slots.size() || !slots[slot].used) {
+      err = "tape slot is empty";
+      return FSI_ESTATE;
+    }
+    if (!(dt > 0) || (!first && !(dtp > 0))) {
+      err = "dt and (unless first) dt_prev must be positive";
+      return FSI_EINVAL;
+    }
+    if (!xadj_supported<T>(nx)) {
+      err = "nx too long for the adjoint x pass in this precision";
+      return FSI_EINVAL;
+    }
+    FSI_TRY(ensure_adjoint());
+    const bool wing = wing_nt > 0 && bcells > 0;
+    if (wing) {
+      if (adj_box_cap < box_cap) {
+        FSI_HIP(hipStreamSynchronize(s));
+        free_dev(lchi_);
+        free_dev(lus_);
+        adj_box_cap = box_cap;
+        FSI_TRY(alloc(&lchi_, adj_box_cap));
+        FSI_TRY(alloc(&lus_, 3 * adj_box_cap));
+      }
+      if (tgrad_cap < wing_nt) {
+        FSI_HIP(hipStreamSynchronize(s));
+        free_dev(tgrad_);
+        tgrad_cap = wing_nt;
+        FSI_TRY(alloc(&tgrad_, 18LL * tgrad_cap));
+      }
+      FSI_TRY(run_mask());
+    }
+    // update transpose and projection: mu = P(lambda_N) / (m_k N^3)
+    {
+      AdjSpecArgs<T> a;
+      memset(&a, 0, sizeof(a));
+      a.lu = lu_;
+      a.lnp = lnp_;
+      a.mu = mu_;
+      a.cfs = clen;
+      a.nrows = nbz * nby;
+      a.nby = nby;
+      a.kx1 = kx1;
+      a.kxp = kxp;
+      a.Ky = Ky;
+      a.Kz = Kz;
+      a.kfx = (T)(2.0 * M_PI / d.lx);
+      a.kfy = (T)(2.0 * M_PI / d.ly);
+      a.kfz = (T)(2.0 * M_PI / d.lz);
+      a.nu = (T)d.nu;
+      a.dt = dt;
+      a.dtp = first ? dt : dtp;
+      a.first = first ? 1 : 0;
+      a.invN3 = 1.0 / (double)npts;
+      FSI_HIP(launch_adj_spectral<T>(a, s));
+    }
+    // inverse transforms: u, omega of the taped state and lambda_G = C2R(mu)
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = slots[slot].uh;
+      a.in_fs = clen;
+      a.out = A9;
+      a.out_fs = Alen;
+      FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
+      a.in = mu_;
+      a.out = A9 + 6 * Alen;
+      a.nf = 3;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = A9;
+      a.in_fs = Alen;
+      a.in_bs = C1;
+      a.out = B9;
+      a.out_fs = Blen;
+      a.out_bs = (long long)ny * kxp;
+      a.nf = 9;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
+    }
+    {
+      XAdjArgs<T> a;
+      memset(&a, 0, sizeof(a));
+      a.spec = B9;
+      a.sfs = Blen;
+      a.ld = kxp;
+      a.nlines = ny * nz;
+      a.ny = ny;
+      a.n = nx;
+      a.kx1 = kx1;
+      a.plan = px;
+      a.tw = twx;
+      if (wing) {
+        a.chi = chi;
+        a.us = us;
+        a.lchi = lchi_;
+        a.lus = lus_;
+        a.bx0 = bx0;
+        a.by0 = by0;
+        a.bz0 = bz0;
+        a.bnx = bnx;
+        a.bny = bny;
+        a.bnz = bnz;
+        a.bcells = bcells;
+      }
+      a.inv_eta = (T)(1.0 / d.eta);
+      a.g0 = (T)(dV * dJdF[0]);
+      a.g1 = (T)(dV * dJdF[1]);
+      a.g2 = (T)(dV * dJdF[2]);
+      const int grid = (int)std::max(1LL, std::min(((long long)ny * nz) / 2, 4096LL));
+      FSI_HIP(launch_xadj<T>(a, grid, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = B9;
+      a.in_fs = Blen;
+      a.in_bs = (long long)ny * kxp;
+      a.out = A9;
+      a.out_fs = Alen;
+      a.out_bs = C1;
+      a.nf = 6;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    {
+      // C2R^T = N^3 m_k R2C_normalized = m_k R2C_unnormalized
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = A9;
+      a.in_fs = Alen;
+      a.out = lu_;
+      a.cfs = clen;
+      a.nf = 3;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_ACC, a, 1, s));
+      a.in = A9 + 3 * Alen;
+      FSI_HIP(launch_col<T>(COL_FWD_ACC_CURL, a, 1, s));
+    }
+    if (dJdx) memset(dJdx, 0, sizeof(double) * 3 * wing_nv);
+    if (dJdv) memset(dJdv, 0, sizeof(double) * 3 * wing_nv);
+    if (wing) {
+      MaskAdjArgs<T> m;
+      memset(&m, 0, sizeof(m));
+      m.x = dx_;
+      m.v = dv_;
+      m.tri = dtri_;
+      m.nt = wing_nt;
+      m.key2 = key2;
+      m.chi = chi;
+      m.lchi = lchi_;
+      m.lus = lus_;
+      m.bx0 = bx0;
+      m.by0 = by0;
+      m.bz0 = bz0;
+      m.bnx = bnx;
+      m.bny = bny;
+      m.bnz = bnz;
+      m.bcells = bcells;
+      m.dx = dxs[0];
+      m.dy = dxs[1];
+      m.dz = dxs[2];
+      m.rsup = rsup;
+      m.tw = d.tw;
+      m.h = d.h;
+      m.profile = d.mask_profile;
+      m.tgrad = tgrad_;
+      FSI_HIP(launch_mask_adj<T>(m, s));
+      std::vector<double> tg(18LL * wing_nt);
+      FSI_HIP(hipMemcpyAsync(tg.data(), tgrad_, sizeof(double) * 18 * wing_nt, hipMemcpyDeviceToHost, s));
+      FSI_HIP(hipStreamSynchronize(s));
+      for (int t = 0; t < wing_nt; ++t)
+        for (int j = 0; j < 3; ++j) {
+          const int vtx = tri_host[3 * t + j];
+          for (int c = 0; c < 3; ++c) {
+            if (dJdx) dJdx[3 * vtx + c] += tg[18LL * t + 3 * j + c];
+            if (dJdv) dJdv[3 * vtx + c] += tg[18LL * t + 9 + 3 * j + c];
+          }
+        }
+    } else {
+      FSI_HIP(hipStreamSynchronize(s));
+    }
+    return FSI_OK;
+  }
+
   fsi_status synchronize() override {
     FSI_HIP(hipStreamSynchronize(s));
     return FSI_OK;
@@ -612,6 +847,14 @@ class Engine : public EngineBase {
     free_dev(dtri_);
     free_dev(key1);
     free_dev(key2);
+    free_dev(lu_);
+    free_dev(lnp_);
+    free_dev(mu_);
+    free_dev(A9);
+    free_dev(B9);
+    free_dev(lchi_);
+    free_dev(lus_);
+    free_dev(tgrad_);
     free_dev(chi);
     free_dev(us);
     for (Slot& sl : slots) {
@@ -891,6 +1134,13 @@ class Engine : public EngineBase {
   int bx0 = 0, by0 = 0, bz0 = 0, bnx = 0, bny = 0, bnz = 0;
   long long bcells = 0, box_cap = 0;
   unsigned long long *key1 = nullptr, *key2 = nullptr;
+  std::vector<int> tri_host;
+  // adjoint state and work buffers (allocated on first use)
+  cpx<T>*lu_ = nullptr, *lnp_ = nullptr, *mu_ = nullptr, *A9 = nullptr, *B9 = nullptr;
+  T *lchi_ = nullptr, *lus_ = nullptr;
+  long long adj_box_cap = 0;
+  double* tgrad_ = nullptr;
+  int tgrad_cap = 0;
   T *chi = nullptr, *us = nullptr;
   // stepping
   long long nstep = 0;

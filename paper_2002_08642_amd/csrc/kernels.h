@@ -18,7 +18,15 @@ namespace fsi {
 
 constexpr int kNT = 256;  // threads per workgroup of the mask and reduction kernels
 
-enum ColMode { COL_INV_PLAIN = 0, COL_INV_CURL = 1, COL_FWD_PLAIN = 2, COL_FWD_PROJECT = 3, COL_FWD_UPDATE = 4 };
+enum ColMode {
+  COL_INV_PLAIN = 0,
+  COL_INV_CURL = 1,
+  COL_FWD_PLAIN = 2,
+  COL_FWD_PROJECT = 3,
+  COL_FWD_UPDATE = 4,
+  COL_FWD_ACC = 5,       // adjoint: out[f] += m_k * forward(in[f])   (m_k = 1 at kx = 0, else 2)
+  COL_FWD_ACC_CURL = 6   // adjoint: out += m_k * (i k x forward(in[0..2]))
+};
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 
 // Device scalars shared by the passes of one step.
@@ -98,6 +106,73 @@ struct MaskArgs {
   double rsup;         // support radius
   double tw, h;
   int profile;
+};
+
+// ---------------------------------------------------------------------------
+// adjoint of one step (dt held fixed)
+// ---------------------------------------------------------------------------
+
+// Spectral part of the reverse step, per compact mode: from the cotangents of
+// (u_hat^{n+1}, N_hat^n) it forms the cotangent of N_hat^n's forward transform
+// (projected and scaled for the transpose of the R2C transform), the update's
+// share of the cotangent of u_hat^n, and the cotangent of N_hat^{n-1}.
+template <typename T>
+struct AdjSpecArgs {
+  cpx<T>* lu;    // [3][cfs] cotangent of u_hat (in: step n+1, out: update share at step n)
+  cpx<T>* lnp;   // [3][cfs] cotangent of the previous nonlinear term (in / out)
+  cpx<T>* mu;    // [3][cfs] out: P(lambda_N) / (m_k N^3)
+  long long cfs;
+  int nrows;     // (2Kz+1)(2Ky+1)
+  int nby, kx1, kxp, Ky, Kz;
+  T kfx, kfy, kfz;
+  T nu;
+  double dt, dtp;
+  int first;
+  double invN3;
+};
+
+// Fused x pass of the reverse step: C2R of u, omega and lambda_G (9 fields),
+// lambda_u = omega x lambda_G - (chi/eta) lambda_G + (dV/eta) chi g,
+// lambda_omega = lambda_G x u, and the mask cotangents
+// lambda_chi = (g dV - lambda_G).(u - u_s)/eta, lambda_us = chi (lambda_G - g dV)/eta;
+// R2C of lambda_u, lambda_omega (6 fields).
+template <typename T>
+struct XAdjArgs {
+  cpx<T>* spec;  // [9][line][ld] in, [6][line][ld] out
+  long long sfs;
+  int ld;
+  int nlines, ny, n, kx1;
+  FftPlan plan;
+  const cpx<T>* tw;
+  const T* chi;
+  const T* us;
+  T* lchi;       // [cell] out
+  T* lus;        // [3][cell] out
+  int bx0, by0, bz0, bnx, bny, bnz;
+  long long bcells;
+  T inv_eta;
+  T g0, g1, g2;  // dV * dJ/dF
+};
+
+// Mask adjoint: per triangle, sums over the cells it wins of the cotangents of
+// its vertex positions and velocities (through the distance, the profile and
+// the barycentric weights of the closest point).
+template <typename T>
+struct MaskAdjArgs {
+  const double* x;
+  const double* v;
+  const int* tri;
+  int nt;
+  const unsigned long long* key2;
+  const T* chi;
+  const T* lchi;
+  const T* lus;
+  int bx0, by0, bz0, bnx, bny, bnz;
+  long long bcells;
+  double dx, dy, dz;
+  double rsup, tw, h;
+  int profile;
+  double* tgrad;  // [nt][18]: d/dx of (a, b, c), then d/dv of (a, b, c)
 };
 
 struct FinalArgs {

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 
+#include "device_util.h"
 #include "kernels.h"
 #include "launch.h"
 
@@ -18,60 +19,6 @@ namespace fsi {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int band_to_row(int i, int K, int n) { return i <= K ? i : i + n - 2 * K - 1; }
-__device__ __forceinline__ int band_mode(int i, int K) { return i <= K ? i : i - 2 * K - 1; }
-
-template <typename T>
-__device__ __forceinline__ T dev_exp(T a);
-template <>
-__device__ __forceinline__ float dev_exp<float>(float a) { return expf(a); }
-template <>
-__device__ __forceinline__ double dev_exp<double>(double a) { return exp(a); }
-
-template <typename T>
-__device__ __forceinline__ T dev_sqrt(T a);
-template <>
-__device__ __forceinline__ float dev_sqrt<float>(float a) { return sqrtf(a); }
-template <>
-__device__ __forceinline__ double dev_sqrt<double>(double a) { return sqrt(a); }
-
-// Fixed-order workgroup sum of NV doubles; result valid in thread 0.
-template <int NV, int NT>
-__device__ void block_sum(double (&v)[NV], double* red /* [NV][NT/64] */) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[i * (NT / 64) + wave] = v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < NT / 64; ++w) s += red[i * (NT / 64) + w];
-      v[i] = s;
-    }
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ double block_max(double v, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[w]);
-  }
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // column passes: FFT along the slow axis of a [rows][C] slice, W columns per WG
@@ -183,7 +130,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
     }
   } else {
     // forward modes: all n rows in, band rows out
-    const int nfield = (MODE == COL_FWD_PLAIN) ? a.nf : 3;
+    const int nfield = (MODE == COL_FWD_PLAIN || MODE == COL_FWD_ACC) ? a.nf : 3;
     cpx<T> st[2][MAXO];
     for (int f = 0; f < nfield; ++f) {
       const int tid = opaque((int)threadIdx.x);
@@ -212,6 +159,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
           }
         }
         __syncthreads();
+      } else if (MODE == COL_FWD_ACC) {
+        cpx<T>* out = a.out + f * a.cfs;
+        const T m = a.scale * (T)((c % a.kxp) == 0 ? 1 : 2);
+        if (cok) {
+#pragma unroll
+          for (int k = 0; k < MAXO; ++k) {
+            const int i = r0 + k * RSTEP;
+            if (i < nb) {
+              const long long idx = (long long)i * a.ld + c;
+              out[idx] = out[idx] + scl(buf[band_to_row(i, K, n) * W + col], m);
+            }
+          }
+        }
+        __syncthreads();
       } else if (f < 2) {
 #pragma unroll
         for (int k = 0; k < MAXO; ++k) {
@@ -224,6 +185,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
           }
         }
         __syncthreads();
+      }
+    }
+    if constexpr (MODE == COL_FWD_ACC_CURL) {
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+      const T m = (T)(ix == 0 ? 1 : 2);  // a.scale is already in st and in v2 below
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (cok && i < nb) {
+          const T kz = a.kfz * (T)band_mode(i, K);
+          const cpx<T> v0 = st[0][k], v1 = st[1][k];
+          const cpx<T> v2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          const cpx<T> t0 = scl(v2, ky) - scl(v1, kz);  // (i k x v) = i t
+          const cpx<T> t1 = scl(v0, kz) - scl(v2, kx);
+          const cpx<T> t2 = scl(v1, kx) - scl(v0, ky);
+          const long long idx = (long long)i * a.ld + c;
+          a.out[idx] = a.out[idx] + scl(mk<T>(-t0.im, t0.re), m);
+          a.out[a.cfs + idx] = a.out[a.cfs + idx] + scl(mk<T>(-t1.im, t1.re), m);
+          a.out[2 * a.cfs + idx] = a.out[2 * a.cfs + idx] + scl(mk<T>(-t2.im, t2.re), m);
+        }
       }
     }
     if constexpr (MODE == COL_FWD_PROJECT || MODE == COL_FWD_UPDATE) {
@@ -298,11 +281,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
 //
 // LDS holds n rows of packed signals with a padded row stride (odd number of
 // complex values against bank conflicts), then the twiddle table.
-
-template <int W>
-struct PadStride {
-  static constexpr int value = (W % 2 == 0) ? W + 1 : W;
-};
 
 // Fused pass: C2R of (u, omega) for L lines, G = u x omega - (chi/eta)(u - u_s),
 // partial sums of the diagnostics, R2C of G truncated to the x band.
@@ -832,82 +810,6 @@ __global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
 // mask: distance keys per triangle, then chi and u_s per cell
 // ---------------------------------------------------------------------------
 
-// Closest point of triangle (a, b, c) to p by Voronoi-region classification
-// (vertex, edge or face region).  Coordinates are relative to a.  Returns the
-// squared distance and the barycentric weights (wa, wb, wc).
-template <typename T>
-__device__ __forceinline__ T closest_on_triangle(T px, T py, T pz, T bx, T by, T bz, T cx, T cy, T cz, T& wa, T& wb,
-                                                 T& wc) {
-  // p, b, c are relative to vertex a
-  const T d1 = bx * px + by * py + bz * pz;
-  const T d2 = cx * px + cy * py + cz * pz;
-  T qx, qy, qz;
-  if (d1 <= (T)0 && d2 <= (T)0) {
-    wa = 1; wb = 0; wc = 0;
-    qx = 0; qy = 0; qz = 0;
-  } else {
-    const T bpx = px - bx, bpy = py - by, bpz = pz - bz;
-    const T d3 = bx * bpx + by * bpy + bz * bpz;
-    const T d4 = cx * bpx + cy * bpy + cz * bpz;
-    const T cpx_ = px - cx, cpy = py - cy, cpz = pz - cz;
-    const T d5 = bx * cpx_ + by * cpy + bz * cpz;
-    const T d6 = cx * cpx_ + cy * cpy + cz * cpz;
-    const T vc = d1 * d4 - d3 * d2;
-    const T vb = d5 * d2 - d1 * d6;
-    const T va = d3 * d6 - d5 * d4;
-    if (d3 >= (T)0 && d4 <= d3) {
-      wa = 0; wb = 1; wc = 0;
-      qx = bx; qy = by; qz = bz;
-    } else if (vc <= (T)0 && d1 >= (T)0 && d3 <= (T)0) {
-      const T t = d1 / (d1 - d3);
-      wa = 1 - t; wb = t; wc = 0;
-      qx = t * bx; qy = t * by; qz = t * bz;
-    } else if (d6 >= (T)0 && d5 <= d6) {
-      wa = 0; wb = 0; wc = 1;
-      qx = cx; qy = cy; qz = cz;
-    } else if (vb <= (T)0 && d2 >= (T)0 && d6 <= (T)0) {
-      const T t = d2 / (d2 - d6);
-      wa = 1 - t; wb = 0; wc = t;
-      qx = t * cx; qy = t * cy; qz = t * cz;
-    } else if (va <= (T)0 && (d4 - d3) >= (T)0 && (d5 - d6) >= (T)0) {
-      const T t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-      wa = 0; wb = 1 - t; wc = t;
-      qx = bx + t * (cx - bx); qy = by + t * (cy - by); qz = bz + t * (cz - bz);
-    } else {
-      const T den = va + vb + vc;
-      if (den > (T)0) {
-        const T vv = vb / den, ww = vc / den;
-        wa = 1 - vv - ww; wb = vv; wc = ww;
-        qx = vv * bx + ww * cx; qy = vv * by + ww * cy; qz = vv * bz + ww * cz;
-      } else {
-        // degenerate triangle: nearest of the three edges
-        T best = (T)INFINITY;
-        wa = 1; wb = 0; wc = 0;
-        qx = 0; qy = 0; qz = 0;
-        const T ex[3][6] = {{0, 0, 0, bx, by, bz}, {bx, by, bz, cx, cy, cz}, {cx, cy, cz, 0, 0, 0}};
-        for (int e = 0; e < 3; ++e) {
-          const T ax_ = ex[e][0], ay_ = ex[e][1], az_ = ex[e][2];
-          const T sx = ex[e][3] - ax_, sy = ex[e][4] - ay_, sz = ex[e][5] - az_;
-          const T ss = sx * sx + sy * sy + sz * sz;
-          T t = ss > (T)0 ? ((px - ax_) * sx + (py - ay_) * sy + (pz - az_) * sz) / ss : (T)0;
-          t = t < (T)0 ? (T)0 : (t > (T)1 ? (T)1 : t);
-          const T hx = ax_ + t * sx - px, hy = ay_ + t * sy - py, hz = az_ + t * sz - pz;
-          const T dd = hx * hx + hy * hy + hz * hz;
-          if (dd < best) {
-            best = dd;
-            qx = ax_ + t * sx; qy = ay_ + t * sy; qz = az_ + t * sz;
-            if (e == 0) { wa = 1 - t; wb = t; wc = 0; }
-            else if (e == 1) { wa = 0; wb = 1 - t; wc = t; }
-            else { wa = t; wb = 0; wc = 1 - t; }
-          }
-        }
-      }
-    }
-  }
-  const T hx = px - qx, hy = py - qy, hz = pz - qz;
-  return hx * hx + hy * hy + hz * hz;
-}
-
 __global__ void fill_keys(unsigned long long* k1, unsigned long long* k2, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     k1[i] = ~0ull;
@@ -960,15 +862,6 @@ __global__ __launch_bounds__(kNT) void mask_dist(MaskArgs<T> a) {
       }
     }
   }
-}
-
-__device__ __forceinline__ double profile_chi(double d, double tw, double h, int profile) {
-  if (profile == 0) {
-    if (d <= tw - h) return 1.0;
-    if (d >= tw + h) return 0.0;
-    return 0.5 * (1.0 + cos(3.14159265358979323846 * (d - tw + h) / (2.0 * h)));
-  }
-  return 0.5 * (1.0 - tanh((d - tw) / h));
 }
 
 template <typename T>
@@ -1032,6 +925,8 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
     FSI_COL_CASE(COL_FWD_PLAIN)
     FSI_COL_CASE(COL_FWD_PROJECT)
     FSI_COL_CASE(COL_FWD_UPDATE)
+    FSI_COL_CASE(COL_FWD_ACC)
+    FSI_COL_CASE(COL_FWD_ACC_CURL)
     default: return hipErrorInvalidValue;
   }
 #undef FSI_COL_CASE

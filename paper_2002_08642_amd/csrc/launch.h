@@ -58,4 +58,13 @@ int xfused_grid(int n, long long nlines, int lines_per_group);
 template <typename T>
 hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
 
+template <typename T>
+hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_xadj(const XAdjArgs<T>& a, int grid, hipStream_t s);
+template <typename T>
+int xadj_supported(int n);
+template <typename T>
+hipError_t launch_mask_adj(const MaskAdjArgs<T>& a, hipStream_t s);
+
 }  // namespace fsi

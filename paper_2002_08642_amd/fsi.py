@@ -31,7 +31,8 @@ EXPORTS = [
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
     "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
-    "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose",
+    "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
+    "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
 ]
 
 
@@ -92,6 +93,12 @@ def load_library():
     lib.fsi_get_pass_times.argtypes = [P, D, ctypes.POINTER(I32)]
     lib.fsi_plate_pose.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, I32, D, D, D, D]
+    lib.fsi_get_nonlinear.argtypes = [P, D]
+    lib.fsi_adjoint_set.argtypes = [P, D, D]
+    lib.fsi_adjoint_get.argtypes = [P, D, D]
+    lib.fsi_step_adjoint.argtypes = [P, I32, ctypes.c_double, ctypes.c_double, I32, D, D, D]
+    lib.fsi_plate_pose_dalpha.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, I32, D, D]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
             "fsi_last_error", "fsi_create_error", "fsi_version") else ctypes.c_int32
@@ -125,6 +132,20 @@ def plate_pose(s, c, t, alpha, omega, t_ramp, axis, law=0):
     if rc != FSI_OK:
         raise FsiError(rc, "fsi_plate_pose")
     return x, v, ph
+
+
+def plate_pose_dalpha(s, c, t, alpha, omega, t_ramp, law=0):
+    """Derivatives of the rigid plate pose with respect to the pitch (fsi_plate_pose_dalpha)."""
+    lib = load_library()
+    s = _f64(s)
+    c = _f64(c)
+    nv = s.shape[0]
+    dx = np.zeros((nv, 3))
+    dv = np.zeros((nv, 3))
+    rc = lib.fsi_plate_pose_dalpha(nv, _dptr(s), _dptr(c), t, alpha, omega, t_ramp, law, _dptr(dx), _dptr(dv))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_plate_pose_dalpha")
+    return dx, dv
 
 
 class Solver:
@@ -194,6 +215,38 @@ class Solver:
         self._check(self.lib.fsi_get_spectrum(self.ctx, _dptr(out)))
         return out[..., 0] + 1j * out[..., 1]
 
+    def nonlinear(self):
+        out = np.zeros((3,) + self.compact_shape + (2,))
+        self._check(self.lib.fsi_get_nonlinear(self.ctx, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def _cbuf(self, a):
+        if a is None:
+            return None
+        a = np.asarray(a, dtype=np.complex128).reshape((3,) + self.compact_shape)
+        return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
+
+    def adjoint_set(self, lam_u=None, lam_n=None):
+        bu, bn = self._cbuf(lam_u), self._cbuf(lam_n)
+        self._check(self.lib.fsi_adjoint_set(self.ctx, None if bu is None else _dptr(bu),
+                                             None if bn is None else _dptr(bn)))
+
+    def adjoint_get(self):
+        bu = np.zeros((3,) + self.compact_shape + (2,))
+        bn = np.zeros((3,) + self.compact_shape + (2,))
+        self._check(self.lib.fsi_adjoint_get(self.ctx, _dptr(bu), _dptr(bn)))
+        return bu[..., 0] + 1j * bu[..., 1], bn[..., 0] + 1j * bn[..., 1]
+
+    def step_adjoint(self, slot, dt, dt_prev, first, dJdF):
+        """Reverse one step (fsi_step_adjoint); returns dJ/dx, dJ/dv of the current wing's vertices."""
+        g = _f64(dJdF, (3,))
+        nv = getattr(self, "_nv", 0)
+        dx = np.zeros((max(nv, 1), 3))
+        dv = np.zeros((max(nv, 1), 3))
+        self._check(self.lib.fsi_step_adjoint(self.ctx, int(slot), float(dt), float(dt_prev), int(first), _dptr(g),
+                                              _dptr(dx), _dptr(dv)))
+        return dx[:nv], dv[:nv]
+
     def set_wing(self, x, v, tri):
         x = _f64(x)
         v = _f64(v)
@@ -202,9 +255,11 @@ class Solver:
         nt = tri.shape[0] if tri.ndim == 2 else 0
         self._check(self.lib.fsi_set_wing(self.ctx, nv, _dptr(x), _dptr(v), nt,
                                           tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self._nv = nv if nt > 0 else 0
 
     def clear_wing(self):
         self._check(self.lib.fsi_set_wing(self.ctx, 0, None, None, 0, None))
+        self._nv = 0
 
     def mask(self):
         chi = np.zeros(self.shape3)
