@@ -68,7 +68,7 @@ def step_model_bytes(n, wsize):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_lds.h", "kernels.h", "launch.h", "engine.hip"):
+    for f in ("kernels.hip", "fft_lds.h", "wave512.h", "device_util.h", "kernels.h", "launch.h", "engine.hip"):
         with open(os.path.join(ROOT, "paper_2002_08642_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -105,6 +105,49 @@ def run_gpu(n, prec, steps, warmup, timing):
     s.set_timing(False)
     per_pass = {k: v / max(nrec, 1) for k, v in passes.items()}
     return el / steps, per_pass, info
+
+
+def run_adjoint(n, prec, K):
+    """Cost of the checkpointed adjoint relative to the forward step.
+
+    One segment of K fixed-dt steps (dt = C_eta eta, the cap that binds on
+    this workload) of the revolving plate in the k^-5/3 field: the forward
+    steps (pose, mesh upload, mask, step, force read-back; checkpoint saved)
+    against the reverse of the same segment (reload, K recomputed steps with
+    tape saves, K adjoint steps with the host pose derivative).  Both legs are
+    timed after one untimed rollout that allocates the tape and the adjoint
+    buffers."""
+    from paper_2002_08642_amd import fsi
+    from paper_2002_08642_amd.rollout import PlateRollout
+    import synth
+    cfg = workload(n)
+    s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
+    dt = cfg["c_eta"] * cfg["eta"]
+    ro = PlateRollout(s, cfg, [dt] * K, K=K, uh0=synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0))
+    a = cfg["alpha"]
+    ro.forward(a)
+    ro.backward(a)
+    ro._reset()
+    s.synchronize()
+    sync_torch()
+    t0 = time.perf_counter()
+    for k in range(K):
+        if k == 0:
+            s.save(0)
+        ro._step(k, a)
+    s.synchronize()
+    tf = time.perf_counter() - t0
+    s.adjoint_set(None, None)
+    t0 = time.perf_counter()
+    g = ro.reverse_segment(0, a)
+    s.synchronize()
+    tb = time.perf_counter() - t0
+    return {"grid": [n, n, n], "segment_steps": K, "dt": dt,
+            "forward_ms_per_step": round(tf / K * 1e3, 4),
+            "backward_ms_per_step": round(tb / K * 1e3, 4),
+            "ratio": round(tb / tf, 3),
+            "dJ_dalpha_segment": g,
+            "note": "backward = reload + K recomputed steps with tape saves + K adjoint steps"}
 
 
 _torch = None
@@ -191,6 +234,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-k", type=int, default=10,
+                    help="steps in the timed adjoint segment (0 skips the adjoint/forward leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--no-torch", action="store_true",
@@ -212,6 +257,8 @@ def main():
     ms64, pass64, _ = (None, {}, None)
     if args.fp64_steps > 0:
         ms64, pass64, _ = run_gpu(n, fsi.PREC_FP64, args.fp64_steps, 2, True)
+
+    adj = run_adjoint(n, fsi.PREC_FP32, args.adjoint_k) if args.adjoint_k > 0 else None
 
     dominant = max(pass32, key=pass32.get)
     cfg = workload(n)
@@ -271,6 +318,7 @@ def main():
             "step_roofline_frac": round(step_model_bytes(n, 8) / ms64 / 1e9 / HBM_PEAK_GBS, 4),
             "pass_ms": {k: round(v, 4) for k, v in pass64.items()},
         },
+        "adjoint": adj,
         "last_step": {"dt": info32["dt"], "umax": info32["umax"], "E": info32["E"],
                       "F": [float(f) for f in info32["F"]]},
         "cpu_baseline": None,

@@ -18,6 +18,7 @@
 #include "device_util.h"
 #include "kernels.h"
 #include "launch.h"
+#include "wave512.h"
 
 namespace fsi {
 
@@ -73,6 +74,15 @@ __global__ __launch_bounds__(256) void adj_spectral(AdjSpecArgs<T> a) {
 // fused x pass of the reverse step (two lines per workgroup, LDS transforms)
 // ---------------------------------------------------------------------------
 
+// Real signals of the inverse transforms, packed two per complex transform:
+// line 0 fields 0..8, then line 1 with its lambda_Gz first.  lambda_G is about
+// N^-1.5 of u and omega in size, and a complex transform of two real signals
+// rounds each at the scale of the larger one, so the lambda_G components only
+// share transforms with each other: (gx, gy), (gz, gz'), (gx', gy').
+__device__ __forceinline__ int adj_sig(int l, int q) { return l == 0 ? q : 9 + (q == 8 ? 0 : q + 1); }
+__device__ __forceinline__ int adj_sig_line(int r) { return r < 9 ? 0 : 1; }
+__device__ __forceinline__ int adj_sig_field(int r) { return r < 9 ? r : (r == 9 ? 8 : r - 10); }
+
 template <typename T, int NT, int MAXE>
 __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -92,13 +102,15 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int tid = opaque((int)threadIdx.x);
     const int line0 = g * L;
-    // 1) C2R of the 9 fields of both lines: real signal r = l * 9 + f, pairs (2j, 2j + 1)
+    // 1) C2R of the 9 fields of both lines: real signals in adj_sig order, pairs (2j, 2j + 1)
     for (int it = tid; it < SI * n; it += NT) {
       const int x = it % n, j = it / n;
       const int ra = 2 * j, rb = 2 * j + 1;
       if (x <= K) {
-        const cpx<T> A = a.spec[(ra % 9) * a.sfs + (long long)(line0 + ra / 9) * a.ld + x];
-        const cpx<T> B = a.spec[(rb % 9) * a.sfs + (long long)(line0 + rb / 9) * a.ld + x];
+        const cpx<T> A =
+            a.spec[adj_sig_field(ra) * a.sfs + (long long)(line0 + adj_sig_line(ra)) * a.ld + x];
+        const cpx<T> B =
+            a.spec[adj_sig_field(rb) * a.sfs + (long long)(line0 + adj_sig_line(rb)) * a.ld + x];
         if (x == 0) buf[j] = mk<T>(A.re, B.re);
         else {
           buf[x * RI + j] = mk<T>(A.re - B.im, A.im + B.re);
@@ -122,7 +134,7 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
         T f[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const int r = l * 9 + q;
+          const int r = adj_sig(l, q);
           f[q] = bufr[2 * (x * RI + (r >> 1)) + (r & 1)];
         }
         const T ux = f[0], uy = f[1], uz = f[2], wx = f[3], wy = f[4], wz = f[5];
@@ -186,6 +198,118 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
       a.spec[(r % 6) * a.sfs + (long long)(line0 + r / 6) * a.ld + k] = v;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused x pass of the reverse step for nx = 512: one wavefront per line pair,
+// register-resident transforms (wave512.h)
+// ---------------------------------------------------------------------------
+//
+// Per line the 9 inputs (u, omega, lambda_G) are 4 packed complex signals
+// (ux + i uy, uz + i wx, wy + i wz, gx + i gy); the lambda_Gz of the two lines
+// of the pair share one more.  The 6 outputs (lambda_u, lambda_omega) of a
+// line are 3 packed forward transforms.  Every line is read completely before
+// any of its outputs is stored, so the pass runs in place.
+
+template <typename T>
+__device__ __forceinline__ void xadj_load(const XAdjArgs<T>& a, int line, int f, int lane, Raw512<T>& w) {
+  load512<T>(a.spec + (long long)f * a.sfs + (long long)line * a.ld,
+             a.spec + (long long)(f + 1) * a.sfs + (long long)line * a.ld, lane, w);
+}
+
+// One line: inverse transforms of the 8 paired inputs (lambda_Gz given in the
+// physical layout), the transposed pointwise term, the sub-box cotangents of
+// chi and u_s, and the forward transforms of the 6 outputs.
+template <typename T>
+__device__ __forceinline__ void xadj_line(const XAdjArgs<T>& a, int line, int lane, cpx<T>* X, const cpx<T>* tIB,
+                                          const cpx<T>* tC, const cpx<T>* tFB, const T (&gzl)[8]) {
+  constexpr int K = 170;
+  cpx<T> P[4][8];
+  Raw512<T> w;
+  xadj_load<T>(a, line, 0, lane, w);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    cpx<T> v[8];
+    pack512<T>(w, lane, v);
+    if (p < 3) xadj_load<T>(a, line, 2 * p + 2, lane, w);  // in flight during the transform
+    inv512<T>(v, X, lane, tIB, tC);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) P[p][j] = v[j];
+  }
+  cpx<T> o[3][8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const T ux = P[0][j].re, uy = P[0][j].im, uz = P[1][j].re;
+    const T wx = P[1][j].im, wy = P[2][j].re, wz = P[2][j].im;
+    const T gx = P[3][j].re, gy = P[3][j].im, gz = gzl[j];
+    o[0][j] = mk<T>(wy * gz - wz * gy, wz * gx - wx * gz);  // omega x lambda_G
+    o[1][j] = mk<T>(wx * gy - wy * gx, gy * uz - gz * uy);  // ..., lambda_G x u
+    o[2][j] = mk<T>(gz * ux - gx * uz, gx * uy - gy * ux);
+  }
+  const int z = line / a.ny, y = line - z * a.ny;
+  const int by = y - a.by0, bz = z - a.bz0;
+  if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
+    const long long rowcell = ((long long)bz * a.bny + by) * a.bnx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int bx = (lane >> 3) + 8 * (lane & 7) + 64 * j - a.bx0;
+      if (bx >= 0 && bx < a.bnx) {
+        const long long cell = rowcell + bx;
+        const T ch = a.chi[cell];
+        const T sx = P[0][j].re - a.us[cell];
+        const T sy = P[0][j].im - a.us[a.bcells + cell];
+        const T sz = P[1][j].re - a.us[2 * a.bcells + cell];
+        // lambda_G and the force seed act on (u - u_s) through chi / eta
+        const T hx = (a.g0 - P[3][j].re) * a.inv_eta;
+        const T hy = (a.g1 - P[3][j].im) * a.inv_eta;
+        const T hz = (a.g2 - gzl[j]) * a.inv_eta;
+        o[0][j].re += ch * hx;
+        o[0][j].im += ch * hy;
+        o[1][j].re += ch * hz;
+        a.lchi[cell] = hx * sx + hy * sy + hz * sz;
+        a.lus[cell] = -ch * hx;
+        a.lus[a.bcells + cell] = -ch * hy;
+        a.lus[2 * a.bcells + cell] = -ch * hz;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    fwd512<T>(o[p], X, lane, tC, tFB);
+    unpack_store512<T>(o[p], lane, K, a.spec + (long long)(2 * p) * a.sfs + (long long)line * a.ld,
+                       a.spec + (long long)(2 * p + 1) * a.sfs + (long long)line * a.ld);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void xadj_wave512(XAdjArgs<T> a) {
+  __shared__ cpx<T> xbuf[4][kXBuf];
+  __shared__ cpx<T> tws[3][512];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cpx<T>* X = xbuf[wv];
+  wave512_twiddles<T, 256>(tws, a.tw);
+  __syncthreads();
+  const int npairs = a.nlines / 2;
+#pragma unroll 1
+  for (int pr = blockIdx.x * 4 + wv; pr < npairs; pr += gridDim.x * 4) {
+    const int l0 = opaque(lane);
+    // lambda_Gz of both lines as one packed signal
+    Raw512<T> w;
+    load512<T>(a.spec + 8 * a.sfs + (long long)(2 * pr) * a.ld, a.spec + 8 * a.sfs + (long long)(2 * pr + 1) * a.ld,
+               l0, w);
+    cpx<T> v[8];
+    pack512<T>(w, l0, v);
+    inv512<T>(v, X, l0, tws[0], tws[1]);
+    T gza[8], gzb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      gza[j] = v[j].re;
+      gzb[j] = v[j].im;
+    }
+    xadj_line<T>(a, 2 * pr, opaque(lane), X, tws[0], tws[1], tws[2], gza);
+    xadj_line<T>(a, 2 * pr + 1, opaque(lane), X, tws[0], tws[1], tws[2], gzb);
   }
 }
 
@@ -347,6 +471,10 @@ hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_xadj(const XAdjArgs<T>& a, int grid, hipStream_t s) {
+  if (a.n == 512 && a.nlines % 2 == 0) {
+    hipLaunchKernelGGL(xadj_wave512<T>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   constexpr int NT = XAdjCfg<T>::NT, M = XAdjCfg<T>::MAXE;
   const size_t lds = (size_t)a.n * (PadStride<9>::value + 1) * sizeof(cpx<T>);
   if (lds > 65536) {

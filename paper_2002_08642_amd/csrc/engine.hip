@@ -565,15 +565,20 @@ class Engine : public EngineBase {
 
   fsi_status adjoint_set(const double* lu, const double* lnp) override {
     FSI_TRY(ensure_adjoint());
-    std::vector<cpx<T>> h(3 * clen);
+    std::vector<cpx<T>> h;
     for (int which = 0; which < 2; ++which) {
       const double* src = which == 0 ? lu : lnp;
-      memset(h.data(), 0, sizeof(cpx<T>) * 3 * clen);
-      if (src)
-        for (int q = 0; q < 3; ++q) pad(src + 2 * q * clen_ext, h.data() + q * clen);
-      FSI_HIP(hipMemcpyAsync(which == 0 ? lu_ : lnp_, h.data(), sizeof(cpx<T>) * 3 * clen, hipMemcpyHostToDevice, s));
+      cpx<T>* dst = which == 0 ? lu_ : lnp_;
+      if (!src) {  // a null cotangent is zero: clear on the device
+        FSI_HIP(hipMemsetAsync(dst, 0, sizeof(cpx<T>) * 3 * clen, s));
+        continue;
+      }
+      h.assign(3 * clen, cpx<T>{});
+      for (int q = 0; q < 3; ++q) pad(src + 2 * q * clen_ext, h.data() + q * clen);
+      FSI_HIP(hipMemcpyAsync(dst, h.data(), sizeof(cpx<T>) * 3 * clen, hipMemcpyHostToDevice, s));
       FSI_HIP(hipStreamSynchronize(s));
     }
+    FSI_HIP(hipStreamSynchronize(s));
     return FSI_OK;
   }
 

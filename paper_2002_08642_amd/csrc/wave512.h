@@ -1,0 +1,153 @@
+// wave512.h - 512-point complex FFTs held by one wavefront (gfx950, wave64).
+//
+// A 512-point transform is held by one wavefront, 8 values per lane.  With
+// k = l + 64 r (lane l, register r) and x = x1 + 8 y1 + 64 y2 (lane 8 x1 + y1,
+// register y2), exp(2 pi i k x / 512) splits into three radix-8 DFTs (over r,
+// over the high lane digit, over the low lane digit) separated by two twiddle
+// multiplications and two exchanges through a wave-private LDS buffer.  The
+// inverse maps the natural spectral layout to that permuted physical layout;
+// the forward transform is its exact reverse, so the pointwise work between
+// them is lane-local and no workgroup barrier is needed.  Lane `lane` holds
+// the physical points x = (lane >> 3) + 8 (lane & 7) + 64 j, j = 0..7.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+
+namespace fsi {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// exchange slots (padded against LDS bank conflicts): 8 x 72 complex per wave
+__device__ __forceinline__ int xslot1(int x1, int l) { return x1 * 72 + l; }
+__device__ __forceinline__ int xslot2(int x1, int y1, int l1) { return x1 * 72 + y1 * 9 + l1; }
+constexpr int kXBuf = 576;
+
+// inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1
+template <typename T>
+__device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tIB, const cpx<T>* tC) {
+  const int hi = lane >> 3, lo = lane & 7;
+  Bfly<T, 8, 1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tIB[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot1(j, lane)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot1(hi, lo + 8 * j)];
+  wave_sync();
+  Bfly<T, 8, 1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], conj(tC[64 * j + lane]));
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot2(hi, j, lo)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot2(hi, lo, j)];
+  wave_sync();
+  Bfly<T, 8, 1>::run(v);
+}
+
+// forward: v[y2] = g[x1 + 8 y1 + 64 y2]  ->  v[r] = G[lane + 64 r] (unnormalized)
+template <typename T>
+__device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tC, const cpx<T>* tFB) {
+  const int hi = lane >> 3, lo = lane & 7;
+  Bfly<T, 8, -1>::run(v);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tC[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot2(hi, lo, j)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot2(hi, j, lo)];
+  wave_sync();
+  Bfly<T, 8, -1>::run(v);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = cmul(v[j], tFB[64 * j + lane]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) X[xslot1(hi, lo + 8 * j)] = v[j];
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xslot1(j, lane)];
+  wave_sync();
+  Bfly<T, 8, -1>::run(v);
+}
+
+// Unpack the transforms X, Y of the two real signals packed in g (natural layout,
+// g[r] = G[lane + 64 r]) and store X to dx, Y to dy for k <= K (K < 192).
+template <typename T>
+__device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, int K, cpx<T>* dx, cpx<T>* dy) {
+  const int src = (64 - lane) & 63;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cpx<T> p;
+    p.re = __shfl(g[7 - r].re, src, 64);
+    p.im = __shfl(g[7 - r].im, src, 64);
+    if (lane == 0) p = g[(8 - r) & 7];
+    const int k = lane + 64 * r;
+    if (k <= K) {
+      const cpx<T> zc = conj(p);
+      const cpx<T> d = g[r] - zc;
+      dx[k] = scl(g[r] + zc, (T)0.5);
+      dy[k] = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+    }
+  }
+}
+
+// Raw spectral values a lane needs for one packed signal of one line: A, B at
+// k = lane + 64 r (r = 0, 1, 2) and at the Hermitian partners n - k of
+// k = lane + 64 r (r = 5, 6, 7); slots outside the 2/3 band are zero.
+template <typename T>
+struct Raw512 {
+  cpx<T> a[6], b[6];
+};
+
+template <typename T>
+__device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int lane, Raw512<T>& w) {
+  constexpr int n = 512, K = 170;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int k = lane + 64 * q;  // direct slots r = q
+    const bool ok = k <= K;
+    w.a[q] = ok ? A[k] : mk<T>(0, 0);
+    w.b[q] = ok ? B[k] : mk<T>(0, 0);
+    const int kp = lane + 64 * (5 + q);  // partner slots r = 5 + q
+    const bool okp = kp >= n - K;
+    w.a[3 + q] = okp ? A[n - kp] : mk<T>(0, 0);
+    w.b[3 + q] = okp ? B[n - kp] : mk<T>(0, 0);
+  }
+}
+
+// Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout v[r] = Z[lane + 64 r].
+template <typename T>
+__device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
+    v[5 + q] = mk<T>(w.a[3 + q].re + w.b[3 + q].im, w.b[3 + q].re - w.a[3 + q].im);
+  }
+  if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
+  v[3] = mk<T>(0, 0);
+  v[4] = mk<T>(0, 0);
+}
+
+// Per-lane twiddle sets [j][lane] in LDS, from the axis table tw[m] =
+// exp(+2 pi i m / 512): exp(-2 pi i lane j / 512) (inverse first stage),
+// exp(+2 pi i lo j / 64) and exp(+2 pi i (lo + 8 j) hi / 512), lo = lane & 7,
+// hi = lane >> 3.  Called by all NT threads of the workgroup; the caller
+// synchronizes afterwards.
+template <typename T, int NT>
+__device__ __forceinline__ void wave512_twiddles(cpx<T> (*tws)[512], const cpx<T>* tw) {
+  for (int i = threadIdx.x; i < 512; i += NT) {
+    const int j = i >> 6, l = i & 63;
+    tws[0][i] = conj(tw[(l * j) & 511]);
+    tws[1][i] = tw[(8 * (l & 7) * j) & 511];
+    tws[2][i] = tw[(((l & 7) + 8 * j) * (l >> 3)) & 511];
+  }
+}
+
+}  // namespace fsi

@@ -22,13 +22,14 @@ from . import fsi
 class PlateRollout:
     """Rigid revolving plate driven through a fixed dt sequence."""
 
-    def __init__(self, solver, cfg, dts, K=10, law=0, u0=None):
+    def __init__(self, solver, cfg, dts, K=10, law=0, u0=None, uh0=None):
         self.s = solver
         self.cfg = cfg
         self.dts = [float(d) for d in dts]
         self.K = int(K)
         self.law = law
         self.u0 = u0
+        self.uh0 = uh0
         self.times = np.concatenate([[0.0], np.cumsum(self.dts)])[:-1]
         self.w = np.array(self.dts) / float(np.sum(self.dts))
         self.nseg = (len(self.dts) + self.K - 1) // self.K
@@ -43,6 +44,9 @@ class PlateRollout:
         return x, v
 
     def _reset(self):
+        if self.uh0 is not None:
+            self.s.set_spectrum(self.uh0)
+            return
         nx, ny, nz = self.s.n
         u0 = self.u0 if self.u0 is not None else np.zeros((3, nz, ny, nx))
         self.s.set_velocity(u0)
@@ -66,26 +70,34 @@ class PlateRollout:
 
     def backward(self, alpha):
         """dJ/dalpha by the adjoint, after ``forward(alpha)`` filled the checkpoints."""
-        cfg = self.cfg
-        tape0 = self.nseg
         self.s.adjoint_set(None, None)
         grad = 0.0
-        N = len(self.dts)
         for seg in reversed(range(self.nseg)):
-            n0, n1 = seg * self.K, min(seg * self.K + self.K, N)
-            self.s.load(seg)
-            for n in range(n0, n1):
-                self.s.save(tape0 + n - n0)
-                self._step(n, alpha)
-            for n in reversed(range(n0, n1)):
-                x, v = self._pose(self.times[n], alpha)
-                self.s.set_wing(x, v, cfg["tri"])
-                first = 1 if n == 0 else 0
-                dtp = self.dts[n - 1] if n > 0 else self.dts[n]
-                dx, dv = self.s.step_adjoint(tape0 + n - n0, self.dts[n], dtp, first, (0.0, 0.0, self.w[n]))
-                dxa, dva = fsi.plate_pose_dalpha(cfg["span_coord"], cfg["chord_coord"], self.times[n], alpha,
-                                                 cfg["omega"], cfg["t_ramp"], self.law)
-                grad += float(np.sum(dx * dxa) + np.sum(dv * dva))
+            grad = self.reverse_segment(seg, alpha, grad)
+        return grad
+
+    def reverse_segment(self, seg, alpha, grad=0.0):
+        """Reload checkpoint ``seg``, recompute its steps into tape slots and
+        reverse them, adding each step's share of dJ/dalpha to ``grad`` (one
+        running sum over all steps, so the segment length does not change the
+        result); returns the sum."""
+        cfg = self.cfg
+        tape0 = self.nseg
+        N = len(self.dts)
+        n0, n1 = seg * self.K, min(seg * self.K + self.K, N)
+        self.s.load(seg)
+        for n in range(n0, n1):
+            self.s.save(tape0 + n - n0)
+            self._step(n, alpha)
+        for n in reversed(range(n0, n1)):
+            x, v = self._pose(self.times[n], alpha)
+            self.s.set_wing(x, v, cfg["tri"])
+            first = 1 if n == 0 else 0
+            dtp = self.dts[n - 1] if n > 0 else self.dts[n]
+            dx, dv = self.s.step_adjoint(tape0 + n - n0, self.dts[n], dtp, first, (0.0, 0.0, self.w[n]))
+            dxa, dva = fsi.plate_pose_dalpha(cfg["span_coord"], cfg["chord_coord"], self.times[n], alpha,
+                                             cfg["omega"], cfg["t_ramp"], self.law)
+            grad += float(np.sum(dx * dxa) + np.sum(dv * dva))
         return grad
 
     def value_and_grad(self, alpha):

@@ -76,6 +76,106 @@ def test_adjoint_dot_product_two_steps(part):
     assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
 
 
+def run_two_steps(s, u0, x0, v0, tri, dts, g, lam_u, lam_n, du, dx, dv):
+    """Central-difference directional derivative of the two-step functional
+    and the adjoint's inner product with the same direction."""
+
+    def run(eps, save=False):
+        s.set_spectrum(u0 + eps * du)
+        s.set_wing(x0 + eps * dx, v0 + eps * dv, tri)
+        J = 0.0
+        for k, dt in enumerate(dts):
+            if save:
+                s.save(k)
+            s.step(dt)
+            J += float(np.dot(g[k], s.info()["F"]))
+        return J + cdot(lam_u, s.spectrum()) + cdot(lam_n, s.nonlinear())
+
+    eps = 1e-5
+    fd = (run(eps) - run(-eps)) / (2 * eps)
+    run(0.0, save=True)
+    s.set_wing(x0, v0, tri)
+    s.adjoint_set(lam_u, lam_n)
+    gx1, gv1 = s.step_adjoint(1, dts[1], dts[0], 0, g[1])
+    gx0, gv0 = s.step_adjoint(0, dts[0], dts[0], 1, g[0])
+    lu0, ln0 = s.adjoint_get()
+    adj = cdot(lu0, du) + float(np.sum((gx0 + gx1) * dx) + np.sum((gv0 + gv1) * dv))
+    return adj, fd, (lu0, ln0, gx0 + gx1, gv0 + gv1)
+
+
+def long_x_case(prec, n=(512, 16, 12), L=(8.0, 2.0, 1.5), tw=0.3, h=0.2):
+    """Long x lines (512 points: the register-resident adjoint x pass), a plate
+    close to the x-y plane in the middle of the box."""
+    s = fsi.Solver(n, L, 0.02, 0.05, tw, h, fsi.PROFILE_COS, prec)
+    rng = np.random.default_rng(11)
+    u0 = synth.random_solenoidal_compact(n, L, seed=5)
+    du = synth.random_solenoidal_compact(n, L, seed=6)
+    # tilted, off the grid planes and jittered, so that no grid point is
+    # equidistant from two triangles (where the distance has a kink)
+    u_ax = np.array([1.0, 0.07, 0.03]) / np.linalg.norm([1.0, 0.07, 0.03])
+    v_ax = np.cross([0.02, -0.05, 1.0], u_ax)
+    v_ax /= np.linalg.norm(v_ax)
+    centre = (0.5 * L[0] + 0.013, 0.5 * L[1] + 0.027, 0.5 * L[2] - 0.0069)
+    x0, tri = synth.flat_rectangle(centre, u_ax, v_ax, 1.0, 0.35, 9, 4)
+    x0 = x0 + 0.004 * rng.standard_normal(x0.shape)
+    v0 = rng.standard_normal(x0.shape)
+    dx = 0.01 * rng.standard_normal(x0.shape)
+    dv = rng.standard_normal(x0.shape)
+    g = [rng.standard_normal(3), rng.standard_normal(3)]
+    lam_u = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    lam_n = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    return run_two_steps(s, u0, x0, v0, tri, (0.01, 0.013), g, lam_u, lam_n, du, dx, dv)
+
+
+# (512, 192, 192): each wavefront of the 512-point pass reverses several line
+# pairs; (384, 128, 96): the LDS pass, several line groups per workgroup.
+LARGE = [((512, 16, 12), (8.0, 2.0, 1.5), 0.3, 0.2),
+         ((512, 192, 192), (8.0, 3.0, 3.0), 0.05, 0.03),
+         ((384, 128, 96), (6.0, 2.0, 1.5), 0.05, 0.03)]
+
+
+@pytest.mark.parametrize("case", LARGE, ids=lambda c: "x".join(map(str, c[0])))
+def test_adjoint_dot_product_long_lines(case):
+    n, L, tw, h = case
+    adj, fd, _ = long_x_case(fsi.PREC_FP64, n, L, tw, h)
+    print("dot product %s: adjoint %.12e fd %.12e" % (n, adj, fd), flush=True)
+    assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
+
+
+@pytest.mark.parametrize("case", LARGE, ids=lambda c: "x".join(map(str, c[0])))
+def test_fp32_adjoint_long_lines_matches_fp64(case):
+    n, L, tw, h = case
+    _, _, r64 = long_x_case(fsi.PREC_FP64, n, L, tw, h)
+    _, _, r32 = long_x_case(fsi.PREC_FP32, n, L, tw, h)
+    for name, a32, a64 in zip(("lambda_u", "lambda_N", "dJ/dx", "dJ/dv"), r32, r64):
+        ref = np.max(np.abs(a64))
+        if name == "lambda_N":  # reversing the first (Euler) step leaves no N^{-1} cotangent
+            assert ref == 0.0 and np.max(np.abs(a32)) == 0.0
+            continue
+        err = np.max(np.abs(a32 - a64)) / ref
+        print("FP32 vs FP64 adjoint %s: rel max err %.3e" % (name, err), flush=True)
+        assert err < 2e-5
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+@pytest.mark.parametrize("n,L", [((96, 16, 12), (6.0, 2.0, 1.5)), ((512, 16, 12), (8.0, 2.0, 1.5))])
+def test_zero_flow_has_zero_nonlinear_cotangent(n, L, prec):
+    """With u = 0 and no wing, u x omega and its transpose vanish: reversing an
+    Euler step from lambda_u = 0 must give exactly zero lambda_u for any
+    lambda_N.  (Catches cross-talk between packed real signals of different
+    size in the transposed x pass.)"""
+    s = fsi.Solver(n, L, 0.02, 0.05, 0.05, 0.03, fsi.PROFILE_COS, prec)
+    shape = synth.random_solenoidal_compact(n, L, seed=5).shape
+    rng = np.random.default_rng(2)
+    s.set_spectrum(np.zeros(shape, dtype=np.complex128))
+    s.save(0)
+    s.step(0.01)
+    s.adjoint_set(None, rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    s.step_adjoint(0, 0.01, 0.01, 1, (0.0, 0.0, 0.0))
+    lu, _ = s.adjoint_get()
+    assert np.max(np.abs(lu)) == 0.0
+
+
 def plate_case(n=32):
     cfg = synth.revolving_plate(n=n, fixed_eta=2.5e-3, t_ramp=0.0)
     dts = [1e-3] * 12
