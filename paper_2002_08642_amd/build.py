@@ -1,7 +1,8 @@
 """Build the HIP library libfsi.so for gfx950 in-tree.
 
-Each translation unit is compiled with hipcc for gfx950 (packed FP32
-instructions disabled), then the objects are linked into
+Each HIP translation unit is compiled with hipcc for gfx950 (packed FP32
+instructions disabled), the host-only C++ sources (the FP64 mass-spring
+solver) with the host compiler, then the objects are linked into
 ``paper_2002_08642_amd/libfsi.so``.
 """
 
@@ -16,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsi.so")
 SOURCES = ["kernels.hip", "adjoint.hip", "engine.hip", "api.hip"]
+HOST_SOURCES = ["structure.cpp"]
 ARCH = "gfx950"
 
 
@@ -32,9 +34,20 @@ def flags():
             "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
 
 
+def host_cxx():
+    path = shutil.which("g++") or shutil.which("c++")
+    if not path:
+        raise RuntimeError("no host C++ compiler")
+    return path
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if src in HOST_SOURCES:
+        cmd = [host_cxx(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(HERE, "..", "include"),
+               "-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -43,8 +56,9 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    srcs = SOURCES + HOST_SOURCES
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,595 @@
+// structure.cpp - FP64 mass-spring wing solver (host), the C ABI of include/fsi_ms.h.
+//
+// Sec. 2.1: the phase vector q = [x, v] obeys dq/dt = [v, (F_int + F_ext)/m];
+// the variable-step BDF2 of Eq. discretized_ODEs,
+//   q^{n+1} - alpha q^n + beta q^{n-1} = gamma dt f(q^{n+1}),
+//   alpha = (1+xi)^2/(1+2xi), beta = xi^2/(1+2xi), gamma = (1+xi)/(1+2xi),
+// is solved by Newton-Raphson from q^n.  The velocity rows are linear in
+// v^{n+1}, so v^{n+1} = (x^{n+1} - b_x) / (gamma dt) (b_x = alpha x^n - beta
+// x^{n-1}) is eliminated exactly and Newton runs on the positions alone:
+//   r(x) = M (x - b_x) - gamma dt M b_v - (gamma dt)^2 (F_int(x) + F_ext) = 0,
+//   A = M + (gamma dt)^2 H(x),   H = Hessian of the elastic energy,
+// the same iterates' root as Newton on the full 6n system.  A is assembled in
+// band form over the free vertices in reverse Cuthill-McKee order and solved by
+// banded LU with partial pivoting.
+//
+// Springs (Sec. 2.2): extension E = k/2 (|x_j - x_i| - l0)^2; bending
+// E = k^b/2 sum_{p in {y,z}} (theta^p - theta^p_0)^2 with theta^p the angle
+// from segment a = x_j - x_i to b = x_k - x_j projected on the wing-frame
+// plane (x, p) (Eq. two_bending_angles).  That angle is the difference of the
+// polar angles of the projections, theta = phi(b) - phi(a), which gives the
+// gradient and Hessian in closed form.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fsi_ms.h"
+
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+
+// Band matrix (general, with room for the fill-in of partial pivoting):
+// row i stores columns i - kl .. i + kl + ku.
+struct Band {
+  int n = 0, kl = 0, ku = 0, w = 0;
+  std::vector<double> a;
+  void init(int n_, int kl_, int ku_) {
+    n = n_;
+    kl = kl_;
+    ku = ku_;
+    w = 2 * kl + ku + 1;
+    a.assign((size_t)n * w, 0.0);
+  }
+  double& operator()(int i, int j) { return a[(size_t)i * w + (j - i + kl)]; }
+  // LU with partial pivoting, solving A x = b in place; false if singular.
+  bool solve(std::vector<double>& b) {
+    const int ue = kl + ku;  // upper bandwidth after pivoting
+    for (int k = 0; k < n; ++k) {
+      const int last = std::min(n - 1, k + kl);
+      int p = k;
+      double pv = fabs((*this)(k, k));
+      for (int i = k + 1; i <= last; ++i)
+        if (fabs((*this)(i, k)) > pv) {
+          pv = fabs((*this)(i, k));
+          p = i;
+        }
+      if (!(pv > 0.0) || !std::isfinite(pv)) return false;
+      const int jend = std::min(n - 1, k + ue);
+      if (p != k) {
+        for (int j = k; j <= jend; ++j) std::swap((*this)(k, j), (*this)(p, j));
+        std::swap(b[k], b[p]);
+      }
+      const double d = (*this)(k, k);
+      for (int i = k + 1; i <= last; ++i) {
+        const double l = (*this)(i, k) / d;
+        if (l == 0.0) continue;
+        for (int j = k + 1; j <= jend; ++j) (*this)(i, j) -= l * (*this)(k, j);
+        b[i] -= l * b[k];
+      }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = b[i];
+      const int jend = std::min(n - 1, i + ue);
+      for (int j = i + 1; j <= jend; ++j) s -= (*this)(i, j) * b[j];
+      b[i] = s / (*this)(i, i);
+    }
+    return true;
+  }
+};
+
+}  // namespace
+
+struct fsi_ms {
+  int nv = 0;
+  std::vector<double> mass;
+  std::vector<int> ei, ej;
+  std::vector<double> ek, el0;
+  std::vector<int> bi, bj, bk;
+  std::vector<double> bkb, bt0;  // bt0: [nb][2]
+  std::vector<int> clamped;      // in the order given
+  std::vector<int> is_clamped;
+  std::vector<double> x, v, xp, vp;
+  double dt_prev = 0.0;
+  bool have_prev = false;
+  // free-vertex ordering for the band solver
+  bool order_valid = false;
+  std::vector<int> slot;  // vertex -> position among free vertices (RCM), -1 if clamped
+  int nfree = 0, vbw = 0;
+  std::string err;
+};
+
+namespace {
+
+fsi_status fail(fsi_ms* ms, fsi_status s, const char* msg) {
+  if (ms) ms->err = msg;
+  return s;
+}
+
+// wing-frame components of an inertial vector: a_w = F^T a (F columns = wing axes)
+inline V3 to_wing(const double* F, V3 a) {
+  return {F[0] * a.x + F[3] * a.y + F[6] * a.z, F[1] * a.x + F[4] * a.y + F[7] * a.z,
+          F[2] * a.x + F[5] * a.y + F[8] * a.z};
+}
+// inertial components of a wing-frame vector: F a_w
+inline V3 to_inertial(const double* F, const double* w) {
+  return {F[0] * w[0] + F[1] * w[1] + F[2] * w[2], F[3] * w[0] + F[4] * w[1] + F[5] * w[2],
+          F[6] * w[0] + F[7] * w[1] + F[8] * w[2]};
+}
+
+const double kIdentity[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+
+// Elastic energy, forces (-grad) and, optionally, the Hessian blocks of every
+// spring handed to `sink(u, w, block[3][3])` (block = d2E / dx_u dx_w).
+template <typename Sink>
+double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bool hess, Sink&& sink) {
+  double E = 0.0;
+  if (f) memset(f, 0, sizeof(double) * 3 * ms.nv);
+  // extension springs
+  for (size_t s = 0; s < ms.ek.size(); ++s) {
+    const int i = ms.ei[s], j = ms.ej[s];
+    const double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double k = ms.ek[s], ext = L - ms.el0[s];
+    E += 0.5 * k * ext * ext;
+    const double e[3] = {d[0] / L, d[1] / L, d[2] / L};
+    if (f)
+      for (int c = 0; c < 3; ++c) {
+        const double fi = k * ext * e[c];
+        f[3 * i + c] += fi;
+        f[3 * j + c] -= fi;
+      }
+    if (hess) {
+      // d2E/dd2 = k [e e^T + (1 - l0/L)(I - e e^T)]
+      double K[3][3];
+      const double t = 1.0 - ms.el0[s] / L;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) K[r][c] = k * ((1.0 - t) * e[r] * e[c] + (r == c ? t : 0.0));
+      double N[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) N[r][c] = -K[r][c];
+      sink(i, i, K);
+      sink(j, j, K);
+      sink(i, j, N);
+      sink(j, i, N);
+    }
+  }
+  // bending springs
+  for (size_t s = 0; s < ms.bkb.size(); ++s) {
+    const int vi = ms.bi[s], vj = ms.bj[s], vk = ms.bk[s];
+    const V3 a = to_wing(F, {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]});
+    const V3 b = to_wing(F, {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]});
+    const double kb = ms.bkb[s];
+    double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};  // dE/da, dE/db (wing frame)
+    double Hab[6][6];                             // d2E/d(a,b)^2 (wing frame)
+    memset(Hab, 0, sizeof(Hab));
+    const double av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    for (int p = 0; p < 2; ++p) {
+      const int q = p + 1;  // projection on the wing plane (x, q): q = y, then z
+      const double ra = av[0] * av[0] + av[q] * av[q], rb = bv[0] * bv[0] + bv[q] * bv[q];
+      const double th = atan2(bv[q], bv[0]) - atan2(av[q], av[0]);
+      // wrap to (-pi, pi], the range of Eq. two_bending_angles
+      double t = th;
+      if (t > M_PI) t -= 2 * M_PI;
+      if (t <= -M_PI) t += 2 * M_PI;
+      const double dth = t - ms.bt0[2 * s + p];
+      E += 0.5 * kb * dth * dth;
+      // grad theta: -grad phi(a), +grad phi(b); grad phi(v) = (-v_q, v_p) / r^2
+      double g[6] = {0, 0, 0, 0, 0, 0};
+      g[0] = av[q] / ra;
+      g[q] = -av[0] / ra;
+      g[3] = -bv[q] / rb;
+      g[3 + q] = bv[0] / rb;
+      for (int c = 0; c < 3; ++c) {
+        ga[c] += kb * dth * g[c];
+        gb[c] += kb * dth * g[3 + c];
+      }
+      if (hess) {
+        for (int r = 0; r < 6; ++r)
+          for (int c = 0; c < 6; ++c) Hab[r][c] += kb * g[r] * g[c];
+        // (theta - theta0) * hess theta: -hess phi(a), +hess phi(b);
+        // hess phi(v) = [[2 v_p v_q, v_q^2 - v_p^2], [., -2 v_p v_q]] / r^4
+        const double fa = -kb * dth / (ra * ra), fb = kb * dth / (rb * rb);
+        const int ia[2] = {0, q}, ib[2] = {3, 3 + q};
+        const double ha[2][2] = {{2 * av[0] * av[q], av[q] * av[q] - av[0] * av[0]},
+                                 {av[q] * av[q] - av[0] * av[0], -2 * av[0] * av[q]}};
+        const double hb[2][2] = {{2 * bv[0] * bv[q], bv[q] * bv[q] - bv[0] * bv[0]},
+                                 {bv[q] * bv[q] - bv[0] * bv[0], -2 * bv[0] * bv[q]}};
+        for (int r = 0; r < 2; ++r)
+          for (int c = 0; c < 2; ++c) {
+            Hab[ia[r]][ia[c]] += fa * ha[r][c];
+            Hab[ib[r]][ib[c]] += fb * hb[r][c];
+          }
+      }
+    }
+    if (f) {
+      const V3 Ga = to_inertial(F, ga), Gb = to_inertial(F, gb);
+      // a = x_j - x_i, b = x_k - x_j:  f_i = F ga, f_j = F (gb - ga), f_k = -F gb
+      const double A[3] = {Ga.x, Ga.y, Ga.z}, B[3] = {Gb.x, Gb.y, Gb.z};
+      for (int c = 0; c < 3; ++c) {
+        f[3 * vi + c] += A[c];
+        f[3 * vj + c] += B[c] - A[c];
+        f[3 * vk + c] -= B[c];
+      }
+    }
+    if (hess) {
+      // rotate to the inertial frame: G = diag(F, F) Hab diag(F^T, F^T)
+      double G[6][6];
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          const int rb0 = (r / 3) * 3, cb0 = (c / 3) * 3, rr = r % 3, cc = c % 3;
+          double sum = 0.0;
+          for (int m = 0; m < 3; ++m)
+            for (int n = 0; n < 3; ++n) sum += F[3 * rr + m] * Hab[rb0 + m][cb0 + n] * F[3 * cc + n];
+          G[r][c] = sum;
+        }
+      // x_i -> (-I, 0), x_j -> (I, -I), x_k -> (0, I)
+      const int vtx[3] = {vi, vj, vk};
+      const double S[3][2] = {{-1, 0}, {1, -1}, {0, 1}};
+      for (int u = 0; u < 3; ++u)
+        for (int w = 0; w < 3; ++w) {
+          double blk[3][3];
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+              blk[r][c] = S[u][0] * S[w][0] * G[r][c] + S[u][0] * S[w][1] * G[r][3 + c] +
+                          S[u][1] * S[w][0] * G[3 + r][c] + S[u][1] * S[w][1] * G[3 + r][3 + c];
+          sink(vtx[u], vtx[w], blk);
+        }
+    }
+  }
+  return E;
+}
+
+struct NoSink {
+  void operator()(int, int, const double (&)[3][3]) const {}
+};
+
+// Reverse Cuthill-McKee order of the free vertices over the spring graph.
+void build_order(fsi_ms& ms) {
+  std::vector<std::vector<int>> adj(ms.nv);
+  auto link = [&](int a, int b) {
+    if (a == b || ms.is_clamped[a] || ms.is_clamped[b]) return;
+    adj[a].push_back(b);
+    adj[b].push_back(a);
+  };
+  for (size_t s = 0; s < ms.ek.size(); ++s) link(ms.ei[s], ms.ej[s]);
+  for (size_t s = 0; s < ms.bkb.size(); ++s) {
+    link(ms.bi[s], ms.bj[s]);
+    link(ms.bj[s], ms.bk[s]);
+    link(ms.bi[s], ms.bk[s]);
+  }
+  for (auto& l : adj) {
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+  }
+  std::vector<int> order;
+  std::vector<char> seen(ms.nv, 0);
+  for (;;) {
+    int start = -1;
+    for (int i = 0; i < ms.nv; ++i)
+      if (!ms.is_clamped[i] && !seen[i] && (start < 0 || adj[i].size() < adj[start].size())) start = i;
+    if (start < 0) break;
+    std::deque<int> qu{start};
+    seen[start] = 1;
+    while (!qu.empty()) {
+      const int u = qu.front();
+      qu.pop_front();
+      order.push_back(u);
+      std::vector<int> nb;
+      for (int w : adj[u])
+        if (!seen[w]) {
+          seen[w] = 1;
+          nb.push_back(w);
+        }
+      std::sort(nb.begin(), nb.end(), [&](int p, int q) { return adj[p].size() < adj[q].size(); });
+      for (int w : nb) qu.push_back(w);
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  ms.slot.assign(ms.nv, -1);
+  for (size_t k = 0; k < order.size(); ++k) ms.slot[order[k]] = (int)k;
+  ms.nfree = (int)order.size();
+  ms.vbw = 0;
+  for (int u = 0; u < ms.nv; ++u)
+    for (int w : adj[u]) ms.vbw = std::max(ms.vbw, std::abs(ms.slot[u] - ms.slot[w]));
+  ms.order_valid = true;
+}
+
+// Newton matrix diag(mass) * mscale + hscale * H over the free vertices, and
+// the elastic forces at x.
+void assemble(fsi_ms& ms, const double* x, const double* F, double mscale, double hscale, Band& A,
+              std::vector<double>& f) {
+  if (!ms.order_valid) build_order(ms);
+  const int bw = 3 * ms.vbw + 2;
+  A.init(3 * ms.nfree, bw, bw);
+  f.assign(3 * ms.nv, 0.0);
+  springs(ms, x, F, f.data(), true, [&](int u, int w, const double (&blk)[3][3]) {
+    const int su = ms.slot[u], sw = ms.slot[w];
+    if (su < 0 || sw < 0) return;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) A(3 * su + r, 3 * sw + c) += hscale * blk[r][c];
+  });
+  if (mscale != 0.0)
+    for (int u = 0; u < ms.nv; ++u)
+      if (ms.slot[u] >= 0)
+        for (int c = 0; c < 3; ++c) A(3 * ms.slot[u] + c, 3 * ms.slot[u] + c) += mscale * ms.mass[u];
+}
+
+}  // namespace
+
+extern "C" {
+
+fsi_status fsi_ms_create(int32_t nv, const double* mass, fsi_ms** out) {
+  if (!out) return FSI_EINVAL;
+  *out = nullptr;
+  if (nv < 1 || !mass) return FSI_EINVAL;
+  for (int i = 0; i < nv; ++i)
+    if (!(mass[i] > 0.0) || !std::isfinite(mass[i])) return FSI_EINVAL;
+  fsi_ms* ms = new (std::nothrow) fsi_ms;
+  if (!ms) return FSI_ENOMEM;
+  ms->nv = nv;
+  ms->mass.assign(mass, mass + nv);
+  ms->is_clamped.assign(nv, 0);
+  ms->x.assign(3 * nv, 0.0);
+  ms->v.assign(3 * nv, 0.0);
+  *out = ms;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_destroy(fsi_ms* ms) {
+  delete ms;
+  return FSI_OK;
+}
+
+const char* fsi_ms_last_error(const fsi_ms* ms) { return ms ? ms->err.c_str() : "null solver"; }
+
+fsi_status fsi_ms_add_extension(fsi_ms* ms, int32_t n, const int32_t* ij, const double* k, const double* l0,
+                                int32_t* first) {
+  if (!ms) return FSI_EINVAL;
+  if (n < 0 || (n > 0 && (!ij || !k || !l0))) return fail(ms, FSI_EINVAL, "bad extension spring arrays");
+  for (int s = 0; s < n; ++s) {
+    if (ij[2 * s] < 0 || ij[2 * s] >= ms->nv || ij[2 * s + 1] < 0 || ij[2 * s + 1] >= ms->nv ||
+        ij[2 * s] == ij[2 * s + 1])
+      return fail(ms, FSI_EINVAL, "extension spring vertex out of range or repeated");
+    if (!(k[s] >= 0.0) || !(l0[s] > 0.0)) return fail(ms, FSI_EINVAL, "extension spring needs k >= 0, l0 > 0");
+  }
+  if (first) *first = (int32_t)ms->ek.size();
+  for (int s = 0; s < n; ++s) {
+    ms->ei.push_back(ij[2 * s]);
+    ms->ej.push_back(ij[2 * s + 1]);
+    ms->ek.push_back(k[s]);
+    ms->el0.push_back(l0[s]);
+  }
+  ms->order_valid = false;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_add_bending(fsi_ms* ms, int32_t n, const int32_t* ijk, const double* kb, const double* theta0,
+                              int32_t* first) {
+  if (!ms) return FSI_EINVAL;
+  if (n < 0 || (n > 0 && (!ijk || !kb || !theta0))) return fail(ms, FSI_EINVAL, "bad bending spring arrays");
+  for (int s = 0; s < n; ++s) {
+    for (int c = 0; c < 3; ++c)
+      if (ijk[3 * s + c] < 0 || ijk[3 * s + c] >= ms->nv) return fail(ms, FSI_EINVAL, "bending vertex out of range");
+    if (ijk[3 * s] == ijk[3 * s + 1] || ijk[3 * s + 1] == ijk[3 * s + 2])
+      return fail(ms, FSI_EINVAL, "bending spring segments must have distinct ends");
+    if (!(kb[s] >= 0.0)) return fail(ms, FSI_EINVAL, "bending stiffness must be >= 0");
+  }
+  if (first) *first = (int32_t)ms->bkb.size();
+  for (int s = 0; s < n; ++s) {
+    ms->bi.push_back(ijk[3 * s]);
+    ms->bj.push_back(ijk[3 * s + 1]);
+    ms->bk.push_back(ijk[3 * s + 2]);
+    ms->bkb.push_back(kb[s]);
+    ms->bt0.push_back(theta0[2 * s]);
+    ms->bt0.push_back(theta0[2 * s + 1]);
+  }
+  ms->order_valid = false;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_extension_k(fsi_ms* ms, const double* k) {
+  if (!ms) return FSI_EINVAL;
+  if (!k && !ms->ek.empty()) return fail(ms, FSI_EINVAL, "k is NULL");
+  for (size_t s = 0; s < ms->ek.size(); ++s)
+    if (!(k[s] >= 0.0)) return fail(ms, FSI_EINVAL, "extension stiffness must be >= 0");
+  for (size_t s = 0; s < ms->ek.size(); ++s) ms->ek[s] = k[s];
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_bending_k(fsi_ms* ms, const double* kb) {
+  if (!ms) return FSI_EINVAL;
+  if (!kb && !ms->bkb.empty()) return fail(ms, FSI_EINVAL, "kb is NULL");
+  for (size_t s = 0; s < ms->bkb.size(); ++s)
+    if (!(kb[s] >= 0.0)) return fail(ms, FSI_EINVAL, "bending stiffness must be >= 0");
+  for (size_t s = 0; s < ms->bkb.size(); ++s) ms->bkb[s] = kb[s];
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_clamped(fsi_ms* ms, int32_t n, const int32_t* idx) {
+  if (!ms) return FSI_EINVAL;
+  if (n < 0 || (n > 0 && !idx)) return fail(ms, FSI_EINVAL, "bad clamped list");
+  std::vector<int> flag(ms->nv, 0);
+  for (int c = 0; c < n; ++c) {
+    if (idx[c] < 0 || idx[c] >= ms->nv) return fail(ms, FSI_EINVAL, "clamped vertex out of range");
+    if (flag[idx[c]]) return fail(ms, FSI_EINVAL, "clamped vertex listed twice");
+    flag[idx[c]] = 1;
+  }
+  ms->clamped.assign(idx, idx + n);
+  ms->is_clamped = flag;
+  ms->order_valid = false;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_bending_angles(const fsi_ms* ms, const double* x, const double* frame, double* theta) {
+  if (!ms || !x || !theta) return FSI_EINVAL;
+  const double* F = frame ? frame : kIdentity;
+  for (size_t s = 0; s < ms->bkb.size(); ++s) {
+    const int vi = ms->bi[s], vj = ms->bj[s], vk = ms->bk[s];
+    const V3 a = to_wing(F, {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]});
+    const V3 b = to_wing(F, {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]});
+    const double av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    for (int p = 0; p < 2; ++p) {
+      const int q = p + 1;
+      // Eq. two_bending_angles: atan2 of the cross and dot products of the projections
+      theta[2 * s + p] = atan2(av[0] * bv[q] - bv[0] * av[q], av[0] * bv[0] + av[q] * bv[q]);
+    }
+  }
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_forces(const fsi_ms* ms, const double* x, const double* frame, double* f, double* energy) {
+  if (!ms || !x || !f) return FSI_EINVAL;
+  const double E = springs(*ms, x, frame ? frame : kIdentity, f, false, NoSink{});
+  if (energy) *energy = E;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_state(fsi_ms* ms, const double* x, const double* v) {
+  if (!ms || !x) return FSI_EINVAL;
+  for (int i = 0; i < 3 * ms->nv; ++i)
+    if (!std::isfinite(x[i]) || (v && !std::isfinite(v[i]))) return fail(ms, FSI_EINVAL, "non-finite state");
+  ms->x.assign(x, x + 3 * ms->nv);
+  if (v)
+    ms->v.assign(v, v + 3 * ms->nv);
+  else
+    ms->v.assign(3 * ms->nv, 0.0);
+  ms->have_prev = false;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_get_state(const fsi_ms* ms, double* x, double* v) {
+  if (!ms) return FSI_EINVAL;
+  if (x) memcpy(x, ms->x.data(), sizeof(double) * 3 * ms->nv);
+  if (v) memcpy(v, ms->v.data(), sizeof(double) * 3 * ms->nv);
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_step(fsi_ms* ms, double dt, const double* frame, const double* f_ext, const double* x_clamp,
+                       const double* v_clamp, double tol, int32_t max_iter, int32_t* iters) {
+  if (!ms) return FSI_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ms, FSI_EINVAL, "dt must be positive");
+  if (max_iter < 1) return fail(ms, FSI_EINVAL, "max_iter must be >= 1");
+  if (tol <= 0.0) tol = 1e-6;
+  const double* F = frame ? frame : kIdentity;
+  const int nv = ms->nv;
+  const double xi = ms->have_prev ? dt / ms->dt_prev : 0.0;
+  const double alpha = (1 + xi) * (1 + xi) / (1 + 2 * xi), beta = xi * xi / (1 + 2 * xi);
+  const double gdt = (1 + xi) / (1 + 2 * xi) * dt;
+  std::vector<double> bx(3 * nv), bv(3 * nv);
+  for (int i = 0; i < 3 * nv; ++i) {
+    bx[i] = alpha * ms->x[i] - (ms->have_prev ? beta * ms->xp[i] : 0.0);
+    bv[i] = alpha * ms->v[i] - (ms->have_prev ? beta * ms->vp[i] : 0.0);
+  }
+  std::vector<double> x = ms->x, v(3 * nv);
+  for (size_t c = 0; c < ms->clamped.size(); ++c) {
+    const int u = ms->clamped[c];
+    for (int d = 0; d < 3; ++d) {
+      x[3 * u + d] = x_clamp ? x_clamp[3 * c + d] : ms->x[3 * u + d];
+      v[3 * u + d] = v_clamp ? v_clamp[3 * c + d] : 0.0;
+    }
+  }
+  Band A;
+  std::vector<double> f, r;
+  int it = 0;
+  bool ok = false;
+  for (it = 1; it <= max_iter; ++it) {
+    // r = M (x - b_x) - gdt M b_v - gdt^2 (F_int + F_ext);  A = M + gdt^2 H
+    assemble(*ms, x.data(), F, 1.0, gdt * gdt, A, f);
+    r.assign(3 * ms->nfree, 0.0);
+    for (int u = 0; u < nv; ++u) {
+      const int su = ms->slot[u];
+      if (su < 0) continue;
+      for (int d = 0; d < 3; ++d) {
+        const double fe = f_ext ? f_ext[3 * u + d] : 0.0;
+        r[3 * su + d] = -(ms->mass[u] * (x[3 * u + d] - bx[3 * u + d]) - gdt * ms->mass[u] * bv[3 * u + d] -
+                          gdt * gdt * (f[3 * u + d] + fe));
+      }
+    }
+    if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular Newton matrix");
+    double dn = 0.0, qn = 0.0;
+    for (int u = 0; u < nv; ++u) {
+      const int su = ms->slot[u];
+      if (su < 0) continue;
+      for (int d = 0; d < 3; ++d) {
+        const double dx = r[3 * su + d];
+        x[3 * u + d] += dx;
+        dn += dx * dx * (1.0 + 1.0 / (gdt * gdt));  // the update of (x, v)
+      }
+    }
+    for (int u = 0; u < nv; ++u)
+      if (ms->slot[u] >= 0)
+        for (int d = 0; d < 3; ++d) v[3 * u + d] = (x[3 * u + d] - bx[3 * u + d]) / gdt;
+    for (int i = 0; i < 3 * nv; ++i) qn += x[i] * x[i] + v[i] * v[i];
+    if (!std::isfinite(dn)) return fail(ms, FSI_ESTATE, "Newton produced a non-finite update");
+    if (sqrt(dn) <= tol * std::max(1.0, sqrt(qn))) {
+      ok = true;
+      break;
+    }
+  }
+  if (!ok) return fail(ms, FSI_ESTATE, "Newton did not converge");
+  ms->xp.swap(ms->x);
+  ms->vp.swap(ms->v);
+  ms->x = x;
+  ms->v = v;
+  ms->dt_prev = dt;
+  ms->have_prev = true;
+  if (iters) *iters = it;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_static(fsi_ms* ms, const double* frame, const double* f_ext, int32_t load_steps, double tol,
+                         int32_t max_iter) {
+  if (!ms) return FSI_EINVAL;
+  if (load_steps < 1 || max_iter < 1) return fail(ms, FSI_EINVAL, "load_steps and max_iter must be >= 1");
+  if (tol <= 0.0) tol = 1e-10;
+  const double* F = frame ? frame : kIdentity;
+  const int nv = ms->nv;
+  std::vector<double> x = ms->x, f, r;
+  Band A;
+  for (int ls = 1; ls <= load_steps; ++ls) {
+    const double lam = (double)ls / load_steps;
+    bool ok = false;
+    for (int it = 0; it < max_iter; ++it) {
+      assemble(*ms, x.data(), F, 0.0, 1.0, A, f);
+      r.assign(3 * ms->nfree, 0.0);
+      for (int u = 0; u < nv; ++u) {
+        const int su = ms->slot[u];
+        if (su < 0) continue;
+        // H dx = F_int + lam F_ext (Newton on F_int(x) + lam F_ext = 0, with dF_int/dx = -H)
+        for (int d = 0; d < 3; ++d) r[3 * su + d] = f[3 * u + d] + lam * (f_ext ? f_ext[3 * u + d] : 0.0);
+      }
+      if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular stiffness matrix");
+      double dn = 0.0, xn = 0.0;
+      for (int u = 0; u < nv; ++u) {
+        const int su = ms->slot[u];
+        if (su < 0) continue;
+        for (int d = 0; d < 3; ++d) {
+          x[3 * u + d] += r[3 * su + d];
+          dn += r[3 * su + d] * r[3 * su + d];
+        }
+      }
+      for (double c : x) xn += c * c;
+      if (!std::isfinite(dn)) return fail(ms, FSI_ESTATE, "static Newton produced a non-finite update");
+      if (sqrt(dn) <= tol * std::max(1.0, sqrt(xn))) {
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) return fail(ms, FSI_ESTATE, "static Newton did not converge");
+  }
+  ms->x = x;
+  ms->v.assign(3 * nv, 0.0);
+  ms->have_prev = false;
+  return FSI_OK;
+}
+
+}  // extern "C"

@@ -1,4 +1,4 @@
-"""Thin ctypes binding of libfsi.so (include/fsi.h).
+"""Thin ctypes binding of libfsi.so (include/fsi.h, include/fsi_ms.h).
 
 Argument marshalling only: every step of the method runs in the HIP library.
 The library must be built (``python -m paper_2002_08642_amd.build`` or
@@ -25,8 +25,11 @@ PREC_FP64 = 1
 NPASS = 7
 PASS_NAMES = ["mask", "z_inverse_curl", "y_inverse", "x_fused", "reduce_dt", "y_forward", "z_forward_update"]
 
-# every symbol declared in include/fsi.h
+# every symbol declared in include/*.h
 EXPORTS = [
+    "fsi_ms_create", "fsi_ms_destroy", "fsi_ms_last_error", "fsi_ms_add_extension", "fsi_ms_add_bending",
+    "fsi_ms_set_extension_k", "fsi_ms_set_bending_k", "fsi_ms_set_clamped", "fsi_ms_bending_angles",
+    "fsi_ms_forces", "fsi_ms_set_state", "fsi_ms_get_state", "fsi_ms_step", "fsi_ms_static",
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
     "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
@@ -99,9 +102,24 @@ def load_library():
     lib.fsi_step_adjoint.argtypes = [P, I32, ctypes.c_double, ctypes.c_double, I32, D, D, D]
     lib.fsi_plate_pose_dalpha.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, I32, D, D]
+    lib.fsi_ms_create.argtypes = [I32, D, ctypes.POINTER(P)]
+    lib.fsi_ms_destroy.argtypes = [P]
+    lib.fsi_ms_last_error.argtypes = [P]
+    lib.fsi_ms_last_error.restype = ctypes.c_char_p
+    lib.fsi_ms_add_extension.argtypes = [P, I32, ctypes.POINTER(I32), D, D, ctypes.POINTER(I32)]
+    lib.fsi_ms_add_bending.argtypes = [P, I32, ctypes.POINTER(I32), D, D, ctypes.POINTER(I32)]
+    lib.fsi_ms_set_extension_k.argtypes = [P, D]
+    lib.fsi_ms_set_bending_k.argtypes = [P, D]
+    lib.fsi_ms_set_clamped.argtypes = [P, I32, ctypes.POINTER(I32)]
+    lib.fsi_ms_bending_angles.argtypes = [P, D, D, D]
+    lib.fsi_ms_forces.argtypes = [P, D, D, D, D]
+    lib.fsi_ms_set_state.argtypes = [P, D, D]
+    lib.fsi_ms_get_state.argtypes = [P, D, D]
+    lib.fsi_ms_step.argtypes = [P, ctypes.c_double, D, D, D, D, ctypes.c_double, I32, ctypes.POINTER(I32)]
+    lib.fsi_ms_static.argtypes = [P, D, D, I32, ctypes.c_double, I32]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
-            "fsi_last_error", "fsi_create_error", "fsi_version") else ctypes.c_int32
+            "fsi_last_error", "fsi_create_error", "fsi_version", "fsi_ms_last_error") else ctypes.c_int32
     _lib = lib
     return lib
 
@@ -313,3 +331,121 @@ class Solver:
         n = ctypes.c_int32()
         self._check(self.lib.fsi_get_pass_times(self.ctx, _dptr(ms), ctypes.byref(n)))
         return dict(zip(PASS_NAMES, ms)), int(n.value)
+
+
+def _i32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _optd(a):
+    return None if a is None else _dptr(a)
+
+
+class MassSpring:
+    """Native FP64 mass-spring wing solver (include/fsi_ms.h)."""
+
+    def __init__(self, mass):
+        self.lib = load_library()
+        mass = _f64(mass)
+        self.nv = int(mass.shape[0])
+        self.ptr = ctypes.c_void_p()
+        rc = self.lib.fsi_ms_create(self.nv, _dptr(mass), ctypes.byref(self.ptr))
+        if rc != FSI_OK:
+            self.ptr = None
+            raise FsiError(rc, "fsi_ms_create")
+        self.n_ext = 0
+        self.n_bend = 0
+        self.clamped = np.zeros(0, dtype=np.int32)
+
+    def _check(self, rc, what):
+        if rc != FSI_OK:
+            raise FsiError(rc, "%s: %s" % (what, self.lib.fsi_ms_last_error(self.ptr).decode()))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.fsi_ms_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_extension(self, ij, k, l0):
+        ij = _i32(ij, (-1, 2))
+        n = ij.shape[0]
+        first = ctypes.c_int32()
+        self._check(self.lib.fsi_ms_add_extension(self.ptr, n, _iptr(ij), _dptr(_f64(k, (n,))), _dptr(_f64(l0, (n,))),
+                                                  ctypes.byref(first)), "fsi_ms_add_extension")
+        self.n_ext += n
+        return first.value
+
+    def add_bending(self, ijk, kb, theta0):
+        ijk = _i32(ijk, (-1, 3))
+        n = ijk.shape[0]
+        first = ctypes.c_int32()
+        self._check(self.lib.fsi_ms_add_bending(self.ptr, n, _iptr(ijk), _dptr(_f64(kb, (n,))),
+                                                _dptr(_f64(theta0, (n, 2))), ctypes.byref(first)),
+                    "fsi_ms_add_bending")
+        self.n_bend += n
+        return first.value
+
+    def set_extension_k(self, k):
+        self._check(self.lib.fsi_ms_set_extension_k(self.ptr, _dptr(_f64(k, (self.n_ext,)))), "fsi_ms_set_extension_k")
+
+    def set_bending_k(self, kb):
+        self._check(self.lib.fsi_ms_set_bending_k(self.ptr, _dptr(_f64(kb, (self.n_bend,)))), "fsi_ms_set_bending_k")
+
+    def set_clamped(self, idx):
+        idx = _i32(idx, (-1,))
+        self._check(self.lib.fsi_ms_set_clamped(self.ptr, idx.shape[0], _iptr(idx)), "fsi_ms_set_clamped")
+        self.clamped = idx.copy()
+
+    def bending_angles(self, x, frame=None):
+        th = np.zeros((self.n_bend, 2))
+        fr = None if frame is None else _f64(frame, (3, 3))
+        self._check(self.lib.fsi_ms_bending_angles(self.ptr, _dptr(_f64(x, (self.nv, 3))), _optd(fr), _dptr(th)),
+                    "fsi_ms_bending_angles")
+        return th
+
+    def forces(self, x, frame=None):
+        f = np.zeros((self.nv, 3))
+        e = ctypes.c_double()
+        fr = None if frame is None else _f64(frame, (3, 3))
+        self._check(self.lib.fsi_ms_forces(self.ptr, _dptr(_f64(x, (self.nv, 3))), _optd(fr), _dptr(f),
+                                           ctypes.byref(e)), "fsi_ms_forces")
+        return f, e.value
+
+    def set_state(self, x, v=None):
+        vv = None if v is None else _f64(v, (self.nv, 3))
+        self._check(self.lib.fsi_ms_set_state(self.ptr, _dptr(_f64(x, (self.nv, 3))), _optd(vv)), "fsi_ms_set_state")
+
+    def state(self):
+        x = np.zeros((self.nv, 3))
+        v = np.zeros((self.nv, 3))
+        self._check(self.lib.fsi_ms_get_state(self.ptr, _dptr(x), _dptr(v)), "fsi_ms_get_state")
+        return x, v
+
+    def step(self, dt, frame=None, f_ext=None, x_clamp=None, v_clamp=None, tol=1e-6, max_iter=30):
+        nc = len(self.clamped)
+        fr = None if frame is None else _f64(frame, (3, 3))
+        fe = None if f_ext is None else _f64(f_ext, (self.nv, 3))
+        xc = None if x_clamp is None else _f64(x_clamp, (nc, 3))
+        vc = None if v_clamp is None else _f64(v_clamp, (nc, 3))
+        it = ctypes.c_int32()
+        self._check(self.lib.fsi_ms_step(self.ptr, float(dt), _optd(fr), _optd(fe), _optd(xc), _optd(vc), float(tol),
+                                         int(max_iter), ctypes.byref(it)), "fsi_ms_step")
+        return it.value
+
+    def static(self, f_ext, frame=None, load_steps=10, tol=1e-10, max_iter=50):
+        fr = None if frame is None else _f64(frame, (3, 3))
+        self._check(self.lib.fsi_ms_static(self.ptr, _optd(fr), _dptr(_f64(f_ext, (self.nv, 3))), int(load_steps),
+                                           float(tol), int(max_iter)), "fsi_ms_static")

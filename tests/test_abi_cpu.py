@@ -1,6 +1,6 @@
 """Host-side checks of the C-ABI library (no GPU needed).
 
-The library loads and exports every function declared in include/fsi.h;
+The library loads and exports every function declared in include/*.h;
 descriptor validation fails before any device call; the host kinematics
 entry point agrees with the oracle's revolving-plate pose (Sec. 4.2.2)."""
 
@@ -19,9 +19,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "fsi.h")).read()
     decl = r"^\s*(?:fsi_status|int32_t|const char\s*\*)\s*(fsi_[a-z0-9_]+)\s*\("
-    return sorted(set(re.findall(decl, text, flags=re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            names |= set(re.findall(decl, open(os.path.join(ROOT, "include", h)).read(), flags=re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
