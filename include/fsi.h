@@ -74,7 +74,9 @@ typedef struct {
   double h;             /* smoothing half-width h of Eq. (mask_function), > 0 */
   int32_t mask_profile; /* FSI_PROFILE_* */
   int32_t precision;    /* FSI_PREC_* */
-  int32_t reserved;     /* must be 0 */
+  int32_t fsi_pressure; /* 1 = FSI mode: every step keeps its total pressure Pi and the
+                           velocity near the wing for fsi_sample_pressure and
+                           fsi_get_pressure_loads; 0 = off */
   void* stream;         /* hipStream_t to queue work on; NULL = default stream */
 } fsi_desc;
 
@@ -148,6 +150,35 @@ fsi_status fsi_step_adaptive(fsi_ctx* ctx, double cfl, double c_eta, double dt_m
  * Any pointer may be NULL. Synchronizes; FSI_ENAN if a non-finite value was met. */
 fsi_status fsi_get_step_info(fsi_ctx* ctx, double F[3], double* dt_used, double* E,
                              double* umax, double* t, int64_t* nstep);
+
+/* ---- pressure loads on the wing (FSI mode, fsi_pressure = 1) ---------------
+ * Sec. 4.1, pressure interpolation and staggered coupling paragraphs: the
+ * wing is loaded by the fluid pressure p = Pi - |u|^2/2 interpolated onto the
+ * mass points with a delta kernel, each triangle giving its three vertices a
+ * force along its normal of magnitude pressure x area / 3.
+ * Readings: Pi of step n is the pressure of that step's nonlinear term,
+ * Pi_hat = -i k.N'_hat / |k|^2 (N' = u x omega - (chi/eta)(u - u_s) before the
+ * projection; Pi_hat = 0 at k = 0), so p^n pairs with u^n and the mesh of step
+ * n (the structure step n -> n+1 uses p^n).  The delta kernel is the 4-point
+ * kernel phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4r^2))/8 for |r| < 1,
+ * (5 - 2|r| - sqrt(-7 + 12|r| - 4r^2))/8 for 1 <= |r| < 2, per axis in grid
+ * units.  A mid-surface carries no net load from a single pressure, so the
+ * load uses the jump across the wing: with c_v = (1/3) sum over the triangles
+ * T of v of A_T n_T (n_T from the vertex order), n_v = c_v / |c_v| and
+ * d = t_w + h, dp_v = p(x_v + d n_v) - p(x_v - d n_v) and load_v = -dp_v c_v.
+ * The pressure box holds the 4-point stencils of every point within d of the
+ * mesh bounding box (per axis, grid indices floor((lo - d)/dx) - 1 ..
+ * floor((hi + d)/dx) + 2); in FSI mode fsi_set_wing returns FSI_EBOUNDS if it
+ * leaves the grid (no periodic wrap). */
+
+/* p^n of the last step at n points pts[n][3]; FSI_EBOUNDS if a point's
+ * 4 x 4 x 4 stencil leaves the pressure box, FSI_ESTATE if FSI mode is off or
+ * no step ran since fsi_set_wing / fsi_load_state.  Synchronizes. */
+fsi_status fsi_sample_pressure(fsi_ctx* ctx, int32_t n, const double* pts, double* p_out);
+/* Vertex loads load[nv][3] of the current mesh from p^n of the last step (see
+ * above) and, if dp is not NULL, the pressure jumps dp[nv].  Same errors as
+ * fsi_sample_pressure.  Synchronizes. */
+fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp);
 
 /* Stand-alone transforms on the context's grid, for testing the FFT passes.
  * r2c: physical f[nz][ny][nx] -> normalized compact band fhat (interleaved).

@@ -15,6 +15,8 @@ Algorithm of one step n (state: u_hat^n, N_hat^{n-1}, dt_{n-1}, t^n):
  5. dt_n given, or adaptive: min(CFL dx_min / u_max, C_eta eta, dt_max),
     the CFL term being +inf when u_max = 0;
  6. N_hat' = D DFT(G) (2/3 band), N_hat = P N_hat' (Leray projection);
+ 6b. the total pressure of the step, Pi_hat = -i k.N_hat' / |k|^2, and
+    p = Pi - |u|^2/2 are kept for the wing loads (oracle.pressure);
  7. integrating-factor AB2 with variable step (IF-Euler at n = 0):
     u_hat^{n+1} = E_n [u_hat^n + dt_n (1 + xi/2) N_hat^n]
                   - dt_n (xi/2) E_n E_{n-1} N_hat^{n-1},
@@ -33,7 +35,7 @@ static mask equals (dV/eta) U sum chi; adaptive dt matches its closed form.
 
 import numpy as np
 
-from . import dft, spectral, mask as mask_mod
+from . import dft, spectral, pressure, mask as mask_mod
 
 
 class OracleNS:
@@ -55,6 +57,7 @@ class OracleNS:
         self.t = 0.0
         self.nstep = 0
         self.wing = None
+        self.p_last = None  # p = Pi - |u|^2/2 of the last step (oracle.pressure)
 
     # -- state ---------------------------------------------------------------
     def set_velocity(self, u):
@@ -106,6 +109,8 @@ class OracleNS:
             "umax": float(np.sqrt(np.max(speed2))),
         }
         nh = spectral.dealias(dft.forward(g), self.n)
+        # pressure of this step (FSI coupling): Pi from the unprojected term
+        self.p_last = pressure.pressure_field(pressure.total_pressure_hat(nh, self.n, self.L), u)
         nh = spectral.project(nh, self.n, self.L)
         return nh, diag
 

@@ -143,6 +143,16 @@ fsi_status fsi_get_step_info(fsi_ctx* ctx, double F[3], double* dt_used, double*
   return st;
 }
 
+fsi_status fsi_sample_pressure(fsi_ctx* ctx, int32_t n, const double* pts, double* p_out) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->sample_pressure(n, pts, p_out);
+}
+
+fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->pressure_loads(loads, dp);
+}
+
 fsi_status fsi_fft_r2c(fsi_ctx* ctx, const double* f, double* fhat) {
   if (guard(ctx) != FSI_OK || !f || !fhat) return FSI_EINVAL;
   return ctx->eng->fft_r2c(f, fhat);

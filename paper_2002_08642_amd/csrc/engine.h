@@ -34,6 +34,8 @@ class EngineBase {
   virtual fsi_status adjoint_get(double* lu, double* lnp) = 0;
   virtual fsi_status step_adjoint(int slot, double dt, double dtp, int first, const double dJdF[3], double* dJdx,
                                   double* dJdv) = 0;
+  virtual fsi_status sample_pressure(int n, const double* pts, double* p) = 0;
+  virtual fsi_status pressure_loads(double* loads, double* dp) = 0;
   virtual fsi_status set_timing(bool on) = 0;
   virtual fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) = 0;
   std::string err;

@@ -69,7 +69,7 @@ std::string check_desc(const fsi_desc& d) {
   if (!(d.h > 0) || !std::isfinite(d.h)) return "h must be > 0";
   if (d.mask_profile != FSI_PROFILE_COS && d.mask_profile != FSI_PROFILE_TANH) return "unknown mask profile";
   if (d.precision != FSI_PREC_FP32 && d.precision != FSI_PREC_FP64) return "unknown precision";
-  if (d.reserved != 0) return "reserved field must be 0";
+  if (d.fsi_pressure != 0 && d.fsi_pressure != 1) return "fsi_pressure must be 0 or 1";
   return "";
 }
 
@@ -137,6 +137,10 @@ class Engine : public EngineBase {
     FSI_TRY(make_twiddles(nz, &twz));
     FSI_HIP(hipMemsetAsync(uh, 0, sizeof(cpx<T>) * 3 * clen, s));
     FSI_HIP(hipMemsetAsync(nh, 0, sizeof(cpx<T>) * 3 * clen, s));
+    if (d.fsi_pressure) {
+      FSI_TRY(alloc(&pi_, clen));
+      FSI_HIP(hipMemsetAsync(pi_, 0, sizeof(cpx<T>) * clen, s));
+    }
     FSI_TRY(reset_scalars());
     FSI_HIP(hipStreamSynchronize(s));
     slots.resize(64);
@@ -233,6 +237,8 @@ class Engine : public EngineBase {
     if (nt == 0) {
       wing_nt = 0;
       bnx = bny = bnz = 0;
+      pnx = pny = pnz = 0;
+      p_ready = false;
       return FSI_OK;
     }
     for (long long i = 0; i < 3LL * nt; ++i)
@@ -265,6 +271,47 @@ class Engine : public EngineBase {
       cnt[q] = std::max(0, i1 - i0[q] + 1);
     }
     const long long cells = (long long)cnt[0] * cnt[1] * cnt[2];
+    // FSI mode: pressure box (every 4-point stencil of a point within d = t_w + h
+    // of the mesh bounding box), vertex load vectors and sample points
+    int q0[3] = {0, 0, 0}, qn[3] = {0, 0, 0};
+    std::vector<double> cv, samp;
+    if (d.fsi_pressure) {
+      const double dd = d.tw + d.h;
+      for (int q = 0; q < 3; ++q) {
+        const int a = (int)std::floor((lo[q] - dd) / dxs[q]) - 1;
+        const int b = (int)std::floor((hi[q] + dd) / dxs[q]) + 2;
+        if (a < 0 || b > Ns[q] - 1) {
+          err = "pressure box (mesh bounding box enlarged by t_w + h and the delta-kernel stencil) leaves the box";
+          return FSI_EBOUNDS;
+        }
+        q0[q] = a;
+        qn[q] = b - a + 1;
+      }
+      cv.assign(3 * (size_t)nv, 0.0);
+      for (long long t = 0; t < nt; ++t) {
+        const int* v3 = tri + 3 * t;
+        double e1[3], e2[3];
+        for (int q = 0; q < 3; ++q) {
+          e1[q] = x[3 * v3[1] + q] - x[3 * v3[0] + q];
+          e2[q] = x[3 * v3[2] + q] - x[3 * v3[0] + q];
+        }
+        // A_T n_T / 3 = (e1 x e2) / 6
+        const double c[3] = {(e1[1] * e2[2] - e1[2] * e2[1]) / 6.0, (e1[2] * e2[0] - e1[0] * e2[2]) / 6.0,
+                             (e1[0] * e2[1] - e1[1] * e2[0]) / 6.0};
+        for (int k = 0; k < 3; ++k)
+          for (int q = 0; q < 3; ++q) cv[3 * (size_t)v3[k] + q] += c[q];
+      }
+      samp.assign(6 * (size_t)nv, 0.0);
+      for (long long i = 0; i < nv; ++i) {
+        const double* c = &cv[3 * i];
+        const double nrm = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int q = 0; q < 3; ++q) {
+          const double off = nrm > 0.0 ? dd * c[q] / nrm : 0.0;
+          samp[6 * i + q] = x[3 * i + q] + off;
+          samp[6 * i + 3 + q] = x[3 * i + q] - off;
+        }
+      }
+    }
     // stage the mesh through pinned memory
     const size_t need = sizeof(double) * 6 * (size_t)nv + sizeof(int) * 3 * (size_t)nt;
     if (need > stage_cap) {
@@ -293,6 +340,23 @@ class Engine : public EngineBase {
       FSI_TRY(alloc(&dv_, 3LL * mesh_vcap));
       FSI_TRY(alloc(&dtri_, 3LL * mesh_tcap));
     }
+    if (d.fsi_pressure) {
+      const long long pc = (long long)qn[0] * qn[1] * qn[2];
+      if (pc > pbox_cap) {
+        FSI_HIP(hipStreamSynchronize(s));
+        free_dev(up_);
+        pbox_cap = pc + pc / 4 + 64;
+        FSI_TRY(alloc(&up_, 3 * pbox_cap));
+      }
+      if (2LL * nv > psamp_cap) {
+        FSI_HIP(hipStreamSynchronize(s));
+        free_dev(dsamp_);
+        free_dev(dpout_);
+        psamp_cap = 4LL * nv;
+        FSI_TRY(alloc(&dsamp_, 3 * psamp_cap));
+        FSI_TRY(alloc(&dpout_, psamp_cap));
+      }
+    }
     if (cells > box_cap) {
       FSI_HIP(hipStreamSynchronize(s));
       free_dev(key1);
@@ -320,6 +384,109 @@ class Engine : public EngineBase {
     bny = cnt[1];
     bnz = cnt[2];
     bcells = cells;
+    if (d.fsi_pressure) {
+      px0 = q0[0];
+      py0 = q0[1];
+      pz0 = q0[2];
+      pnx = qn[0];
+      pny = qn[1];
+      pnz = qn[2];
+      pcells = (long long)pnx * pny * pnz;
+      load_cv.swap(cv);
+      samp_host.swap(samp);
+    }
+    p_ready = false;
+    return FSI_OK;
+  }
+
+  // -- pressure samples and wing loads (FSI mode) ----------------------------------
+  fsi_status pressure_ready() {
+    if (!d.fsi_pressure) {
+      err = "FSI mode (fsi_pressure) is off";
+      return FSI_ESTATE;
+    }
+    if (!p_ready || wing_nt == 0 || pcells == 0) {
+      err = "no step since the wing was set or the state was loaded";
+      return FSI_ESTATE;
+    }
+    return FSI_OK;
+  }
+
+  // p = Pi - |u|^2/2 at n points (host FP64 [n][3]) into out[n]
+  fsi_status run_psample(int n, const double* pts_host, double* out) {
+    for (int i = 0; i < n; ++i)
+      for (int q = 0; q < 3; ++q) {
+        const int pq0 = q == 0 ? px0 : (q == 1 ? py0 : pz0), pqn = q == 0 ? pnx : (q == 1 ? pny : pnz);
+        const double g = pts_host[3 * i + q] / dxs[q];
+        if (!std::isfinite(g)) {
+          err = "non-finite sample point";
+          return FSI_EINVAL;
+        }
+        const int a = (int)std::floor(g) - 1;
+        if (a < pq0 || a + 3 > pq0 + pqn - 1) {
+          err = "sample stencil leaves the pressure box";
+          return FSI_EBOUNDS;
+        }
+      }
+    if (n == 0) return FSI_OK;
+    if (!phys) FSI_TRY(alloc(&phys, 3 * npts));
+    if (n > psamp_cap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      free_dev(dsamp_);
+      free_dev(dpout_);
+      psamp_cap = 2LL * n;
+      FSI_TRY(alloc(&dsamp_, 3 * psamp_cap));
+      FSI_TRY(alloc(&dpout_, psamp_cap));
+    }
+    FSI_TRY(run_inverse(pi_, clen, 1, phys));  // Pi on the grid
+    FSI_HIP(hipMemcpyAsync(dsamp_, pts_host, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    PressArgs<T> a;
+    a.pi = phys;
+    a.up = up_;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.px0 = px0;
+    a.py0 = py0;
+    a.pz0 = pz0;
+    a.pnx = pnx;
+    a.pny = pny;
+    a.pnz = pnz;
+    a.pcells = pcells;
+    a.pts = dsamp_;
+    a.ns = n;
+    a.dx = dxs[0];
+    a.dy = dxs[1];
+    a.dz = dxs[2];
+    a.out = dpout_;
+    FSI_HIP(launch_psample<T>(a, s));
+    FSI_HIP(hipMemcpyAsync(out, dpout_, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
+  fsi_status sample_pressure(int n, const double* pts, double* p) override {
+    if (n < 0 || (n > 0 && (!pts || !p))) {
+      err = "invalid sample arrays";
+      return FSI_EINVAL;
+    }
+    FSI_TRY(pressure_ready());
+    return run_psample(n, pts, p);
+  }
+
+  fsi_status pressure_loads(double* loads, double* dp) override {
+    if (!loads) {
+      err = "loads is NULL";
+      return FSI_EINVAL;
+    }
+    FSI_TRY(pressure_ready());
+    std::vector<double> p(2 * (size_t)wing_nv);
+    FSI_TRY(run_psample(2 * wing_nv, samp_host.data(), p.data()));
+    for (int i = 0; i < wing_nv; ++i) {
+      const double jump = p[2 * i] - p[2 * i + 1];
+      if (dp) dp[i] = jump;
+      for (int q = 0; q < 3; ++q) loads[3 * i + q] = -jump * load_cv[3 * (size_t)i + q];
+    }
     return FSI_OK;
   }
 
@@ -408,6 +575,16 @@ class Engine : public EngineBase {
         a.bny = bny;
         a.bnz = bnz;
         a.bcells = bcells;
+        if (d.fsi_pressure) {
+          a.up = up_;
+          a.px0 = px0;
+          a.py0 = py0;
+          a.pz0 = pz0;
+          a.pnx = pnx;
+          a.pny = pny;
+          a.pnz = pnz;
+          a.pcells = pcells;
+        }
       }
       a.inv_eta = (T)(1.0 / d.eta);
       FSI_HIP(launch_xfused<T>(a, nfused, s));
@@ -456,12 +633,14 @@ class Engine : public EngineBase {
       a.first = have_prev ? 0 : 1;
       a.nu = (T)d.nu;
       a.scale = (T)(1.0 / (double)npts);
+      a.pi = d.fsi_pressure ? pi_ : nullptr;
       FSI_HIP(launch_col<T>(COL_FWD_UPDATE, a, 1, s));
     }
     if (ev) FSI_HIP(hipEventRecord(ev[7], s));
     FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     ++nstep;
     have_prev = true;
+    p_ready = d.fsi_pressure && wing_nt > 0 && bcells > 0;
     return FSI_OK;
   }
 
@@ -545,6 +724,7 @@ class Engine : public EngineBase {
     FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     nstep = sl.nstep;
     have_prev = sl.have_prev;
+    p_ready = false;
     return FSI_OK;
   }
 
@@ -862,6 +1042,10 @@ class Engine : public EngineBase {
     free_dev(tgrad_);
     free_dev(chi);
     free_dev(us);
+    free_dev(pi_);
+    free_dev(up_);
+    free_dev(dsamp_);
+    free_dev(dpout_);
     for (Slot& sl : slots) {
       free_dev(sl.uh);
       free_dev(sl.nh);
@@ -1147,6 +1331,14 @@ class Engine : public EngineBase {
   double* tgrad_ = nullptr;
   int tgrad_cap = 0;
   T *chi = nullptr, *us = nullptr;
+  // FSI mode: Pi_hat of the last step, u on the pressure box, sample points
+  cpx<T>* pi_ = nullptr;
+  T* up_ = nullptr;
+  double *dsamp_ = nullptr, *dpout_ = nullptr;
+  long long pbox_cap = 0, psamp_cap = 0, pcells = 0;
+  int px0 = 0, py0 = 0, pz0 = 0, pnx = 0, pny = 0, pnz = 0;
+  std::vector<double> load_cv, samp_host;
+  bool p_ready = false;
   // stepping
   long long nstep = 0;
   bool have_prev = false;

@@ -64,6 +64,7 @@ struct ColArgs {
   int cur;    // parity index of dt_n
   int first;  // 1: integrating-factor Euler step
   T nu;
+  cpx<T>* pi;  // update pass: total pressure Pi_hat = -i k.N'/|k|^2 (compact), NULL = not kept
 };
 
 template <typename T>
@@ -86,6 +87,25 @@ struct XArgs {
   long long bcells;
   T inv_eta;
   double* partials;   // [gridDim.x][8]
+  // velocity kept on the pressure box (FSI mode), [3][cell]; pnx = 0: off
+  T* up;
+  int px0, py0, pz0, pnx, pny, pnz;
+  long long pcells;
+};
+
+// Sampling of p = Pi - |u|^2 / 2 with the 4-point delta kernel: Pi on the full
+// grid ([z][y][x]), u on the pressure box, points in FP64.
+template <typename T>
+struct PressArgs {
+  const T* pi;
+  const T* up;
+  int nx, ny, nz;
+  int px0, py0, pz0, pnx, pny, pnz;
+  long long pcells;
+  const double* pts;  // [ns][3]
+  int ns;
+  double dx, dy, dz;
+  double* out;        // [ns]
 };
 
 // The mask geometry is evaluated in FP64 in both precisions (it is a small

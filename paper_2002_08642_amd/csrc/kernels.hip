@@ -237,14 +237,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
           cpx<T> n0 = st[0][k], n1 = st[1][k];
           cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
           const T k2 = kx * kx + ky * ky + kz * kz;
+          const long long idx = (long long)i * a.ld + c;
           if (k2 > (T)0) {
             const T ik2 = (T)1 / k2;
             cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
             n0 = n0 - scl(sp, kx);
             n1 = n1 - scl(sp, ky);
             n2 = n2 - scl(sp, kz);
+            if constexpr (MODE == COL_FWD_UPDATE) {
+              if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
+            }
+          } else if constexpr (MODE == COL_FWD_UPDATE) {
+            if (a.pi) a.pi[idx] = mk<T>(0, 0);
           }
-          const long long idx = (long long)i * a.ld + c;
           if constexpr (MODE == COL_FWD_PROJECT) {
             a.out[idx] = n0;
             a.out[a.cfs + idx] = n1;
@@ -377,6 +382,17 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
             }
           }
         }
+        if (a.pnx > 0) {
+          const int line = line0 + l;
+          const int z = line / a.ny, y = line - z * a.ny;
+          const int qx = x - a.px0, qy = y - a.py0, qz = z - a.pz0;
+          if (qx >= 0 && qx < a.pnx && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {
+            const long long cell = ((long long)qz * a.pny + qy) * a.pnx + qx;
+            a.up[cell] = ux;
+            a.up[a.pcells + cell] = uy;
+            a.up[2 * a.pcells + cell] = uz;
+          }
+        }
         const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         aE += u2;
         aM = fmax(aM, u2);
@@ -485,6 +501,19 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
     aM = fmax(aM, u2);
   }
   const int z = line / a.ny, y = line - z * a.ny;
+  const int qy = y - a.py0, qz = z - a.pz0;
+  if (a.pnx > 0 && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {  // uniform per wave
+    const long long rowcell = ((long long)qz * a.pny + qy) * a.pnx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int qx = (lane >> 3) + 8 * (lane & 7) + 64 * j - a.px0;
+      if (qx >= 0 && qx < a.pnx) {
+        a.up[rowcell + qx] = P[0][j].re;
+        a.up[a.pcells + rowcell + qx] = P[0][j].im;
+        a.up[2 * a.pcells + rowcell + qx] = P[1][j].re;
+      }
+    }
+  }
   const int by = y - a.by0, bz = z - a.bz0;
   if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
     const long long rowcell = ((long long)bz * a.bny + by) * a.bnx;
@@ -772,6 +801,60 @@ __global__ __launch_bounds__(kNT) void mask_eval(MaskArgs<T> a) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// pressure samples for the wing loads (FSI mode)
+// ---------------------------------------------------------------------------
+
+// 4-point delta kernel (Peskin's), phi(r) for |r| < 2 in grid units: it
+// reproduces constants and linear functions and splits evenly between even
+// and odd grid points.
+__device__ __forceinline__ double delta4(double r) {
+  r = fabs(r);
+  if (r < 1.0) return 0.125 * (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r));
+  if (r < 2.0) return 0.125 * (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r));
+  return 0.0;
+}
+
+// One thread per point: p(X) = sum over the 4 x 4 x 4 grid points around X of
+// phi phi phi (Pi - |u|^2 / 2); the host guarantees every stencil lies in the
+// pressure box.
+template <typename T>
+__global__ __launch_bounds__(kNT) void pressure_sample(PressArgs<T> a) {
+  const int sidx = blockIdx.x * kNT + threadIdx.x;
+  if (sidx >= a.ns) return;
+  const double g[3] = {a.pts[3 * sidx] / a.dx, a.pts[3 * sidx + 1] / a.dy, a.pts[3 * sidx + 2] / a.dz};
+  int i0[3];
+  double w[3][4];
+  for (int q = 0; q < 3; ++q) {
+    i0[q] = (int)floor(g[q]) - 1;
+    for (int m = 0; m < 4; ++m) w[q][m] = delta4(g[q] - (double)(i0[q] + m));
+  }
+  double acc = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int z = i0[2] + c;
+    for (int b = 0; b < 4; ++b) {
+      const int y = i0[1] + b;
+      const double wzy = w[2][c] * w[1][b];
+      for (int m = 0; m < 4; ++m) {
+        const int x = i0[0] + m;
+        const long long cell = ((long long)(z - a.pz0) * a.pny + (y - a.py0)) * a.pnx + (x - a.px0);
+        const double ux = (double)a.up[cell], uy = (double)a.up[a.pcells + cell],
+                     uz = (double)a.up[2 * a.pcells + cell];
+        const double pi = (double)a.pi[((long long)z * a.ny + y) * a.nx + x];
+        acc += wzy * w[0][m] * (pi - 0.5 * (ux * ux + uy * uy + uz * uz));
+      }
+    }
+  }
+  a.out[sidx] = acc;
+}
+
+template <typename T>
+hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s) {
+  if (a.ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pressure_sample<T>, dim3((a.ns + kNT - 1) / kNT), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename K>
 static hipError_t set_lds(K kernel, size_t lds) {
   if (lds > 65536) return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -921,6 +1004,8 @@ template hipError_t launch_xfused<float>(const XArgs<float>&, int, hipStream_t);
 template hipError_t launch_xfused<double>(const XArgs<double>&, int, hipStream_t);
 template hipError_t launch_xplain<float>(int, int, const XArgs<float>&, int, hipStream_t);
 template hipError_t launch_xplain<double>(int, int, const XArgs<double>&, int, hipStream_t);
+template hipError_t launch_psample<float>(const PressArgs<float>&, hipStream_t);
+template hipError_t launch_psample<double>(const PressArgs<double>&, hipStream_t);
 template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);
 template hipError_t launch_mask<double>(const MaskArgs<double>&, hipStream_t);
 

@@ -57,6 +57,8 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 int xfused_grid(int n, long long nlines, int lines_per_group);
 template <typename T>
 hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
 
 template <typename T>
 hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s);

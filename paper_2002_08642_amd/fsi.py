@@ -36,6 +36,7 @@ EXPORTS = [
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
+    "fsi_sample_pressure", "fsi_get_pressure_loads",
 ]
 
 
@@ -52,7 +53,7 @@ class Desc(ctypes.Structure):
         ("nu", ctypes.c_double), ("eta", ctypes.c_double),
         ("tw", ctypes.c_double), ("h", ctypes.c_double),
         ("mask_profile", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("fsi_pressure", ctypes.c_int32), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -102,6 +103,8 @@ def load_library():
     lib.fsi_step_adjoint.argtypes = [P, I32, ctypes.c_double, ctypes.c_double, I32, D, D, D]
     lib.fsi_plate_pose_dalpha.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, I32, D, D]
+    lib.fsi_sample_pressure.argtypes = [P, I32, D, D]
+    lib.fsi_get_pressure_loads.argtypes = [P, D, D]
     lib.fsi_ms_create.argtypes = [I32, D, ctypes.POINTER(P)]
     lib.fsi_ms_destroy.argtypes = [P]
     lib.fsi_ms_last_error.argtypes = [P]
@@ -169,12 +172,13 @@ def plate_pose_dalpha(s, c, t, alpha, omega, t_ramp, law=0):
 class Solver:
     """One context of the penalized pseudo-spectral step (see include/fsi.h)."""
 
-    def __init__(self, n, L, nu, eta, tw=0.0, h=1.0, profile=PROFILE_COS, precision=PREC_FP32, stream=None):
+    def __init__(self, n, L, nu, eta, tw=0.0, h=1.0, profile=PROFILE_COS, precision=PREC_FP32, stream=None,
+                 pressure=False):
         self.lib = load_library()
         self.n = tuple(int(a) for a in n)
         nx, ny, nz = self.n
         d = Desc(nx, ny, nz, float(L[0]), float(L[1]), float(L[2]), float(nu), float(eta), float(tw),
-                 float(h), int(profile), int(precision), 0, stream)
+                 float(h), int(profile), int(precision), 1 if pressure else 0, stream)
         ctx = ctypes.c_void_p()
         rc = self.lib.fsi_create(ctypes.byref(d), ctypes.byref(ctx))
         if rc != FSI_OK:
@@ -278,6 +282,20 @@ class Solver:
     def clear_wing(self):
         self._check(self.lib.fsi_set_wing(self.ctx, 0, None, None, 0, None))
         self._nv = 0
+
+    def sample_pressure(self, pts):
+        """p = Pi - |u|^2/2 of the last step at points (n, 3) (fsi_sample_pressure)."""
+        pts = _f64(pts).reshape(-1, 3)
+        out = np.zeros(pts.shape[0])
+        self._check(self.lib.fsi_sample_pressure(self.ctx, pts.shape[0], _dptr(pts), _dptr(out)))
+        return out
+
+    def pressure_loads(self):
+        """Vertex loads (nv, 3) and pressure jumps (nv,) of the current mesh (fsi_get_pressure_loads)."""
+        loads = np.zeros((self._nv, 3))
+        dp = np.zeros(self._nv)
+        self._check(self.lib.fsi_get_pressure_loads(self.ctx, _dptr(loads), _dptr(dp)))
+        return loads, dp
 
     def mask(self):
         chi = np.zeros(self.shape3)
