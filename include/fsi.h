@@ -228,6 +228,14 @@ fsi_status fsi_step_adjoint(fsi_ctx* ctx, int32_t tape_slot, double dt, double d
 fsi_status fsi_plate_pose_dalpha(int32_t nv, const double* s, const double* c, double t, double alpha,
                                  double omega, double t_ramp, int32_t law, double* dxda, double* dvda);
 
+/* Wing frame of the revolving plate of fsi_plate_pose at time t (host, FP64):
+ * frame[3][3] row-major with the span, chord and normal directions as columns,
+ * Rz(phi(t)) applied to (1, 0, 0), (0, cos alpha, sin alpha) and
+ * (0, -sin alpha, cos alpha); phi_out[2] (may be NULL) = (phi, dphi/dt).  The
+ * frame in which the mass-spring wing measures its bending angles. */
+fsi_status fsi_plate_frame(double t, double alpha, double omega, double t_ramp, int32_t law, double* frame,
+                           double* phi_out);
+
 /* Wait for all queued work of the context. */
 fsi_status fsi_synchronize(fsi_ctx* ctx);
 

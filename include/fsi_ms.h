@@ -45,16 +45,30 @@ const char* fsi_ms_last_error(const fsi_ms* ms);
 fsi_status fsi_ms_add_extension(fsi_ms* ms, int32_t n, const int32_t* ij, const double* k, const double* l0,
                                 int32_t* first);
 /* Append n bending springs on vertex triples ijk[n][3] (segments i->j and
- * j->k), stiffness kb[n] >= 0 and rest angles theta0[n][2] = (theta^y_0,
- * theta^z_0).  *first as above. */
+ * j->k), stiffness kb[n] >= 0 and rest angles theta0[n][2].  axis[n] (NULL =
+ * all 0) is the wing axis the spring lies along: Eq. two_bending_angles
+ * projects on the wing planes (x, y) and (x, z), which suits springs along x
+ * (axis 0); a spring along wing axis a uses the planes (a, a+1) and (a, a+2),
+ * cyclically (a reading: the paper's veins all run spanwise).  *first as above. */
 fsi_status fsi_ms_add_bending(fsi_ms* ms, int32_t n, const int32_t* ijk, const double* kb, const double* theta0,
-                              int32_t* first);
+                              const int32_t* axis, int32_t* first);
 /* Replace the stiffness of all extension springs (k[n_ext]) or bending springs
  * (kb[n_bend]); the topology is unchanged. */
 fsi_status fsi_ms_set_extension_k(fsi_ms* ms, const double* k);
 fsi_status fsi_ms_set_bending_k(fsi_ms* ms, const double* kb);
 /* Mark n vertices idx[n] as clamped: their motion is prescribed at every step. */
 fsi_status fsi_ms_set_clamped(fsi_ms* ms, int32_t n, const int32_t* idx);
+
+/* Rest lengths of all extension springs and rest angles of all bending springs
+ * (in `frame`, NULL = identity) taken from the current positions. */
+fsi_status fsi_ms_set_rest(fsi_ms* ms, const double* frame);
+/* k^b of Eq. EI_k_relation for a vein of length l_b (> 0) carrying n (>= 1)
+ * bending springs, from its flexural rigidity EI (>= 0). */
+fsi_status fsi_ms_bending_stiffness(double EI, double l_b, int32_t n, double* kb);
+/* Lumped masses mass[nv]: areal density (> 0) times one third of the area of
+ * each triangle tri[nt][3] of positions x[nv][3], summed per vertex. */
+fsi_status fsi_ms_lumped_masses(int32_t nv, const double* x, int32_t nt, const int32_t* tri, double density,
+                                double* mass);
 
 /* Projected bending angles theta[n_bend][2] of positions x[nv][3] in the given
  * frame (Eq. two_bending_angles). */

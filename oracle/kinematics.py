@@ -59,6 +59,17 @@ def plate_pose(s, c, t, alpha, omega, t_ramp, axis_point, law=LAW_RAMP):
     return x, v
 
 
+def plate_frame(t, alpha, omega, t_ramp, law=LAW_RAMP):
+    """Wing frame of the revolving plate at time t: columns span, chord and
+    normal directions, Rz(phi) applied to (1, 0, 0), (0, cos a, sin a) and
+    (0, -sin a, cos a) (the pitched plate of plate_pose)."""
+    phi, _ = angle_and_rate(t, omega, t_ramp, law)
+    cp, sp = np.cos(phi), np.sin(phi)
+    rot = np.array([[cp, -sp, 0.0], [sp, cp, 0.0], [0.0, 0.0, 1.0]])
+    pitch = np.array([[1.0, 0.0, 0.0], [0.0, np.cos(alpha), -np.sin(alpha)], [0.0, np.sin(alpha), np.cos(alpha)]])
+    return rot @ pitch
+
+
 def motion_direction(phi):
     """Unit vector of the plate's motion at angle phi: e_z x e_span."""
     return np.array([-np.sin(phi), np.cos(phi), 0.0])

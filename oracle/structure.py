@@ -15,6 +15,9 @@ structure model that the library's native solver is checked against.
 * Bending springs (Sec. 2.2, Eqs. bending_spring_moment, two_bending_angles):
   two projected angles theta^y (Oxy plane) and theta^z (Oxz plane) between the
   segments i->j and j->k, measured in the wing frame.  Reading: the printed
+  angles suit springs along the wing x axis; a spring along wing axis a uses
+  the planes (a, a+1) and (a, a+2) (cyclic), a = 0 being the printed case.
+  Reading: the printed
   force formula omits the 1/length factors of the angle's gradient, so the
   force is taken as the exact negative gradient of the energy
   k^b/2 [(theta^y - theta^y_0)^2 + (theta^z - theta^z_0)^2]; its moment is the
@@ -36,18 +39,21 @@ import numpy as np
 class Network:
     """Mass points with extension and bending springs.
 
-    mass: (n,) ; ext: rows (i, j, k, l0) ; bend: rows (i, j, k, kb, th0y, th0z);
+    mass: (n,) ; ext: rows (i, j, k, l0) ; bend: rows (i, j, k, kb, th0y, th0z)
+    or (i, j, k, kb, th0_1, th0_2, axis) for a spring along wing axis ``axis``;
     clamped: indices of points whose motion is prescribed.
     """
 
     def __init__(self, mass, ext=(), bend=(), clamped=()):
         self.mass = np.asarray(mass, dtype=np.float64)
         ext = np.asarray(ext, dtype=np.float64).reshape(-1, 4)
-        bend = np.asarray(bend, dtype=np.float64).reshape(-1, 6)
+        bend = [tuple(b) + (0,) * (7 - len(b)) for b in bend]
+        bend = np.asarray(bend, dtype=np.float64).reshape(-1, 7)
         self.ext_ij = ext[:, :2].astype(np.int64)
         self.ext_k, self.ext_l0 = ext[:, 2].copy(), ext[:, 3].copy()
         self.bend_ijk = bend[:, :3].astype(np.int64)
         self.bend_kb, self.bend_th0 = bend[:, 3].copy(), bend[:, 4:6].copy()
+        self.bend_axis = bend[:, 6].astype(np.int64)
         self.clamped = np.array(sorted(set(int(c) for c in clamped)), dtype=np.int64)
 
     @property
@@ -73,17 +79,22 @@ def projected_angle(a, b):
     return th, ga, gb
 
 
-def _segments(x, ijk, frame):
-    """Segments i->j and j->k of every bending spring in wing coordinates."""
+def _segments(x, ijk, frame, axis):
+    """Segments i->j and j->k of every bending spring in wing coordinates,
+    cyclically permuted so that component 0 is the spring's own wing axis."""
     a = (x[ijk[:, 1]] - x[ijk[:, 0]]) @ frame
     b = (x[ijk[:, 2]] - x[ijk[:, 1]]) @ frame
-    return a, b
+    perm = (np.asarray(axis)[:, None] + np.arange(3)[None, :]) % 3
+    rows = np.arange(len(a))[:, None]
+    return a[rows, perm], b[rows, perm], perm
 
 
-def bending_angles(x, ijk, frame):
+def bending_angles(x, ijk, frame, axis=None):
     """(theta^y, theta^z) of Eq. two_bending_angles, (m, 2), for points x given
     in the inertial frame; ``frame`` (3x3) has the wing axes as columns."""
-    a, b = _segments(x, np.asarray(ijk).reshape(-1, 3), frame)
+    ijk = np.asarray(ijk).reshape(-1, 3)
+    axis = np.zeros(len(ijk), dtype=np.int64) if axis is None else np.asarray(axis)
+    a, b, _ = _segments(x, ijk, frame, axis)
     ty, _, _ = projected_angle(a[:, [0, 1]], b[:, [0, 1]])
     tz, _, _ = projected_angle(a[:, [0, 2]], b[:, [0, 2]])
     return np.stack([ty, tz], axis=-1)
@@ -94,7 +105,7 @@ def energy(net, x, frame):
     L = np.linalg.norm(x[net.ext_ij[:, 1]] - x[net.ext_ij[:, 0]], axis=1)
     e = 0.5 * np.sum(net.ext_k * (L - net.ext_l0) ** 2)
     if len(net.bend_kb):
-        th = bending_angles(x, net.bend_ijk, frame)
+        th = bending_angles(x, net.bend_ijk, frame, net.bend_axis)
         e += 0.5 * np.sum(net.bend_kb[:, None] * (th - net.bend_th0) ** 2)
     return e
 
@@ -110,7 +121,7 @@ def internal_forces(net, x, frame):
     np.add.at(f, j, -fi)
     if len(net.bend_kb):
         ijk = net.bend_ijk
-        a, b = _segments(x, ijk, frame)
+        a, b, perm = _segments(x, ijk, frame, net.bend_axis)
         ga3 = np.zeros_like(a)
         gb3 = np.zeros_like(b)
         for col, (p, q) in enumerate(((0, 1), (0, 2))):
@@ -118,9 +129,14 @@ def internal_forces(net, x, frame):
             m = net.bend_kb * (th - net.bend_th0[:, col])  # dE/dtheta
             ga3[:, [p, q]] += m[:, None] * ga
             gb3[:, [p, q]] += m[:, None] * gb
-        # back to the inertial frame; a = x_j - x_i, b = x_k - x_j
-        ga3 = ga3 @ frame.T
-        gb3 = gb3 @ frame.T
+        # undo the permutation, back to the inertial frame; a = x_j - x_i, b = x_k - x_j
+        rows = np.arange(len(a))[:, None]
+        gaw = np.zeros_like(ga3)
+        gbw = np.zeros_like(gb3)
+        gaw[rows, perm] = ga3
+        gbw[rows, perm] = gb3
+        ga3 = gaw @ frame.T
+        gb3 = gbw @ frame.T
         np.add.at(f, ijk[:, 0], ga3)
         np.add.at(f, ijk[:, 1], gb3 - ga3)
         np.add.at(f, ijk[:, 2], -gb3)
@@ -245,3 +261,26 @@ def cantilever(n, l_b, EI, ke, mass=1.0):
     ext = [(i, i + 1, ke, ds) for i in range(npts - 1)]
     bend = [(i - 1, i, i + 1, kb, 0.0, 0.0) for i in range(1, npts - 1)]
     return Network(np.full(npts, mass), ext, bend, clamped=(0, 1)), x
+
+
+def lumped_masses(x, tri, density):
+    """Mass of each point: areal density x one third of the area of its triangles
+    (reading of the wing's mass distribution for a uniform membrane)."""
+    x = np.asarray(x, dtype=np.float64)
+    m = np.zeros(len(x))
+    for t in np.asarray(tri):
+        area = 0.5 * np.linalg.norm(np.cross(x[t[1]] - x[t[0]], x[t[2]] - x[t[0]]))
+        m[t] += density * area / 3.0
+    return m
+
+
+def rest_network(mass, x, ext_ij, ext_k, bend_ijk, bend_kb, bend_axis, clamped, frame):
+    """Network at rest in configuration x: rest lengths and rest angles from x."""
+    x = np.asarray(x, dtype=np.float64)
+    ext_ij = np.asarray(ext_ij).reshape(-1, 2)
+    l0 = np.linalg.norm(x[ext_ij[:, 1]] - x[ext_ij[:, 0]], axis=1)
+    bend_ijk = np.asarray(bend_ijk).reshape(-1, 3)
+    th0 = bending_angles(x, bend_ijk, frame, bend_axis)
+    ext = [(i, j, k, l) for (i, j), k, l in zip(ext_ij, ext_k, l0)]
+    bend = [(i, j, k, kb, t[0], t[1], a) for (i, j, k), kb, t, a in zip(bend_ijk, bend_kb, th0, bend_axis)]
+    return Network(mass, ext, bend, clamped)

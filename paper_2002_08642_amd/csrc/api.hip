@@ -252,6 +252,25 @@ fsi_status fsi_plate_pose(int32_t nv, const double* s, const double* c, double t
   return FSI_OK;
 }
 
+fsi_status fsi_plate_frame(double t, double alpha, double omega, double t_ramp, int32_t law, double* frame,
+                           double* phi_out) {
+  if (!frame) return FSI_EINVAL;
+  // the pose of a vertex at span 1, chord 0 gives phi and its rate
+  const double one = 1.0, zero = 0.0, axis0[3] = {0.0, 0.0, 0.0};
+  double xs[3], vs[3], ph[2];
+  const fsi_status st = fsi_plate_pose(1, &one, &zero, t, alpha, omega, t_ramp, law, axis0, xs, vs, ph);
+  if (st != FSI_OK) return st;
+  const double cp = cos(ph[0]), sp = sin(ph[0]), ca = cos(alpha), sa = sin(alpha);
+  const double cols[3][3] = {{cp, sp, 0.0}, {-sp * ca, cp * ca, sa}, {sp * sa, -cp * sa, ca}};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) frame[3 * r + c] = cols[c][r];
+  if (phi_out) {
+    phi_out[0] = ph[0];
+    phi_out[1] = ph[1];
+  }
+  return FSI_OK;
+}
+
 // Derivative of the rigid plate pose with respect to the pitch alpha: the pose
 // x = axis + Rz(phi) (s, c cos alpha, c sin alpha) gives dx/dalpha = Rz(phi)
 // (0, -c sin alpha, c cos alpha) and v = dphi/dt e_z x (x - axis) gives

@@ -16,9 +16,10 @@
 // Springs (Sec. 2.2): extension E = k/2 (|x_j - x_i| - l0)^2; bending
 // E = k^b/2 sum_{p in {y,z}} (theta^p - theta^p_0)^2 with theta^p the angle
 // from segment a = x_j - x_i to b = x_k - x_j projected on the wing-frame
-// plane (x, p) (Eq. two_bending_angles).  That angle is the difference of the
-// polar angles of the projections, theta = phi(b) - phi(a), which gives the
-// gradient and Hessian in closed form.
+// plane (x, p) (Eq. two_bending_angles); a spring lying along wing axis
+// `axis` uses the planes (axis, axis+1) and (axis, axis+2), cyclically.  The
+// angle is the difference of the polar angles of the projections,
+// theta = phi(b) - phi(a), which gives the gradient and Hessian in closed form.
 #include <math.h>
 #include <string.h>
 
@@ -93,7 +94,7 @@ struct fsi_ms {
   std::vector<double> mass;
   std::vector<int> ei, ej;
   std::vector<double> ek, el0;
-  std::vector<int> bi, bj, bk;
+  std::vector<int> bi, bj, bk, bax;
   std::vector<double> bkb, bt0;  // bt0: [nb][2]
   std::vector<int> clamped;      // in the order given
   std::vector<int> is_clamped;
@@ -168,10 +169,14 @@ double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bo
     const V3 a = to_wing(F, {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]});
     const V3 b = to_wing(F, {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]});
     const double kb = ms.bkb[s];
-    double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};  // dE/da, dE/db (wing frame)
-    double Hab[6][6];                             // d2E/d(a,b)^2 (wing frame)
+    const int ax = ms.bax[s];
+    double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};  // dE/da, dE/db (permuted wing frame)
+    double Hab[6][6];                             // d2E/d(a,b)^2 (permuted wing frame)
     memset(Hab, 0, sizeof(Hab));
-    const double av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    const double aw[3] = {a.x, a.y, a.z}, bw[3] = {b.x, b.y, b.z};
+    // component c of the permuted frame is wing component (ax + c) mod 3
+    const double av[3] = {aw[ax], aw[(ax + 1) % 3], aw[(ax + 2) % 3]};
+    const double bv[3] = {bw[ax], bw[(ax + 1) % 3], bw[(ax + 2) % 3]};
     for (int p = 0; p < 2; ++p) {
       const int q = p + 1;  // projection on the wing plane (x, q): q = y, then z
       const double ra = av[0] * av[0] + av[q] * av[q], rb = bv[0] * bv[0] + bv[q] * bv[q];
@@ -210,8 +215,14 @@ double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bo
           }
       }
     }
+    // back to wing components
+    double gaw[3], gbw[3];
+    for (int c = 0; c < 3; ++c) {
+      gaw[(ax + c) % 3] = ga[c];
+      gbw[(ax + c) % 3] = gb[c];
+    }
     if (f) {
-      const V3 Ga = to_inertial(F, ga), Gb = to_inertial(F, gb);
+      const V3 Ga = to_inertial(F, gaw), Gb = to_inertial(F, gbw);
       // a = x_j - x_i, b = x_k - x_j:  f_i = F ga, f_j = F (gb - ga), f_k = -F gb
       const double A[3] = {Ga.x, Ga.y, Ga.z}, B[3] = {Gb.x, Gb.y, Gb.z};
       for (int c = 0; c < 3; ++c) {
@@ -221,14 +232,19 @@ double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bo
       }
     }
     if (hess) {
-      // rotate to the inertial frame: G = diag(F, F) Hab diag(F^T, F^T)
+      // undo the permutation, then rotate to the inertial frame:
+      // G = diag(F, F) Hw diag(F^T, F^T)
+      double Hw[6][6];
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c)
+          Hw[(r / 3) * 3 + (ax + r % 3) % 3][(c / 3) * 3 + (ax + c % 3) % 3] = Hab[r][c];
       double G[6][6];
       for (int r = 0; r < 6; ++r)
         for (int c = 0; c < 6; ++c) {
           const int rb0 = (r / 3) * 3, cb0 = (c / 3) * 3, rr = r % 3, cc = c % 3;
           double sum = 0.0;
           for (int m = 0; m < 3; ++m)
-            for (int n = 0; n < 3; ++n) sum += F[3 * rr + m] * Hab[rb0 + m][cb0 + n] * F[3 * cc + n];
+            for (int n = 0; n < 3; ++n) sum += F[3 * rr + m] * Hw[rb0 + m][cb0 + n] * F[3 * cc + n];
           G[r][c] = sum;
         }
       // x_i -> (-I, 0), x_j -> (I, -I), x_k -> (0, I)
@@ -373,7 +389,7 @@ fsi_status fsi_ms_add_extension(fsi_ms* ms, int32_t n, const int32_t* ij, const 
 }
 
 fsi_status fsi_ms_add_bending(fsi_ms* ms, int32_t n, const int32_t* ijk, const double* kb, const double* theta0,
-                              int32_t* first) {
+                              const int32_t* axis, int32_t* first) {
   if (!ms) return FSI_EINVAL;
   if (n < 0 || (n > 0 && (!ijk || !kb || !theta0))) return fail(ms, FSI_EINVAL, "bad bending spring arrays");
   for (int s = 0; s < n; ++s) {
@@ -382,6 +398,7 @@ fsi_status fsi_ms_add_bending(fsi_ms* ms, int32_t n, const int32_t* ijk, const d
     if (ijk[3 * s] == ijk[3 * s + 1] || ijk[3 * s + 1] == ijk[3 * s + 2])
       return fail(ms, FSI_EINVAL, "bending spring segments must have distinct ends");
     if (!(kb[s] >= 0.0)) return fail(ms, FSI_EINVAL, "bending stiffness must be >= 0");
+    if (axis && (axis[s] < 0 || axis[s] > 2)) return fail(ms, FSI_EINVAL, "bending axis must be 0, 1 or 2");
   }
   if (first) *first = (int32_t)ms->bkb.size();
   for (int s = 0; s < n; ++s) {
@@ -389,6 +406,7 @@ fsi_status fsi_ms_add_bending(fsi_ms* ms, int32_t n, const int32_t* ijk, const d
     ms->bj.push_back(ijk[3 * s + 1]);
     ms->bk.push_back(ijk[3 * s + 2]);
     ms->bkb.push_back(kb[s]);
+    ms->bax.push_back(axis ? axis[s] : 0);
     ms->bt0.push_back(theta0[2 * s]);
     ms->bt0.push_back(theta0[2 * s + 1]);
   }
@@ -436,12 +454,64 @@ fsi_status fsi_ms_bending_angles(const fsi_ms* ms, const double* x, const double
     const int vi = ms->bi[s], vj = ms->bj[s], vk = ms->bk[s];
     const V3 a = to_wing(F, {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]});
     const V3 b = to_wing(F, {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]});
-    const double av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    const double aw[3] = {a.x, a.y, a.z}, bw[3] = {b.x, b.y, b.z};
+    const int ax = ms->bax[s];
+    const double av[3] = {aw[ax], aw[(ax + 1) % 3], aw[(ax + 2) % 3]};
+    const double bv[3] = {bw[ax], bw[(ax + 1) % 3], bw[(ax + 2) % 3]};
     for (int p = 0; p < 2; ++p) {
       const int q = p + 1;
       // Eq. two_bending_angles: atan2 of the cross and dot products of the projections
       theta[2 * s + p] = atan2(av[0] * bv[q] - bv[0] * av[q], av[0] * bv[0] + av[q] * bv[q]);
     }
+  }
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_rest(fsi_ms* ms, const double* frame) {
+  if (!ms) return FSI_EINVAL;
+  const double* x = ms->x.data();
+  for (size_t s = 0; s < ms->ek.size(); ++s) {
+    const int i = ms->ei[s], j = ms->ej[s];
+    const double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(L > 0.0)) return fail(ms, FSI_EINVAL, "extension spring of zero length in the rest state");
+  }
+  std::vector<double> th(2 * ms->bkb.size());
+  const fsi_status st = fsi_ms_bending_angles(ms, x, frame, th.data());
+  if (st != FSI_OK) return st;
+  for (size_t s = 0; s < ms->ek.size(); ++s) {
+    const int i = ms->ei[s], j = ms->ej[s];
+    const double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+    ms->el0[s] = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  }
+  ms->bt0 = th;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_bending_stiffness(double EI, double l_b, int32_t n, double* kb) {
+  if (!kb || !(EI >= 0.0) || !(l_b > 0.0) || n < 1) return FSI_EINVAL;
+  // Eq. EI_k_relation: equal bending energy of a cantilever of length l_b and of
+  // n + 2 mass points (the first two clamped) under a tip force
+  *kb = EI / l_b * (double)n * (2.0 * n + 1.0) / (2.0 * (n + 1.0));
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_lumped_masses(int32_t nv, const double* x, int32_t nt, const int32_t* tri, double density,
+                                double* mass) {
+  if (nv < 1 || nt < 0 || !x || !mass || (nt > 0 && !tri) || !(density > 0.0)) return FSI_EINVAL;
+  for (int t = 0; t < 3 * nt; ++t)
+    if (tri[t] < 0 || tri[t] >= nv) return FSI_EINVAL;
+  memset(mass, 0, sizeof(double) * nv);
+  for (int t = 0; t < nt; ++t) {
+    const int* v = tri + 3 * t;
+    double e1[3], e2[3];
+    for (int q = 0; q < 3; ++q) {
+      e1[q] = x[3 * v[1] + q] - x[3 * v[0] + q];
+      e2[q] = x[3 * v[2] + q] - x[3 * v[0] + q];
+    }
+    const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double area = 0.5 * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    for (int k = 0; k < 3; ++k) mass[v[k]] += density * area / 3.0;
   }
   return FSI_OK;
 }

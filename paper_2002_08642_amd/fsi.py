@@ -30,6 +30,7 @@ EXPORTS = [
     "fsi_ms_create", "fsi_ms_destroy", "fsi_ms_last_error", "fsi_ms_add_extension", "fsi_ms_add_bending",
     "fsi_ms_set_extension_k", "fsi_ms_set_bending_k", "fsi_ms_set_clamped", "fsi_ms_bending_angles",
     "fsi_ms_forces", "fsi_ms_set_state", "fsi_ms_get_state", "fsi_ms_step", "fsi_ms_static",
+    "fsi_ms_set_rest", "fsi_ms_bending_stiffness", "fsi_ms_lumped_masses", "fsi_plate_frame",
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
     "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
@@ -110,7 +111,11 @@ def load_library():
     lib.fsi_ms_last_error.argtypes = [P]
     lib.fsi_ms_last_error.restype = ctypes.c_char_p
     lib.fsi_ms_add_extension.argtypes = [P, I32, ctypes.POINTER(I32), D, D, ctypes.POINTER(I32)]
-    lib.fsi_ms_add_bending.argtypes = [P, I32, ctypes.POINTER(I32), D, D, ctypes.POINTER(I32)]
+    lib.fsi_ms_add_bending.argtypes = [P, I32, ctypes.POINTER(I32), D, D, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.fsi_ms_set_rest.argtypes = [P, D]
+    lib.fsi_ms_bending_stiffness.argtypes = [ctypes.c_double, ctypes.c_double, I32, D]
+    lib.fsi_ms_lumped_masses.argtypes = [I32, D, I32, ctypes.POINTER(I32), ctypes.c_double, D]
+    lib.fsi_plate_frame.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, D, D]
     lib.fsi_ms_set_extension_k.argtypes = [P, D]
     lib.fsi_ms_set_bending_k.argtypes = [P, D]
     lib.fsi_ms_set_clamped.argtypes = [P, I32, ctypes.POINTER(I32)]
@@ -406,12 +411,14 @@ class MassSpring:
         self.n_ext += n
         return first.value
 
-    def add_bending(self, ijk, kb, theta0):
+    def add_bending(self, ijk, kb, theta0=None, axis=None):
         ijk = _i32(ijk, (-1, 3))
         n = ijk.shape[0]
         first = ctypes.c_int32()
-        self._check(self.lib.fsi_ms_add_bending(self.ptr, n, _iptr(ijk), _dptr(_f64(kb, (n,))),
-                                                _dptr(_f64(theta0, (n, 2))), ctypes.byref(first)),
+        th = np.zeros((n, 2)) if theta0 is None else _f64(theta0, (n, 2))
+        ax = None if axis is None else _i32(axis, (n,))
+        self._check(self.lib.fsi_ms_add_bending(self.ptr, n, _iptr(ijk), _dptr(_f64(kb, (n,))), _dptr(th),
+                                                None if ax is None else _iptr(ax), ctypes.byref(first)),
                     "fsi_ms_add_bending")
         self.n_bend += n
         return first.value
@@ -421,6 +428,10 @@ class MassSpring:
 
     def set_bending_k(self, kb):
         self._check(self.lib.fsi_ms_set_bending_k(self.ptr, _dptr(_f64(kb, (self.n_bend,)))), "fsi_ms_set_bending_k")
+
+    def set_rest(self, frame=None):
+        fr = None if frame is None else _f64(frame, (3, 3))
+        self._check(self.lib.fsi_ms_set_rest(self.ptr, _optd(fr)), "fsi_ms_set_rest")
 
     def set_clamped(self, idx):
         idx = _i32(idx, (-1,))
@@ -467,3 +478,34 @@ class MassSpring:
         fr = None if frame is None else _f64(frame, (3, 3))
         self._check(self.lib.fsi_ms_static(self.ptr, _optd(fr), _dptr(_f64(f_ext, (self.nv, 3))), int(load_steps),
                                            float(tol), int(max_iter)), "fsi_ms_static")
+
+
+def bending_stiffness(EI, l_b, n):
+    """k^b from the flexural rigidity (fsi_ms_bending_stiffness)."""
+    kb = ctypes.c_double()
+    rc = load_library().fsi_ms_bending_stiffness(float(EI), float(l_b), int(n), ctypes.byref(kb))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_ms_bending_stiffness")
+    return kb.value
+
+
+def lumped_masses(x, tri, density):
+    """Per-vertex masses from triangle areas (fsi_ms_lumped_masses)."""
+    x = _f64(x).reshape(-1, 3)
+    tri = _i32(tri, (-1, 3))
+    m = np.zeros(x.shape[0])
+    rc = load_library().fsi_ms_lumped_masses(x.shape[0], _dptr(x), tri.shape[0], _iptr(tri), float(density), _dptr(m))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_ms_lumped_masses")
+    return m
+
+
+def plate_frame(t, alpha, omega, t_ramp, law=0):
+    """Wing frame (3x3, columns span/chord/normal) of the revolving plate (fsi_plate_frame)."""
+    fr = np.zeros((3, 3))
+    ph = np.zeros(2)
+    rc = load_library().fsi_plate_frame(float(t), float(alpha), float(omega), float(t_ramp), int(law), _dptr(fr),
+                                        _dptr(ph))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_plate_frame")
+    return fr

@@ -39,3 +39,14 @@ def test_pose_is_rigid_and_velocity_is_time_derivative():
         assert np.allclose(rel[:, 2], c * np.sin(cfg["alpha"]))
     x0, v0 = kin.plate_pose(s, c, 0.0, *args)
     assert np.all(v0 == 0.0)
+
+
+def test_plate_frame_maps_local_coordinates_to_the_pose():
+    rng = np.random.default_rng(3)
+    s, c = rng.random(10) * 3.0, rng.random(10) - 0.5
+    axis = np.array([6.0, 6.0, 6.0])
+    for t in (0.0, 0.13, 0.9):
+        F = kin.plate_frame(t, 0.6, 2 * np.pi, 0.4)
+        x, _ = kin.plate_pose(s, c, t, 0.6, 2 * np.pi, 0.4, axis)
+        assert np.allclose(x, axis + np.stack([s, c, 0 * s], 1) @ F.T, atol=1e-14)
+        assert np.allclose(F.T @ F, np.eye(3), atol=1e-15) and np.linalg.det(F) > 0

@@ -3,7 +3,8 @@ the paper fix.
 
 * Forces are the exact negative gradient of the energy (central differences),
   internal forces sum to zero, and the extension force is the printed one.
-* Projected bending angles of a planar polyline are its turning angles.
+* Projected bending angles of a planar polyline are its turning angles; a
+  spring along another wing axis measures its angles in the permuted planes.
 * Small-deflection cantilever: with k^b from the EI relation the tip deflection
   is F l^3 / (3 EI) (Euler-Bernoulli), the identity the relation is built on.
 * Large deflection: the printed table (tests/golden) - the network's tip
@@ -30,8 +31,8 @@ def random_network(seed, n=7):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal((n, 3))
     ext = [(i, i + 1, 1.0 + rng.random(), 0.8 + 0.4 * rng.random()) for i in range(n - 1)] + [(0, 3, 2.0, 1.0)]
-    bend = [(i - 1, i, i + 1, 0.5 + rng.random(), 0.1 * rng.standard_normal(), 0.1 * rng.standard_normal())
-            for i in range(1, n - 1)]
+    bend = [(i - 1, i, i + 1, 0.5 + rng.random(), 0.1 * rng.standard_normal(), 0.1 * rng.standard_normal(),
+             i % 3) for i in range(1, n - 1)]  # springs along each wing axis
     q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
     return st.Network(1.0 + rng.random(n), ext, bend), x, q
 
@@ -64,6 +65,14 @@ def test_extension_force_is_the_printed_law():
     f = st.internal_forces(net, x, np.eye(3))
     assert np.allclose(f[0], 3.0 * (L - 0.5) * d / L, atol=1e-15)
     assert np.allclose(f[1], -f[0], atol=1e-15)
+
+
+def test_axis_of_a_bending_spring_permutes_the_projection_planes():
+    # a polyline along wing y, bent in the (y, z) plane, measured as an axis-1 spring
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 2.0, 0.3]])
+    th = st.bending_angles(x, [(0, 1, 2)], np.eye(3), axis=[1])
+    assert th[0, 0] == pytest.approx(np.arctan2(0.3, 1.0), abs=1e-15)  # plane (y, z)
+    assert th[0, 1] == pytest.approx(0.0, abs=1e-15)                    # plane (y, x)
 
 
 def test_projected_angles_of_planar_polyline_are_turning_angles():

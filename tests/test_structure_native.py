@@ -24,9 +24,10 @@ def rot(axis, ang):
     return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
 
 
-def plate_network(ns=7, nc=4, seed=0, span=1.0, chord=0.4):
+def plate_network(ns=7, nc=4, seed=0, span=1.0, chord=0.4, chordwise=False):
     """A small plate: membrane extension springs on a grid with diagonals,
-    spanwise bending springs on every chordwise row, root column clamped."""
+    spanwise bending springs on every chordwise row (and, if chordwise, springs
+    along wing y on every spanwise column), root column clamped."""
     rng = np.random.default_rng(seed)
     s = np.linspace(0, span, ns)
     c = np.linspace(-chord / 2, chord / 2, nc)
@@ -43,6 +44,10 @@ def plate_network(ns=7, nc=4, seed=0, span=1.0, chord=0.4):
     trip = [(idx(i - 1, j), idx(i, j), idx(i + 1, j)) for j in range(nc) for i in range(1, ns - 1)]
     th0 = st.bending_angles(x, trip, np.eye(3))
     bend = [(a, b, cc, 0.05 * (1 + rng.random()), t[0], t[1]) for (a, b, cc), t in zip(trip, th0)]
+    if chordwise:
+        ctrip = [(idx(i, j - 1), idx(i, j), idx(i, j + 1)) for i in range(ns) for j in range(1, nc - 1)]
+        cth0 = st.bending_angles(x, ctrip, np.eye(3), axis=np.ones(len(ctrip), int))
+        bend += [(a, b, cc, 0.08 * (1 + rng.random()), t[0], t[1], 1) for (a, b, cc), t in zip(ctrip, cth0)]
     mass = 0.01 * (1 + rng.random(ns * nc))
     clamped = [idx(0, j) for j in range(nc)]
     return mass, ext, bend, clamped, x
@@ -52,14 +57,15 @@ def native(mass, ext, bend, clamped):
     ms = fsi.MassSpring(mass)
     e = np.array(ext)
     ms.add_extension(e[:, :2], e[:, 2], e[:, 3])
-    b = np.array(bend)
-    ms.add_bending(b[:, :3], b[:, 3], b[:, 4:6])
+    b = np.array([tuple(r) + (0,) * (7 - len(r)) for r in bend], dtype=float)
+    ms.add_bending(b[:, :3], b[:, 3], b[:, 4:6], b[:, 6])
     ms.set_clamped(sorted(clamped))
     return ms
 
 
-def test_forces_energy_and_angles_match_oracle():
-    mass, ext, bend, clamped, x0 = plate_network(seed=1)
+@pytest.mark.parametrize("chordwise", [False, True])
+def test_forces_energy_and_angles_match_oracle(chordwise):
+    mass, ext, bend, clamped, x0 = plate_network(seed=1, chordwise=chordwise)
     rng = np.random.default_rng(3)
     net = st.Network(mass, ext, bend, clamped)
     ms = native(mass, ext, bend, clamped)
@@ -70,11 +76,12 @@ def test_forces_energy_and_angles_match_oracle():
         fo = st.internal_forces(net, x, F)
         assert np.max(np.abs(f - fo)) <= 1e-12 * np.max(np.abs(fo))
         assert e == pytest.approx(st.energy(net, x, F), rel=1e-13)
-        assert np.allclose(ms.bending_angles(x, F), st.bending_angles(x, net.bend_ijk, F), atol=1e-14)
+        assert np.allclose(ms.bending_angles(x, F), st.bending_angles(x, net.bend_ijk, F, net.bend_axis), atol=1e-14)
 
 
-def test_bdf2_steps_match_oracle():
-    mass, ext, bend, clamped, x0 = plate_network(seed=2)
+@pytest.mark.parametrize("chordwise", [False, True])
+def test_bdf2_steps_match_oracle(chordwise):
+    mass, ext, bend, clamped, x0 = plate_network(seed=2, chordwise=chordwise)
     clamped = sorted(clamped)
     net = st.Network(mass, ext, bend, clamped)
     ms = native(mass, ext, bend, clamped)
@@ -157,3 +164,30 @@ def test_error_paths():
         ms.step(0.1, tol=1e-15, max_iter=1)  # cannot converge in one iteration
     assert e.value.code == -5
     assert np.array_equal(ms.state()[0], x_before)  # unchanged on failure
+
+
+def test_rest_state_stiffness_masses_and_frame_helpers():
+    mass, ext, bend, clamped, x0 = plate_network(seed=5, chordwise=True)
+    rng = np.random.default_rng(6)
+    F = rot(rng.standard_normal(3), 0.7)
+    x = x0 @ F.T + 0.01 * rng.standard_normal(x0.shape)
+    e = np.array(ext)
+    b = np.array([tuple(r) + (0,) * (7 - len(r)) for r in bend], dtype=float)
+    ms = fsi.MassSpring(mass)
+    ms.add_extension(e[:, :2], e[:, 2], np.ones(len(e)))
+    ms.add_bending(b[:, :3], b[:, 3], None, b[:, 6])
+    ms.set_state(x)
+    ms.set_rest(F)
+    net = st.rest_network(mass, x, e[:, :2].astype(int), e[:, 2], b[:, :3].astype(int), b[:, 3],
+                          b[:, 6].astype(int), [], F)
+    f, en = ms.forces(x, F)
+    assert en < 1e-24 and np.max(np.abs(f)) < 1e-10  # at rest in its own configuration
+    xp = x + 0.02 * rng.standard_normal(x.shape)
+    assert np.allclose(ms.forces(xp, F)[0], st.internal_forces(net, xp, F), rtol=0, atol=1e-12)
+    assert fsi.bending_stiffness(0.24, 0.3, 64) == pytest.approx(st.bending_stiffness(0.24, 0.3, 64), rel=1e-15)
+    tri = np.array([[0, 1, 8], [1, 9, 8], [5, 6, 12]])
+    assert np.allclose(fsi.lumped_masses(x, tri, 1e-3), st.lumped_masses(x, tri, 1e-3), rtol=1e-14, atol=0)
+    from oracle import kinematics
+    for t in (0.0, 0.1, 0.5):
+        assert np.allclose(fsi.plate_frame(t, 0.7, 2 * np.pi, 0.4), kinematics.plate_frame(t, 0.7, 2 * np.pi, 0.4),
+                           atol=1e-15)
