@@ -245,3 +245,113 @@ def revolving_plate(n=128, box=12.0, fixed_eta=None, t_ramp=0.4):
                 axis_point=(box / 2, box / 2, box / 2),
                 span_coord=s, chord_coord=c, tri=grid_triangles(ns, nc),
                 cfl=0.1, c_eta=2.0 / 3.0, dt_max=1e-2)
+
+
+# ---------------------------------------------------------------------------
+# flexible wings (mass-spring networks): geometry, topology and seeded draws
+# ---------------------------------------------------------------------------
+
+def _grid_edges(ns, nc):
+    """Vertex pairs of the triangle edges of grid_triangles: spanwise, chordwise
+    and the (i, j)-(i+1, j+1) diagonals."""
+    e = []
+    for j in range(nc):
+        for i in range(ns):
+            v = j * ns + i
+            if i + 1 < ns:
+                e.append((v, v + 1))
+            if j + 1 < nc:
+                e.append((v, v + ns))
+            if i + 1 < ns and j + 1 < nc:
+                e.append((v, v + ns + 1))
+    return np.array(e, dtype=np.int32)
+
+
+def structure_units(omega=2 * math.pi, span=3.0):
+    """Factor converting structure stiffnesses given in units with unit tip speed
+    into the fluid units used here (one revolution per time unit): forces scale
+    with the square of the tip speed, so stiffness x (omega span)^2."""
+    return (omega * span) ** 2
+
+
+def flexible_wing(ns=31, nc=16, n_veins=8, vein_nodes=25, span=3.0, chord=1.0, seed=0,
+                  EI_range=(1e-3, 1e-1), k_membrane_range=(1e-4, 1e-2), k_vein=1.0, density=1e-3):
+    """Membrane of ns x nc vertices over span x chord with veins on every other
+    chordwise row (rows 0, 2, ..., 2 (n_veins - 1)), each vein the first
+    vein_nodes spanwise vertices of its row.  Draws (numpy default_rng(seed)):
+    one EI per vein, log-uniform in EI_range, and one stiffness per membrane
+    spring, log-uniform in k_membrane_range; vein edges have stiffness k_vein.
+    Stiffnesses are returned in fluid units (structure_units()).  The first two
+    spanwise columns are clamped to the root motion."""
+    rng = np.random.default_rng(seed)
+    s, c = plate_span_chord(ns, nc, span, chord)
+    tri = grid_triangles(ns, nc)
+    edges = _grid_edges(ns, nc)
+    scale = structure_units(span=span)
+    lo, hi = np.log(EI_range[0]), np.log(EI_range[1])
+    EI = np.exp(lo + (hi - lo) * rng.random(n_veins)) * scale
+    klo, khi = np.log(k_membrane_range[0]), np.log(k_membrane_range[1])
+    k = np.exp(klo + (khi - klo) * rng.random(len(edges))) * scale
+    rows = [2 * v for v in range(n_veins)]
+    vein_edge = set()
+    for r in rows:
+        for i in range(vein_nodes - 1):
+            vein_edge.add((r * ns + i, r * ns + i + 1))
+    for e, (a, b) in enumerate(edges):
+        if (int(a), int(b)) in vein_edge:
+            k[e] = k_vein * scale
+    veins = [np.array([r * ns + i for i in range(vein_nodes)], dtype=np.int32) for r in rows]
+    clamped = np.array([j * ns + i for j in range(nc) for i in (0, 1)], dtype=np.int32)
+    return dict(span_coord=s, chord_coord=c, tri=tri, ext_ij=edges, ext_k=k, veins=veins, vein_EI=EI,
+                vein_length=span / (ns - 1) * (vein_nodes - 1), clamped=clamped, density=density)
+
+
+def vein_bending(wing):
+    """Bending triples (axis 0) of the veins and the vein each belongs to: every
+    interior vein node carries one spring (n = vein_nodes - 2 per vein)."""
+    ijk, owner = [], []
+    for v, nodes in enumerate(wing["veins"]):
+        for m in range(1, len(nodes) - 1):
+            ijk.append((nodes[m - 1], nodes[m], nodes[m + 1]))
+            owner.append(v)
+    return np.array(ijk, dtype=np.int32), np.array(owner, dtype=np.int32)
+
+
+HINGE_COLUMNS = (2, 10, 20, 30)
+
+
+def hinge_plate(ns=41, nc=13, span=3.0, chord=1.0, k_hinge=(1e-2, 1e-2, 1e-2, 1e-2), k_ext=1e2, density=1e-3,
+                hinge_columns=HINGE_COLUMNS):
+    """Plate of four spanwise segments joined by hinges: extension springs on
+    all triangle edges (k_ext), spanwise bending springs (axis 0) at every
+    interior column of every chordwise row and chordwise bending springs
+    (axis 1) at every interior row of every spanwise column.  Spanwise springs
+    at hinge column hinge_columns[g] have stiffness k_hinge[g] (group g); all
+    other bending springs are rigid, 1e3 max(k_hinge) (group -1).  Columns 0 and
+    1 are clamped.  Stiffnesses in fluid units (structure_units())."""
+    scale = structure_units(span=span)
+    s, c = plate_span_chord(ns, nc, span, chord)
+    tri = grid_triangles(ns, nc)
+    edges = _grid_edges(ns, nc)
+    k_rigid = 1e3 * max(k_hinge)
+    ijk, axis, group, kb = [], [], [], []
+    for j in range(nc):
+        for i in range(1, ns - 1):
+            v = j * ns + i
+            ijk.append((v - 1, v, v + 1))
+            axis.append(0)
+            g = hinge_columns.index(i) if i in hinge_columns else -1
+            group.append(g)
+            kb.append((k_hinge[g] if g >= 0 else k_rigid) * scale)
+    for i in range(ns):
+        for j in range(1, nc - 1):
+            v = j * ns + i
+            ijk.append((v - ns, v, v + ns))
+            axis.append(1)
+            group.append(-1)
+            kb.append(k_rigid * scale)
+    clamped = np.array([j * ns + i for j in range(nc) for i in (0, 1)], dtype=np.int32)
+    return dict(span_coord=s, chord_coord=c, tri=tri, ext_ij=edges, ext_k=np.full(len(edges), k_ext * scale),
+                bend_ijk=np.array(ijk, dtype=np.int32), bend_axis=np.array(axis, dtype=np.int32),
+                bend_group=np.array(group, dtype=np.int32), bend_kb=np.array(kb), clamped=clamped,
+                density=density, scale=scale)

@@ -1,0 +1,85 @@
+"""GPU parity of the staggered fluid-structure coupling against the oracle.
+
+A small flexible wing (11 x 6 membrane, 3 veins of 9 nodes, EI and membrane
+stiffness drawn as in the flexible-wing recipe, areal density 1) revolving in a
+48^3 box of side 12: fluid step on the GPU (FSI mode), pressure loads, native
+BDF2/Newton structure step - against oracle.coupling (numpy fluid, FD-Jacobian
+Newton structure).  Tolerances relative to the largest value: FP64 1e-9
+(positions, velocities, forces); FP32 fluid 1e-4 (forces and deflections carry
+the FP32 rounding of the loads through the structure).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import structure as st
+from oracle.coupling import CoupledOracle
+from paper_2002_08642_amd import fsi
+from paper_2002_08642_amd.coupled import FlexibleWingFSI
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {fsi.PREC_FP64: 1e-9, fsi.PREC_FP32: 1e-4}
+
+
+def small_case(n=48, density=1.0):
+    cfg = synth.revolving_plate(n=n, t_ramp=0.05)
+    w = synth.flexible_wing(ns=11, nc=6, n_veins=3, vein_nodes=9, density=density)
+    ijk, owner = synth.vein_bending(w)
+    kin = dict(alpha=cfg["alpha"], omega=cfg["omega"], t_ramp=cfg["t_ramp"], axis_point=cfg["axis_point"])
+    return cfg, w, ijk, owner, kin
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_coupled_flexible_wing_matches_oracle(prec):
+    cfg, w, ijk, owner, kin = small_case()
+    kb_o = np.array([st.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
+    kb_g = np.array([fsi.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
+    axis = np.zeros(len(ijk), dtype=np.int32)
+    o = CoupledOracle(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], w, ijk, kb_o,
+                      axis, kin)
+    s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec,
+                   pressure=True)
+    s.set_velocity(np.zeros((3,) + cfg["n"]))
+    g = FlexibleWingFSI(s, w, ijk, kb_g, axis, kin, tol=1e-12)
+    fo, fg = [], []
+    for k in range(10):
+        fo.append(o.step(2e-3))
+        fg.append(g.step(2e-3))
+    x, v = g.state()
+    xr, _ = o._root_pose(o.t, None)
+    ex, ev, ef = rel(x - xr, o.q[0] - xr), rel(v, o.q[1]), rel(fg, fo)
+    print("coupled prec %d: deflection %.3e velocity %.3e force %.3e (max deflection %.3e, Newton its %s)"
+          % (prec, ex, ev, ef, np.max(np.abs(o.q[0] - xr)), g.iters), flush=True)
+    assert ex < TOL[prec] and ev < TOL[prec] and ef < TOL[prec]
+    assert max(g.iters) <= 8
+
+
+def test_full_flexible_wing_fp32_follows_fp64():
+    """The config-2 wing (31 x 16 membrane, 8 veins of 25 nodes) at 96^3: the
+    FP32 fluid with the FP64 structure follows the FP64 run."""
+    cfg = synth.revolving_plate(n=96, t_ramp=0.05)
+    w = synth.flexible_wing(density=1.0)
+    ijk, owner = synth.vein_bending(w)
+    kb = np.array([fsi.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
+    kin = dict(alpha=cfg["alpha"], omega=cfg["omega"], t_ramp=cfg["t_ramp"], axis_point=cfg["axis_point"])
+    runs = {}
+    for prec in (fsi.PREC_FP64, fsi.PREC_FP32):
+        s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec,
+                       pressure=True)
+        s.set_velocity(np.zeros((3,) + cfg["n"]))
+        g = FlexibleWingFSI(s, w, ijk, kb, np.zeros(len(ijk), np.int32), kin, tol=1e-10)
+        F = [g.step(1e-3) for _ in range(12)]
+        runs[prec] = (g.state()[0], np.array(F), g)
+    x64, F64, g64 = runs[fsi.PREC_FP64]
+    x32, F32, _ = runs[fsi.PREC_FP32]
+    xr, _ = g64._root_pose(g64.t, None)
+    ed, ef = rel(x32 - xr, x64 - xr), rel(F32, F64)
+    print("config-2 wing 96^3: FP32 vs FP64 deflection %.3e force %.3e (max deflection %.3e)"
+          % (ed, ef, np.max(np.abs(x64 - xr))), flush=True)
+    assert ed < 1e-4 and ef < 1e-4
