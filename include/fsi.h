@@ -236,6 +236,10 @@ fsi_status fsi_plate_pose_dalpha(int32_t nv, const double* s, const double* c, d
 fsi_status fsi_plate_frame(double t, double alpha, double omega, double t_ramp, int32_t law, double* frame,
                            double* phi_out);
 
+/* d frame / d alpha of fsi_plate_frame (host, FP64): Rz(phi(t)) applied to
+ * (0, 0, 0), (0, -sin alpha, cos alpha), (0, -cos alpha, -sin alpha). */
+fsi_status fsi_plate_frame_dalpha(double t, double alpha, double omega, double t_ramp, int32_t law, double* dframe);
+
 /* Wait for all queued work of the context. */
 fsi_status fsi_synchronize(fsi_ctx* ctx);
 

@@ -94,6 +94,46 @@ fsi_status fsi_ms_get_state(const fsi_ms* ms, double* x, double* v);
 fsi_status fsi_ms_step(fsi_ms* ms, double dt, const double* frame, const double* f_ext, const double* x_clamp,
                        const double* v_clamp, double tol, int32_t max_iter, int32_t* iters);
 
+/* Restore the BDF2 history (positions and velocities at t^{n-1} and the
+ * previous dt) for recomputing a step from a stored state; x_prev = NULL
+ * clears it (the next step is implicit Euler). */
+fsi_status fsi_ms_set_history(fsi_ms* ms, const double* x_prev, const double* v_prev, double dt_prev);
+
+/* Transpose of one fsi_ms_step (the map (q^n, q^{n-1}, f_ext, stiffnesses,
+ * clamp values, frame) -> q^{n+1}, at its converged solution).  Given the
+ * cotangents lam_x, lam_v [nv][3] of x^{n+1}, v^{n+1} (those of clamped
+ * vertices included), it solves the transposed Newton system, whose matrix
+ * M + (gamma dt)^2 H(x^{n+1}) is the symmetric Newton matrix of the step, and
+ * ADDS the cotangents of: x^n, v^n (lam_xn, lam_vn), x^{n-1}, v^{n-1} (lam_xp,
+ * lam_vp; nothing is added when dt_prev <= 0, the implicit-Euler step),
+ * f_ext (lam_load [nv][3]), each extension and bending stiffness
+ * (lam_kext[n_ext], lam_kb[n_bend]), the prescribed clamp positions and
+ * velocities (lam_clamp_x/v [n_clamped][3]), and a frame moving along dframe
+ * (3x3, d frame / d parameter; lam_dframe scalar).  Any output may be NULL.
+ * x_new = x^{n+1}; dt, dt_prev and frame as in the forward step.  The solver's
+ * state is not used or changed (only its masses, springs and clamps). */
+fsi_status fsi_ms_step_adjoint(fsi_ms* ms, double dt, double dt_prev, const double* frame, const double* dframe,
+                               const double* x_new, const double* lam_x, const double* lam_v, double* lam_xn,
+                               double* lam_vn, double* lam_xp, double* lam_vp, double* lam_load, double* lam_kext,
+                               double* lam_kb, double* lam_clamp_x, double* lam_clamp_v, double* lam_dframe);
+
+/* ---- wing pressure loads on the host (FSI coupling, Sec. 4.1) -------------
+ * The loads of fsi_get_pressure_loads computed from a pressure box held on
+ * the host: box0[3] (grid index of its first cell), boxn[3] (cells per axis,
+ * >= 4), pbox[boxn[2]][boxn[1]][boxn[0]] = p = Pi - |u|^2/2 at the cells (as
+ * returned by fsi_get_pressure_box), grid spacing dx[3]; d = t_w + h.  Mesh as
+ * in fsi_set_wing.  FSI_EBOUNDS if a sample stencil leaves the box.  */
+fsi_status fsi_loads_from_box(int32_t nv, const double* x, int32_t nt, const int32_t* tri, double d, const double* dx,
+                              const int32_t* box0, const int32_t* boxn, const double* pbox, double* loads,
+                              double* dp);
+/* Transpose of fsi_loads_from_box at (x, pbox): given the load cotangents
+ * lam_load[nv][3], ADDS the cotangents of the vertex positions (lam_x[nv][3],
+ * through the sample points, normals and areas) and of the box values
+ * (lam_pbox, box-shaped).  Either output may be NULL. */
+fsi_status fsi_loads_adjoint(int32_t nv, const double* x, int32_t nt, const int32_t* tri, double d, const double* dx,
+                             const int32_t* box0, const int32_t* boxn, const double* pbox, const double* lam_load,
+                             double* lam_x, double* lam_pbox);
+
 /* Static equilibrium F_int(x) + f_ext = 0 from the current positions, clamped
  * vertices fixed, the load applied in load_steps equal increments with Newton
  * at each; the velocities are set to zero and the history cleared. */

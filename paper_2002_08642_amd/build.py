@@ -2,7 +2,7 @@
 
 Each HIP translation unit is compiled with hipcc for gfx950 (packed FP32
 instructions disabled), the host-only C++ sources (the FP64 mass-spring
-solver) with the host compiler, then the objects are linked into
+solver and the wing-load transpose) with the host compiler, then the objects are linked into
 ``paper_2002_08642_amd/libfsi.so``.
 """
 
@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsi.so")
 SOURCES = ["kernels.hip", "adjoint.hip", "engine.hip", "api.hip"]
-HOST_SOURCES = ["structure.cpp"]
+HOST_SOURCES = ["structure.cpp", "loads.cpp"]
 ARCH = "gfx950"
 
 

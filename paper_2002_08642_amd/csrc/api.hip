@@ -271,6 +271,18 @@ fsi_status fsi_plate_frame(double t, double alpha, double omega, double t_ramp, 
   return FSI_OK;
 }
 
+fsi_status fsi_plate_frame_dalpha(double t, double alpha, double omega, double t_ramp, int32_t law, double* dframe) {
+  if (!dframe) return FSI_EINVAL;
+  double fr[9], ph[2];
+  const fsi_status st = fsi_plate_frame(t, alpha, omega, t_ramp, law, fr, ph);
+  if (st != FSI_OK) return st;
+  const double cp = cos(ph[0]), sp = sin(ph[0]), ca = cos(alpha), sa = sin(alpha);
+  const double cols[3][3] = {{0.0, 0.0, 0.0}, {sp * sa, -cp * sa, ca}, {sp * ca, -cp * ca, -sa}};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) dframe[3 * r + c] = cols[c][r];
+  return FSI_OK;
+}
+
 // Derivative of the rigid plate pose with respect to the pitch alpha: the pose
 // x = axis + Rz(phi) (s, c cos alpha, c sin alpha) gives dx/dalpha = Rz(phi)
 // (0, -c sin alpha, c cos alpha) and v = dphi/dt e_z x (x - axis) gives

@@ -129,11 +129,15 @@ inline V3 to_inertial(const double* F, const double* w) {
 const double kIdentity[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
 
 // Elastic energy, forces (-grad) and, optionally, the Hessian blocks of every
-// spring handed to `sink(u, w, block[3][3])` (block = d2E / dx_u dx_w).
+// spring handed to `sink(u, w, block[3][3])` (block = d2E / dx_u dx_w).  With
+// dF (and hess), df receives the derivative of the forces at fixed x when the
+// frame moves along dF (only bending springs depend on the frame).
 template <typename Sink>
-double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bool hess, Sink&& sink) {
+double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bool hess, Sink&& sink,
+               const double* dF = nullptr, double* df = nullptr) {
   double E = 0.0;
   if (f) memset(f, 0, sizeof(double) * 3 * ms.nv);
+  if (df) memset(df, 0, sizeof(double) * 3 * ms.nv);
   // extension springs
   for (size_t s = 0; s < ms.ek.size(); ++s) {
     const int i = ms.ei[s], j = ms.ej[s];
@@ -259,9 +263,71 @@ double springs(const fsi_ms& ms, const double* x, const double* F, double* f, bo
                           S[u][1] * S[w][0] * G[3 + r][c] + S[u][1] * S[w][1] * G[3 + r][3 + c];
           sink(vtx[u], vtx[w], blk);
         }
+      if (dF && df) {
+        // d(ga, gb)/d(frame) along dF: Hw (dF^T a, dF^T b); f_i = F ga etc.
+        const double ai[3] = {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]};
+        const double bi[3] = {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]};
+        double v6[6];
+        for (int c = 0; c < 3; ++c) {
+          v6[c] = dF[c] * ai[0] + dF[3 + c] * ai[1] + dF[6 + c] * ai[2];
+          v6[3 + c] = dF[c] * bi[0] + dF[3 + c] * bi[1] + dF[6 + c] * bi[2];
+        }
+        double dg[6];
+        for (int r = 0; r < 6; ++r) {
+          double sum = 0.0;
+          for (int c = 0; c < 6; ++c) sum += Hw[r][c] * v6[c];
+          dg[r] = sum;
+        }
+        const V3 dA1 = to_inertial(dF, gaw), dB1 = to_inertial(dF, gbw);
+        const V3 dA2 = to_inertial(F, dg), dB2 = to_inertial(F, dg + 3);
+        const double dA[3] = {dA1.x + dA2.x, dA1.y + dA2.y, dA1.z + dA2.z};
+        const double dB[3] = {dB1.x + dB2.x, dB1.y + dB2.y, dB1.z + dB2.z};
+        for (int c = 0; c < 3; ++c) {
+          df[3 * vi + c] += dA[c];
+          df[3 * vj + c] += dB[c] - dA[c];
+          df[3 * vk + c] -= dB[c];
+        }
+      }
     }
   }
   return E;
+}
+
+// -grad of the unit-stiffness energy (1/2) sum_p (theta^p - theta^p_0)^2 of
+// bending spring s, for its vertices (i, j, k): the derivative of the forces
+// with respect to k^b_s.
+void bend_unit_forces(const fsi_ms& ms, size_t s, const double* x, const double* F, double out[3][3]) {
+  const int vi = ms.bi[s], vj = ms.bj[s], vk = ms.bk[s], ax = ms.bax[s];
+  const V3 a = to_wing(F, {x[3 * vj] - x[3 * vi], x[3 * vj + 1] - x[3 * vi + 1], x[3 * vj + 2] - x[3 * vi + 2]});
+  const V3 b = to_wing(F, {x[3 * vk] - x[3 * vj], x[3 * vk + 1] - x[3 * vj + 1], x[3 * vk + 2] - x[3 * vj + 2]});
+  const double aw[3] = {a.x, a.y, a.z}, bw[3] = {b.x, b.y, b.z};
+  const double av[3] = {aw[ax], aw[(ax + 1) % 3], aw[(ax + 2) % 3]};
+  const double bv[3] = {bw[ax], bw[(ax + 1) % 3], bw[(ax + 2) % 3]};
+  double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+  for (int p = 0; p < 2; ++p) {
+    const int q = p + 1;
+    const double ra = av[0] * av[0] + av[q] * av[q], rb = bv[0] * bv[0] + bv[q] * bv[q];
+    double t = atan2(bv[q], bv[0]) - atan2(av[q], av[0]);
+    if (t > M_PI) t -= 2 * M_PI;
+    if (t <= -M_PI) t += 2 * M_PI;
+    const double dth = t - ms.bt0[2 * s + p];
+    ga[0] += dth * av[q] / ra;
+    ga[q] += -dth * av[0] / ra;
+    gb[0] += -dth * bv[q] / rb;
+    gb[q] += dth * bv[0] / rb;
+  }
+  double gaw[3], gbw[3];
+  for (int c = 0; c < 3; ++c) {
+    gaw[(ax + c) % 3] = ga[c];
+    gbw[(ax + c) % 3] = gb[c];
+  }
+  const V3 A = to_inertial(F, gaw), B = to_inertial(F, gbw);
+  const double Av[3] = {A.x, A.y, A.z}, Bv[3] = {B.x, B.y, B.z};
+  for (int c = 0; c < 3; ++c) {
+    out[0][c] = Av[c];
+    out[1][c] = Bv[c] - Av[c];
+    out[2][c] = -Bv[c];
+  }
 }
 
 struct NoSink {
@@ -613,6 +679,111 @@ fsi_status fsi_ms_step(fsi_ms* ms, double dt, const double* frame, const double*
   ms->dt_prev = dt;
   ms->have_prev = true;
   if (iters) *iters = it;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_set_history(fsi_ms* ms, const double* x_prev, const double* v_prev, double dt_prev) {
+  if (!ms) return FSI_EINVAL;
+  if (!x_prev) {
+    ms->have_prev = false;
+    return FSI_OK;
+  }
+  if (!v_prev || !(dt_prev > 0.0)) return fail(ms, FSI_EINVAL, "history needs x_prev, v_prev and dt_prev > 0");
+  ms->xp.assign(x_prev, x_prev + 3 * ms->nv);
+  ms->vp.assign(v_prev, v_prev + 3 * ms->nv);
+  ms->dt_prev = dt_prev;
+  ms->have_prev = true;
+  return FSI_OK;
+}
+
+fsi_status fsi_ms_step_adjoint(fsi_ms* ms, double dt, double dt_prev, const double* frame, const double* dframe,
+                               const double* x_new, const double* lam_x, const double* lam_v, double* lam_xn,
+                               double* lam_vn, double* lam_xp, double* lam_vp, double* lam_load, double* lam_kext,
+                               double* lam_kb, double* lam_clamp_x, double* lam_clamp_v, double* lam_dframe) {
+  if (!ms || !x_new || !lam_x || !lam_v) return FSI_EINVAL;
+  if (!(dt > 0.0)) return fail(ms, FSI_EINVAL, "dt must be positive");
+  const double* F = frame ? frame : kIdentity;
+  const int nv = ms->nv;
+  const bool first = !(dt_prev > 0.0);
+  const double xi = first ? 0.0 : dt / dt_prev;
+  const double alpha = (1 + xi) * (1 + xi) / (1 + 2 * xi), beta = xi * xi / (1 + 2 * xi);
+  const double gdt = (1 + xi) / (1 + 2 * xi) * dt;
+  // A w = gdt lam_x + lam_v over the free vertices, A = M + gdt^2 H(x_new)
+  Band A;
+  std::vector<double> f;
+  assemble(*ms, x_new, F, 1.0, gdt * gdt, A, f);
+  std::vector<double> w3(3 * ms->nfree);
+  for (int u = 0; u < nv; ++u) {
+    const int su = ms->slot[u];
+    if (su < 0) continue;
+    for (int d = 0; d < 3; ++d) w3[3 * su + d] = gdt * lam_x[3 * u + d] + lam_v[3 * u + d];
+  }
+  if (!A.solve(w3)) return fail(ms, FSI_ESTATE, "singular Newton matrix in the adjoint step");
+  std::vector<double> w(3 * nv, 0.0);  // M^-1 mu_v on the free vertices, 0 on clamped ones
+  for (int u = 0; u < nv; ++u)
+    if (ms->slot[u] >= 0)
+      for (int d = 0; d < 3; ++d) w[3 * u + d] = w3[3 * ms->slot[u] + d];
+  for (int u = 0; u < nv; ++u) {
+    if (ms->slot[u] < 0) continue;
+    for (int d = 0; d < 3; ++d) {
+      const int i = 3 * u + d;
+      const double mv = ms->mass[u] * w[i];        // mu_v
+      const double mx = (mv - lam_v[i]) / gdt;      // mu_x
+      if (lam_xn) lam_xn[i] += alpha * mx;
+      if (lam_vn) lam_vn[i] += alpha * mv;
+      if (!first) {
+        if (lam_xp) lam_xp[i] -= beta * mx;
+        if (lam_vp) lam_vp[i] -= beta * mv;
+      }
+      if (lam_load) lam_load[i] += gdt * w[i];
+    }
+  }
+  // stiffness parameters
+  if (lam_kext)
+    for (size_t s = 0; s < ms->ek.size(); ++s) {
+      const int i = ms->ei[s], j = ms->ej[s];
+      const double d[3] = {x_new[3 * j] - x_new[3 * i], x_new[3 * j + 1] - x_new[3 * i + 1],
+                           x_new[3 * j + 2] - x_new[3 * i + 2]};
+      const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double dot = 0.0;
+      for (int c = 0; c < 3; ++c) dot += (L - ms->el0[s]) * d[c] / L * (w[3 * i + c] - w[3 * j + c]);
+      lam_kext[s] += gdt * dot;
+    }
+  if (lam_kb)
+    for (size_t s = 0; s < ms->bkb.size(); ++s) {
+      double g[3][3];
+      bend_unit_forces(*ms, s, x_new, F, g);
+      const int vt[3] = {ms->bi[s], ms->bj[s], ms->bk[s]};
+      double dot = 0.0;
+      for (int m = 0; m < 3; ++m)
+        for (int c = 0; c < 3; ++c) dot += g[m][c] * w[3 * vt[m] + c];
+      lam_kb[s] += gdt * dot;
+    }
+  // clamped rows: mu_cx = lam_cx - gdt (H w)_c, mu_cv = lam_cv; they are the
+  // cotangents of the prescribed positions and velocities
+  if (lam_clamp_x || lam_clamp_v) {
+    std::vector<double> Hw(3 * nv, 0.0);
+    springs(*ms, x_new, F, nullptr, true, [&](int u, int v2, const double (&blk)[3][3]) {
+      if (!ms->is_clamped[u] || ms->is_clamped[v2]) return;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Hw[3 * u + r] += blk[r][c] * w[3 * v2 + c];
+    });
+    for (size_t c = 0; c < ms->clamped.size(); ++c) {
+      const int u = ms->clamped[c];
+      for (int d = 0; d < 3; ++d) {
+        if (lam_clamp_x) lam_clamp_x[3 * c + d] += lam_x[3 * u + d] - gdt * Hw[3 * u + d];
+        if (lam_clamp_v) lam_clamp_v[3 * c + d] += lam_v[3 * u + d];
+      }
+    }
+  }
+  // frame moving along dframe: the forces change by df at fixed x
+  if (dframe && lam_dframe) {
+    std::vector<double> df(3 * nv);
+    springs(*ms, x_new, F, nullptr, true, NoSink{}, dframe, df.data());
+    double dot = 0.0;
+    for (int i = 0; i < 3 * nv; ++i) dot += df[i] * w[i];
+    *lam_dframe += gdt * dot;
+  }
   return FSI_OK;
 }
 

@@ -31,6 +31,8 @@ EXPORTS = [
     "fsi_ms_set_extension_k", "fsi_ms_set_bending_k", "fsi_ms_set_clamped", "fsi_ms_bending_angles",
     "fsi_ms_forces", "fsi_ms_set_state", "fsi_ms_get_state", "fsi_ms_step", "fsi_ms_static",
     "fsi_ms_set_rest", "fsi_ms_bending_stiffness", "fsi_ms_lumped_masses", "fsi_plate_frame",
+    "fsi_ms_set_history", "fsi_ms_step_adjoint", "fsi_plate_frame_dalpha", "fsi_loads_from_box",
+    "fsi_loads_adjoint",
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
     "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
@@ -116,6 +118,13 @@ def load_library():
     lib.fsi_ms_bending_stiffness.argtypes = [ctypes.c_double, ctypes.c_double, I32, D]
     lib.fsi_ms_lumped_masses.argtypes = [I32, D, I32, ctypes.POINTER(I32), ctypes.c_double, D]
     lib.fsi_plate_frame.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, D, D]
+    lib.fsi_plate_frame_dalpha.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, D]
+    lib.fsi_ms_set_history.argtypes = [P, D, D, ctypes.c_double]
+    lib.fsi_loads_from_box.argtypes = [I32, D, I32, ctypes.POINTER(I32), ctypes.c_double, D, ctypes.POINTER(I32),
+                                       ctypes.POINTER(I32), D, D, D]
+    lib.fsi_loads_adjoint.argtypes = [I32, D, I32, ctypes.POINTER(I32), ctypes.c_double, D, ctypes.POINTER(I32),
+                                      ctypes.POINTER(I32), D, D, D, D]
+    lib.fsi_ms_step_adjoint.argtypes = [P, ctypes.c_double, ctypes.c_double, D, D, D, D, D] + [D] * 10
     lib.fsi_ms_set_extension_k.argtypes = [P, D]
     lib.fsi_ms_set_bending_k.argtypes = [P, D]
     lib.fsi_ms_set_clamped.argtypes = [P, I32, ctypes.POINTER(I32)]
@@ -474,6 +483,28 @@ class MassSpring:
                                          int(max_iter), ctypes.byref(it)), "fsi_ms_step")
         return it.value
 
+    def set_history(self, x_prev=None, v_prev=None, dt_prev=0.0):
+        xp = None if x_prev is None else _f64(x_prev, (self.nv, 3))
+        vp = None if v_prev is None else _f64(v_prev, (self.nv, 3))
+        self._check(self.lib.fsi_ms_set_history(self.ptr, _optd(xp), _optd(vp), float(dt_prev)), "fsi_ms_set_history")
+
+    def step_adjoint(self, dt, dt_prev, frame, x_new, lam_x, lam_v, dframe=None):
+        """Transpose of one step (fsi_ms_step_adjoint); returns a dict of cotangents."""
+        nv, nc = self.nv, len(self.clamped)
+        out = dict(xn=np.zeros((nv, 3)), vn=np.zeros((nv, 3)), xp=np.zeros((nv, 3)), vp=np.zeros((nv, 3)),
+                   load=np.zeros((nv, 3)), kext=np.zeros(self.n_ext), kb=np.zeros(self.n_bend),
+                   clamp_x=np.zeros((nc, 3)), clamp_v=np.zeros((nc, 3)), dframe=np.zeros(1))
+        fr = None if frame is None else _f64(frame, (3, 3))
+        dfr = None if dframe is None else _f64(dframe, (3, 3))
+        self._check(self.lib.fsi_ms_step_adjoint(
+            self.ptr, float(dt), float(dt_prev if dt_prev is not None else 0.0), _optd(fr), _optd(dfr),
+            _dptr(_f64(x_new, (nv, 3))), _dptr(_f64(lam_x, (nv, 3))), _dptr(_f64(lam_v, (nv, 3))),
+            _dptr(out["xn"]), _dptr(out["vn"]), _dptr(out["xp"]), _dptr(out["vp"]), _dptr(out["load"]),
+            _dptr(out["kext"]), _dptr(out["kb"]), _dptr(out["clamp_x"]), _dptr(out["clamp_v"]),
+            _dptr(out["dframe"])), "fsi_ms_step_adjoint")
+        out["dframe"] = float(out["dframe"][0])
+        return out
+
     def static(self, f_ext, frame=None, load_steps=10, tol=1e-10, max_iter=50):
         fr = None if frame is None else _f64(frame, (3, 3))
         self._check(self.lib.fsi_ms_static(self.ptr, _optd(fr), _dptr(_f64(f_ext, (self.nv, 3))), int(load_steps),
@@ -509,3 +540,48 @@ def plate_frame(t, alpha, omega, t_ramp, law=0):
     if rc != FSI_OK:
         raise FsiError(rc, "fsi_plate_frame")
     return fr
+
+
+def plate_frame_dalpha(t, alpha, omega, t_ramp, law=0):
+    """d frame / d alpha of the revolving plate (fsi_plate_frame_dalpha)."""
+    fr = np.zeros((3, 3))
+    rc = load_library().fsi_plate_frame_dalpha(float(t), float(alpha), float(omega), float(t_ramp), int(law),
+                                               _dptr(fr))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_plate_frame_dalpha")
+    return fr
+
+
+def loads_from_box(x, tri, d, dx, box0, pbox):
+    """Wing loads and pressure jumps from a host pressure box (fsi_loads_from_box);
+    pbox has shape (nz, ny, nx) of the box."""
+    x = _f64(x).reshape(-1, 3)
+    tri = _i32(tri, (-1, 3))
+    pbox = _f64(pbox)
+    boxn = _i32([pbox.shape[2], pbox.shape[1], pbox.shape[0]])
+    b0 = _i32(box0, (3,))
+    loads = np.zeros_like(x)
+    dp = np.zeros(x.shape[0])
+    rc = load_library().fsi_loads_from_box(x.shape[0], _dptr(x), tri.shape[0], _iptr(tri), float(d),
+                                           _dptr(_f64(dx, (3,))), _iptr(b0), _iptr(boxn), _dptr(pbox),
+                                           _dptr(loads), _dptr(dp))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_loads_from_box")
+    return loads, dp
+
+
+def loads_adjoint(x, tri, d, dx, box0, pbox, lam_load):
+    """Cotangents (of x, of pbox) of the loads map (fsi_loads_adjoint)."""
+    x = _f64(x).reshape(-1, 3)
+    tri = _i32(tri, (-1, 3))
+    pbox = _f64(pbox)
+    boxn = _i32([pbox.shape[2], pbox.shape[1], pbox.shape[0]])
+    b0 = _i32(box0, (3,))
+    lx = np.zeros_like(x)
+    lp = np.zeros_like(pbox)
+    rc = load_library().fsi_loads_adjoint(x.shape[0], _dptr(x), tri.shape[0], _iptr(tri), float(d),
+                                          _dptr(_f64(dx, (3,))), _iptr(b0), _iptr(boxn), _dptr(pbox),
+                                          _dptr(_f64(lam_load, x.shape)), _dptr(lx), _dptr(lp))
+    if rc != FSI_OK:
+        raise FsiError(rc, "fsi_loads_adjoint")
+    return lx, lp

@@ -191,3 +191,81 @@ def test_rest_state_stiffness_masses_and_frame_helpers():
     for t in (0.0, 0.1, 0.5):
         assert np.allclose(fsi.plate_frame(t, 0.7, 2 * np.pi, 0.4), kinematics.plate_frame(t, 0.7, 2 * np.pi, 0.4),
                            atol=1e-15)
+
+
+def step_map(ms, x_n, v_n, hist, dt, F, fext, xc, vc, kext, kb):
+    """q^{n+1} of one native step from a given state, history and parameters."""
+    ms.set_extension_k(kext)
+    ms.set_bending_k(kb)
+    ms.set_state(x_n, v_n)
+    if hist is not None:
+        ms.set_history(*hist)
+    ms.step(dt, F, fext, xc, vc, tol=1e-14, max_iter=40)
+    return ms.state()
+
+
+@pytest.mark.parametrize("first", [True, False])
+@pytest.mark.parametrize("part", ["state", "prev", "load", "stiffness", "clamp", "frame"])
+def test_structure_step_adjoint_dot_product(part, first):
+    mass, ext, bend, clamped, x0 = plate_network(seed=7, chordwise=True)
+    clamped = sorted(clamped)
+    ms = native(mass, ext, bend, clamped)
+    rng = np.random.default_rng(11)
+    nv = len(mass)
+    alpha = 0.4
+    Fr = lambda a: rot([0, 0, 1], 0.3) @ rot([1, 0, 0], a)
+    dFr = (Fr(alpha + 1e-7) - Fr(alpha - 1e-7)) / 2e-7
+    x_n = x0 @ Fr(alpha).T + 0.02 * rng.standard_normal(x0.shape)
+    v_n = 0.2 * rng.standard_normal(x0.shape)
+    hist = None if first else (x_n - 0.01 * v_n + 0.001 * rng.standard_normal(x0.shape), v_n.copy(), 0.012)
+    dt = 0.01
+    fext = 0.05 * rng.standard_normal(x0.shape)
+    xc = x_n[clamped] + 0.003
+    vc = 0.1 * rng.standard_normal((len(clamped), 3))
+    e = np.array(ext)
+    b = np.array([tuple(r) + (0,) * (7 - len(r)) for r in bend], dtype=float)
+    kext, kb = e[:, 2].copy(), b[:, 3].copy()
+    lam_x, lam_v = rng.standard_normal((nv, 3)), rng.standard_normal((nv, 3))
+    # perturbation direction
+    d = dict(xn=0 * x_n, vn=0 * v_n, xp=0 * x_n, vp=0 * v_n, load=0 * fext, kext=0 * kext, kb=0 * kb,
+             cx=0 * xc, cv=0 * vc, a=0.0)
+    if part == "state":
+        d["xn"], d["vn"] = rng.standard_normal(x_n.shape), rng.standard_normal(v_n.shape)
+    elif part == "prev":
+        if first:
+            pytest.skip("no history on the implicit-Euler step")
+        d["xp"], d["vp"] = rng.standard_normal(x_n.shape), rng.standard_normal(v_n.shape)
+    elif part == "load":
+        d["load"] = rng.standard_normal(fext.shape)
+    elif part == "stiffness":
+        d["kext"], d["kb"] = kext * rng.standard_normal(len(kext)), kb * rng.standard_normal(len(kb))
+    elif part == "clamp":
+        d["cx"], d["cv"] = rng.standard_normal(xc.shape), rng.standard_normal(vc.shape)
+    else:
+        d["a"] = 1.0
+
+    def J(eps):
+        h = None if hist is None else (hist[0] + eps * d["xp"], hist[1] + eps * d["vp"], hist[2])
+        x1, v1 = step_map(ms, x_n + eps * d["xn"], v_n + eps * d["vn"], h, dt, Fr(alpha + eps * d["a"]),
+                          fext + eps * d["load"], xc + eps * d["cx"], vc + eps * d["cv"],
+                          kext + eps * d["kext"], kb + eps * d["kb"])
+        return float(np.sum(lam_x * x1) + np.sum(lam_v * v1))
+
+    # O(eps^2) truncation vs Newton tolerance (1e-14) / eps: random state moves are
+    # strongly curved, the frame's effect is small
+    eps = 3e-5 if part == "frame" else 1e-6
+    fd = (J(eps) - J(-eps)) / (2 * eps)
+    x1, _ = step_map(ms, x_n, v_n, hist, dt, Fr(alpha), fext, xc, vc, kext, kb)
+    g = ms.step_adjoint(dt, None if first else hist[2], Fr(alpha), x1, lam_x, lam_v, dframe=dFr)
+    adj = (np.sum(g["xn"] * d["xn"]) + np.sum(g["vn"] * d["vn"]) + np.sum(g["xp"] * d["xp"]) +
+           np.sum(g["vp"] * d["vp"]) + np.sum(g["load"] * d["load"]) + np.sum(g["kext"] * d["kext"]) +
+           np.sum(g["kb"] * d["kb"]) + np.sum(g["clamp_x"] * d["cx"]) + np.sum(g["clamp_v"] * d["cv"]) +
+           g["dframe"] * d["a"])
+    assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-6), (adj, fd)
+
+
+def test_plate_frame_dalpha_is_the_derivative():
+    for t in (0.0, 0.21):
+        h = 1e-6
+        fd = (fsi.plate_frame(t, 0.7 + h, 2 * np.pi, 0.4) - fsi.plate_frame(t, 0.7 - h, 2 * np.pi, 0.4)) / (2 * h)
+        assert np.allclose(fsi.plate_frame_dalpha(t, 0.7, 2 * np.pi, 0.4), fd, atol=1e-9)
