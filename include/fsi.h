@@ -180,6 +180,14 @@ fsi_status fsi_sample_pressure(fsi_ctx* ctx, int32_t n, const double* pts, doubl
  * fsi_sample_pressure.  Synchronizes. */
 fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp);
 
+/* The pressure box of the current mesh (box0[3]: grid index of its first
+ * cell, boxn[3]: cells per axis) and, if p is not NULL, p = Pi - |u|^2/2 of
+ * the last step at its cells, p[boxn[2]][boxn[1]][boxn[0]] (the data the host
+ * needs to transpose the loads, fsi_loads_adjoint).  FSI_ESTATE without FSI
+ * mode or wing, or (p != NULL) without a step since fsi_set_wing.
+ * Synchronizes. */
+fsi_status fsi_get_pressure_box(fsi_ctx* ctx, int32_t* box0, int32_t* boxn, double* p);
+
 /* Stand-alone transforms on the context's grid, for testing the FFT passes.
  * r2c: physical f[nz][ny][nx] -> normalized compact band fhat (interleaved).
  * c2r: compact band fhat -> physical f (real part of the inverse transform,
@@ -222,6 +230,16 @@ fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev);
  * through the mask and the solid velocity. Synchronizes. */
 fsi_status fsi_step_adjoint(fsi_ctx* ctx, int32_t tape_slot, double dt, double dt_prev, int32_t first,
                             const double dJdF[3], double* dJdx, double* dJdv);
+
+/* Pressure seed of the next fsi_step_adjoint (FSI coupling): the cotangent
+ * lam_p of p = Pi - |u|^2/2 of that step at the cells of the current pressure
+ * box (box0/boxn must be those of fsi_get_pressure_box for the current mesh,
+ * else FSI_EINVAL; lam_p = NULL clears it).  The reverse step then also
+ * carries lam_p back to u_hat^n and to the mesh through Pi_hat =
+ * -i k.N'_hat/|k|^2 and through -|u|^2/2.  A new fsi_set_wing clears it.
+ * Synchronizes. */
+fsi_status fsi_adjoint_set_pressure_seed(fsi_ctx* ctx, const int32_t* box0, const int32_t* boxn,
+                                         const double* lam_p);
 
 /* Derivatives of fsi_plate_pose's x and v with respect to the pitch alpha
  * (host, FP64): dxda[nv][3], dvda[nv][3]. */

@@ -24,12 +24,16 @@ structure model that the library's native solver is checked against.
   printed -k^b (theta - theta_0).
 * Bending stiffness from flexural rigidity (Sec. 2.3.1, Eq. EI_k_relation).
 
-The Newton Jacobian here is a central finite difference of the forces (the
-root is fixed by the residual alone, so the Jacobian only affects the path).
+The Newton Jacobian here is a central finite difference of the residual (the
+root is fixed by the residual alone, so the Jacobian only affects the path);
+columns whose rows do not overlap (vertices more than two springs apart) are
+differenced together, and the sparse system is solved by scipy.
 Pins: tests/test_oracle_structure.py.
 """
 
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 # ---------------------------------------------------------------------------
@@ -161,6 +165,52 @@ def rhs(net, q, frame, f_ext):
     return np.stack([v, a])
 
 
+def neighbourhoods(net):
+    """N[v]: v and every point sharing a spring with it."""
+    nb = [{v} for v in range(net.n)]
+    for i, j in net.ext_ij:
+        nb[i].add(j)
+        nb[j].add(i)
+    for t in net.bend_ijk:
+        for a in t:
+            nb[a].update(int(b) for b in t)
+    return [np.array(sorted(x)) for x in nb]
+
+
+def colours(nbhd):
+    """Greedy colouring with N[a] and N[b] disjoint within a colour."""
+    n = len(nbhd)
+    col = -np.ones(n, dtype=np.int64)
+    for v in range(n):
+        near = set()
+        for w in nbhd[v]:
+            for u in nbhd[w]:
+                if col[u] >= 0:
+                    near.add(int(col[u]))
+        c = 0
+        while c in near:
+            c += 1
+        col[v] = c
+    return col
+
+
+def fd_jacobian(residual, z, groups, m, fd_h):
+    """Central-difference Jacobian (m x len(z), sparse): groups is a list of
+    lists of (column, rows) whose row sets are disjoint within a group."""
+    rows_all, cols_all, vals_all = [], [], []
+    for grp in groups:
+        h = np.zeros_like(z)
+        for c, _ in grp:
+            h[c] = fd_h * max(1.0, abs(z[c]))
+        d = residual(z + h) - residual(z - h)
+        for c, rows in grp:
+            rows_all.append(rows)
+            cols_all.append(np.full(len(rows), c))
+            vals_all.append(d[rows] / (2 * h[c]))
+    return sp.csr_matrix((np.concatenate(vals_all), (np.concatenate(rows_all), np.concatenate(cols_all))),
+                         shape=(m, len(z)))
+
+
 def bdf2_step(net, q, q_prev, dt, dt_prev, frame, f_ext, clamp_x=None, clamp_v=None, tol=1e-12, max_iter=50,
               fd_h=1e-7):
     """One structure step: returns (q^{n+1}, Newton iterations).
@@ -185,18 +235,23 @@ def bdf2_step(net, q, q_prev, dt, dt_prev, frame, f_ext, clamp_x=None, clamp_v=N
         qn[0, net.clamped] = clamp_x
         qn[1, net.clamped] = clamp_v
     m = qn.size
+    # column groups: x of vertex v touches its x row and the v rows of N[v]; v of
+    # a vertex touches only its own rows
+    nbhd = neighbourhoods(net)
+    col = colours(nbhd)
+    groups = []
+    for c in range(3):
+        for k in range(int(col.max()) + 1):
+            grp = []
+            for v in np.flatnonzero(col == k):
+                vrows = (n * 3 + nbhd[v][:, None] * 3 + np.arange(3)[None, :]).ravel()
+                grp.append((v * 3 + c, np.concatenate([[v * 3 + c], vrows])))
+            groups.append(grp)
+        groups.append([(n * 3 + v * 3 + c, np.array([v * 3 + c, n * 3 + v * 3 + c])) for v in range(n)])
     for it in range(1, max_iter + 1):
         r = residual(qn)
-        J = np.empty((m, m))
-        flat = qn.reshape(-1)
-        for c in range(m):
-            hp = flat.copy()
-            hm = flat.copy()
-            h = fd_h * max(1.0, abs(flat[c]))
-            hp[c] += h
-            hm[c] -= h
-            J[:, c] = (residual(hp.reshape(qn.shape)) - residual(hm.reshape(qn.shape))) / (2 * h)
-        dq = np.linalg.solve(J, -r)
+        J = fd_jacobian(lambda z: residual(z.reshape(qn.shape)), qn.reshape(-1), groups, m, fd_h)
+        dq = spla.spsolve(J.tocsc(), -r)
         qn = qn + dq.reshape(qn.shape)
         if np.linalg.norm(dq) <= tol * max(1.0, np.linalg.norm(qn)):
             return qn, it

@@ -65,8 +65,17 @@ __global__ __launch_bounds__(256) void adj_spectral(AdjSpecArgs<T> a) {
       ln[2] = ln[2] - scl(s, kz);
     }
     const T sc = (T)(a.invN3 / (ix == 0 ? 1.0 : 2.0));
+    cpx<T> extra[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+    if (a.lpi && k2 > (T)0) {
+      // Pi_hat = -i k.N'_hat / |k|^2: its transpose adds i k lambda_Pi_hat / |k|^2
+      const cpx<T> lp = a.lpi[e];
+      const T ik2 = (T)1 / k2;
+      const T kk[3] = {kx, ky, kz};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) a.mu[q * a.cfs + e] = scl(ln[q], sc);
+      for (int q = 0; q < 3; ++q) extra[q] = mk<T>(-kk[q] * lp.im * ik2, kk[q] * lp.re * ik2);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.mu[q * a.cfs + e] = scl(ln[q], sc) + extra[q];
   }
 }
 
@@ -144,6 +153,16 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
         T luz = wx * gy - wy * gx;
         const int line = line0 + l;
         const int z = line / a.ny, y = line - z * a.ny;
+        if (a.pnx > 0) {
+          const int qx = x - a.px0, qy = y - a.py0, qz = z - a.pz0;
+          if (qx >= 0 && qx < a.pnx && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {
+            // p = Pi - |u|^2 / 2: lambda_u -= u lambda_p
+            const T lpv = a.lp[((long long)qz * a.pny + qy) * a.pnx + qx];
+            lux -= ux * lpv;
+            luy -= uy * lpv;
+            luz -= uz * lpv;
+          }
+        }
         const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
         if (a.bnx > 0 && bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {
           const long long cell = ((long long)bz * a.bny + by) * a.bnx + bx;
@@ -248,6 +267,21 @@ __device__ __forceinline__ void xadj_line(const XAdjArgs<T>& a, int line, int la
     o[2][j] = mk<T>(gz * ux - gx * uz, gx * uy - gy * ux);
   }
   const int z = line / a.ny, y = line - z * a.ny;
+  const int qy = y - a.py0, qz = z - a.pz0;
+  if (a.pnx > 0 && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {  // uniform per wave
+    const long long rowcell = ((long long)qz * a.pny + qy) * a.pnx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int qx = (lane >> 3) + 8 * (lane & 7) + 64 * j - a.px0;
+      if (qx >= 0 && qx < a.pnx) {
+        // p = Pi - |u|^2 / 2: lambda_u -= u lambda_p
+        const T lpv = a.lp[rowcell + qx];
+        o[0][j].re -= P[0][j].re * lpv;
+        o[0][j].im -= P[0][j].im * lpv;
+        o[1][j].re -= P[1][j].re * lpv;
+      }
+    }
+  }
   const int by = y - a.by0, bz = z - a.bz0;
   if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
     const long long rowcell = ((long long)bz * a.bny + by) * a.bnx;

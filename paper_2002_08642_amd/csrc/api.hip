@@ -153,6 +153,23 @@ fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp) {
   return ctx->eng->pressure_loads(loads, dp);
 }
 
+fsi_status fsi_get_pressure_box(fsi_ctx* ctx, int32_t* box0, int32_t* boxn, double* p) {
+  if (guard(ctx) != FSI_OK || !box0 || !boxn) return FSI_EINVAL;
+  int b0[3], bn[3];
+  const fsi_status st = ctx->eng->pressure_box(b0, bn, p);
+  for (int q = 0; q < 3; ++q) {
+    box0[q] = b0[q];
+    boxn[q] = bn[q];
+  }
+  return st;
+}
+
+fsi_status fsi_adjoint_set_pressure_seed(fsi_ctx* ctx, const int32_t* box0, const int32_t* boxn, const double* lam_p) {
+  if (guard(ctx) != FSI_OK || !box0 || !boxn) return FSI_EINVAL;
+  const int b0[3] = {box0[0], box0[1], box0[2]}, bn[3] = {boxn[0], boxn[1], boxn[2]};
+  return ctx->eng->set_pressure_seed(b0, bn, lam_p);
+}
+
 fsi_status fsi_fft_r2c(fsi_ctx* ctx, const double* f, double* fhat) {
   if (guard(ctx) != FSI_OK || !f || !fhat) return FSI_EINVAL;
   return ctx->eng->fft_r2c(f, fhat);

@@ -36,6 +36,8 @@ class EngineBase {
                                   double* dJdv) = 0;
   virtual fsi_status sample_pressure(int n, const double* pts, double* p) = 0;
   virtual fsi_status pressure_loads(double* loads, double* dp) = 0;
+  virtual fsi_status pressure_box(int box0[3], int boxn[3], double* p) = 0;
+  virtual fsi_status set_pressure_seed(const int box0[3], const int boxn[3], const double* lam) = 0;
   virtual fsi_status set_timing(bool on) = 0;
   virtual fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) = 0;
   std::string err;

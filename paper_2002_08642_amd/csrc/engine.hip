@@ -396,6 +396,7 @@ class Engine : public EngineBase {
       samp_host.swap(samp);
     }
     p_ready = false;
+    seed_pending = false;
     return FSI_OK;
   }
 
@@ -472,6 +473,80 @@ class Engine : public EngineBase {
     }
     FSI_TRY(pressure_ready());
     return run_psample(n, pts, p);
+  }
+
+  fsi_status pressure_box(int box0[3], int boxn[3], double* p) override {
+    if (!d.fsi_pressure || wing_nt == 0 || pcells == 0) {
+      err = "no pressure box: FSI mode off or no wing";
+      return FSI_ESTATE;
+    }
+    box0[0] = px0;
+    box0[1] = py0;
+    box0[2] = pz0;
+    boxn[0] = pnx;
+    boxn[1] = pny;
+    boxn[2] = pnz;
+    if (!p) return FSI_OK;
+    FSI_TRY(pressure_ready());
+    if (!phys) FSI_TRY(alloc(&phys, 3 * npts));
+    if (pcells > dpbox_cap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      free_dev(dpbox_);
+      dpbox_cap = pcells + pcells / 4;
+      FSI_TRY(alloc(&dpbox_, dpbox_cap));
+    }
+    FSI_TRY(run_inverse(pi_, clen, 1, phys));
+    BoxArgs<T> a = box_args();
+    a.pi = phys;
+    a.out = dpbox_;
+    FSI_HIP(launch_pbox<T>(0, a, s));
+    FSI_HIP(hipMemcpyAsync(p, dpbox_, sizeof(double) * pcells, hipMemcpyDeviceToHost, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
+  fsi_status set_pressure_seed(const int box0[3], const int boxn[3], const double* lam) override {
+    if (!d.fsi_pressure || wing_nt == 0 || pcells == 0) {
+      err = "no pressure box: FSI mode off or no wing";
+      return FSI_ESTATE;
+    }
+    if (box0[0] != px0 || box0[1] != py0 || box0[2] != pz0 || boxn[0] != pnx || boxn[1] != pny || boxn[2] != pnz) {
+      err = "pressure seed box differs from the box of the current mesh";
+      return FSI_EINVAL;
+    }
+    if (!lam) {
+      seed_pending = false;
+      return FSI_OK;
+    }
+    if (pcells > lp_cap) {
+      FSI_HIP(hipStreamSynchronize(s));
+      free_dev(lp_);
+      lp_cap = pcells + pcells / 4;
+      FSI_TRY(alloc(&lp_, lp_cap));
+    }
+    std::vector<T> h(pcells);
+    for (long long c = 0; c < pcells; ++c) h[c] = (T)lam[c];
+    FSI_HIP(hipMemcpyAsync(lp_, h.data(), sizeof(T) * pcells, hipMemcpyHostToDevice, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    seed_pending = true;
+    return FSI_OK;
+  }
+
+  BoxArgs<T> box_args() {
+    BoxArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.up = up_;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.px0 = px0;
+    a.py0 = py0;
+    a.pz0 = pz0;
+    a.pnx = pnx;
+    a.pny = pny;
+    a.pnz = pnz;
+    a.pcells = pcells;
+    return a;
   }
 
   fsi_status pressure_loads(double* loads, double* dp) override {
@@ -808,6 +883,19 @@ class Engine : public EngineBase {
       }
       FSI_TRY(run_mask());
     }
+    // pressure seed: lambda_Pi on the grid (zero outside the box), its normalized R2C
+    const bool seed = seed_pending && d.fsi_pressure && wing && pcells > 0;
+    if (seed) {
+      if (!phys) FSI_TRY(alloc(&phys, 3 * npts));
+      if (!piadj_) FSI_TRY(alloc(&piadj_, clen));
+      FSI_HIP(hipMemsetAsync(phys, 0, sizeof(T) * npts, s));
+      BoxArgs<T> b = box_args();
+      b.in = lp_;
+      b.grid = phys;
+      FSI_HIP(launch_pbox<T>(1, b, s));
+      FSI_TRY(run_forward(phys, 1, piadj_, COL_FWD_PLAIN));
+    }
+    seed_pending = false;
     // update transpose and projection: mu = P(lambda_N) / (m_k N^3)
     {
       AdjSpecArgs<T> a;
@@ -830,6 +918,7 @@ class Engine : public EngineBase {
       a.dtp = first ? dt : dtp;
       a.first = first ? 1 : 0;
       a.invN3 = 1.0 / (double)npts;
+      a.lpi = seed ? piadj_ : nullptr;
       FSI_HIP(launch_adj_spectral<T>(a, s));
     }
     // inverse transforms: u, omega of the taped state and lambda_G = C2R(mu)
@@ -880,6 +969,16 @@ class Engine : public EngineBase {
         a.bny = bny;
         a.bnz = bnz;
         a.bcells = bcells;
+      }
+      if (seed) {
+        a.lp = lp_;
+        a.px0 = px0;
+        a.py0 = py0;
+        a.pz0 = pz0;
+        a.pnx = pnx;
+        a.pny = pny;
+        a.pnz = pnz;
+        a.pcells = pcells;
       }
       a.inv_eta = (T)(1.0 / d.eta);
       a.g0 = (T)(dV * dJdF[0]);
@@ -1046,6 +1145,9 @@ class Engine : public EngineBase {
     free_dev(up_);
     free_dev(dsamp_);
     free_dev(dpout_);
+    free_dev(dpbox_);
+    free_dev(lp_);
+    free_dev(piadj_);
     for (Slot& sl : slots) {
       free_dev(sl.uh);
       free_dev(sl.nh);
@@ -1339,6 +1441,11 @@ class Engine : public EngineBase {
   int px0 = 0, py0 = 0, pz0 = 0, pnx = 0, pny = 0, pnz = 0;
   std::vector<double> load_cv, samp_host;
   bool p_ready = false;
+  double* dpbox_ = nullptr;
+  long long dpbox_cap = 0, lp_cap = 0;
+  T* lp_ = nullptr;          // pressure seed on the box (adjoint)
+  cpx<T>* piadj_ = nullptr;  // its normalized R2C (compact)
+  bool seed_pending = false;
   // stepping
   long long nstep = 0;
   bool have_prev = false;

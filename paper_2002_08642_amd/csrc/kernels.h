@@ -93,6 +93,20 @@ struct XArgs {
   long long pcells;
 };
 
+// p = Pi - |u|^2/2 at the cells of the pressure box (out, FP64), and the
+// embedding of box values into a full grid field.
+template <typename T>
+struct BoxArgs {
+  const T* pi;    // full grid [z][y][x] (pbox_pressure) / out grid (embed)
+  const T* up;    // [3][cell]
+  int nx, ny, nz;
+  int px0, py0, pz0, pnx, pny, pnz;
+  long long pcells;
+  double* out;       // [cell] (pbox_pressure)
+  const T* in;       // [cell] (embed)
+  T* grid;           // full grid (embed)
+};
+
 // Sampling of p = Pi - |u|^2 / 2 with the 4-point delta kernel: Pi on the full
 // grid ([z][y][x]), u on the pressure box, points in FP64.
 template <typename T>
@@ -149,6 +163,9 @@ struct AdjSpecArgs {
   double dt, dtp;
   int first;
   double invN3;
+  // pressure seed (FSI coupling): normalized R2C of the cotangent of Pi on the
+  // grid; mu gains i k lpi / |k|^2 (NULL: none)
+  const cpx<T>* lpi;
 };
 
 // Fused x pass of the reverse step: C2R of u, omega and lambda_G (9 fields),
@@ -172,6 +189,11 @@ struct XAdjArgs {
   long long bcells;
   T inv_eta;
   T g0, g1, g2;  // dV * dJ/dF
+  // pressure seed (FSI coupling): cotangent of p = Pi - |u|^2/2 on the pressure
+  // box, adds -u lp to lambda_u there (pnx = 0: none)
+  const T* lp;
+  int px0, py0, pz0, pnx, pny, pnz;
+  long long pcells;
 };
 
 // Mask adjoint: per triangle, sums over the cells it wins of the cotangents of

@@ -849,6 +849,36 @@ __global__ __launch_bounds__(kNT) void pressure_sample(PressArgs<T> a) {
 }
 
 template <typename T>
+__global__ __launch_bounds__(kNT) void pbox_pressure(BoxArgs<T> a) {
+  for (long long c = (long long)blockIdx.x * kNT + threadIdx.x; c < a.pcells; c += (long long)gridDim.x * kNT) {
+    const int qx = (int)(c % a.pnx), qy = (int)((c / a.pnx) % a.pny), qz = (int)(c / ((long long)a.pnx * a.pny));
+    const long long g = ((long long)(qz + a.pz0) * a.ny + (qy + a.py0)) * a.nx + (qx + a.px0);
+    const double ux = (double)a.up[c], uy = (double)a.up[a.pcells + c], uz = (double)a.up[2 * a.pcells + c];
+    a.out[c] = (double)a.pi[g] - 0.5 * (ux * ux + uy * uy + uz * uz);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void embed_box(BoxArgs<T> a) {
+  for (long long c = (long long)blockIdx.x * kNT + threadIdx.x; c < a.pcells; c += (long long)gridDim.x * kNT) {
+    const int qx = (int)(c % a.pnx), qy = (int)((c / a.pnx) % a.pny), qz = (int)(c / ((long long)a.pnx * a.pny));
+    const long long g = ((long long)(qz + a.pz0) * a.ny + (qy + a.py0)) * a.nx + (qx + a.px0);
+    a.grid[g] = a.in[c];
+  }
+}
+
+template <typename T>
+hipError_t launch_pbox(int embed, const BoxArgs<T>& a, hipStream_t s) {
+  if (a.pcells <= 0) return hipSuccess;
+  long long blocks = std::min((a.pcells + kNT - 1) / kNT, 4096LL);
+  if (embed)
+    hipLaunchKernelGGL(embed_box<T>, dim3((unsigned)blocks), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(pbox_pressure<T>, dim3((unsigned)blocks), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s) {
   if (a.ns <= 0) return hipSuccess;
   hipLaunchKernelGGL(pressure_sample<T>, dim3((a.ns + kNT - 1) / kNT), dim3(kNT), 0, s, a);
@@ -1004,6 +1034,8 @@ template hipError_t launch_xfused<float>(const XArgs<float>&, int, hipStream_t);
 template hipError_t launch_xfused<double>(const XArgs<double>&, int, hipStream_t);
 template hipError_t launch_xplain<float>(int, int, const XArgs<float>&, int, hipStream_t);
 template hipError_t launch_xplain<double>(int, int, const XArgs<double>&, int, hipStream_t);
+template hipError_t launch_pbox<float>(int, const BoxArgs<float>&, hipStream_t);
+template hipError_t launch_pbox<double>(int, const BoxArgs<double>&, hipStream_t);
 template hipError_t launch_psample<float>(const PressArgs<float>&, hipStream_t);
 template hipError_t launch_psample<double>(const PressArgs<double>&, hipStream_t);
 template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);

@@ -59,6 +59,8 @@ template <typename T>
 hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_pbox(int embed, const BoxArgs<T>& a, hipStream_t s);
 
 template <typename T>
 hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s);

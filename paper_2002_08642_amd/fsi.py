@@ -39,7 +39,7 @@ EXPORTS = [
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
-    "fsi_sample_pressure", "fsi_get_pressure_loads",
+    "fsi_sample_pressure", "fsi_get_pressure_loads", "fsi_get_pressure_box", "fsi_adjoint_set_pressure_seed",
 ]
 
 
@@ -108,6 +108,8 @@ def load_library():
                                           ctypes.c_double, I32, D, D]
     lib.fsi_sample_pressure.argtypes = [P, I32, D, D]
     lib.fsi_get_pressure_loads.argtypes = [P, D, D]
+    lib.fsi_get_pressure_box.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
+    lib.fsi_adjoint_set_pressure_seed.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
     lib.fsi_ms_create.argtypes = [I32, D, ctypes.POINTER(P)]
     lib.fsi_ms_destroy.argtypes = [P]
     lib.fsi_ms_last_error.argtypes = [P]
@@ -190,6 +192,8 @@ class Solver:
                  pressure=False):
         self.lib = load_library()
         self.n = tuple(int(a) for a in n)
+        self.L = tuple(float(a) for a in L)
+        self.tw, self.h = float(tw), float(h)
         nx, ny, nz = self.n
         d = Desc(nx, ny, nz, float(L[0]), float(L[1]), float(L[2]), float(nu), float(eta), float(tw),
                  float(h), int(profile), int(precision), 1 if pressure else 0, stream)
@@ -310,6 +314,30 @@ class Solver:
         dp = np.zeros(self._nv)
         self._check(self.lib.fsi_get_pressure_loads(self.ctx, _dptr(loads), _dptr(dp)))
         return loads, dp
+
+    def pressure_box(self, values=True):
+        """(box0, p) of the current pressure box; p (nz, ny, nx of the box) of the
+        last step if values (fsi_get_pressure_box)."""
+        b0 = np.zeros(3, dtype=np.int32)
+        bn = np.zeros(3, dtype=np.int32)
+        self._check(self.lib.fsi_get_pressure_box(self.ctx, _iptr(b0), _iptr(bn), None))
+        if not values:
+            return b0, None
+        p = np.zeros((bn[2], bn[1], bn[0]))
+        self._check(self.lib.fsi_get_pressure_box(self.ctx, _iptr(b0), _iptr(bn), _dptr(p)))
+        return b0, p
+
+    def adjoint_set_pressure_seed(self, box0, lam_p):
+        """Seed the next step_adjoint with the cotangent of p on the pressure box."""
+        b0 = _i32(box0, (3,))
+        if lam_p is None:
+            bn = np.zeros(3, dtype=np.int32)
+            self._check(self.lib.fsi_get_pressure_box(self.ctx, _iptr(b0), _iptr(bn), None))
+            self._check(self.lib.fsi_adjoint_set_pressure_seed(self.ctx, _iptr(b0), _iptr(bn), None))
+            return
+        lam_p = _f64(lam_p)
+        bn = _i32([lam_p.shape[2], lam_p.shape[1], lam_p.shape[0]])
+        self._check(self.lib.fsi_adjoint_set_pressure_seed(self.ctx, _iptr(b0), _iptr(bn), _dptr(lam_p)))
 
     def mask(self):
         chi = np.zeros(self.shape3)

@@ -246,3 +246,58 @@ def test_torch_autograd_function():
     J.backward()
     _, g = ro.value_and_grad(cfg["alpha"])
     assert float(alpha.grad) == pytest.approx(g, rel=1e-12)
+
+
+@pytest.mark.parametrize("part", ["u", "x", "v"])
+@pytest.mark.parametrize("n,L", [((32, 24, 20), (2.0, 1.5, 1.25)), ((512, 16, 12), (8.0, 2.0, 1.5))])
+def test_pressure_seed_dot_product(part, n, L):
+    """One step in FSI mode with J = lam_p . p(box) + g . F + <lam_u, u_hat^1>:
+    the seeded adjoint step against central differences (the pressure path
+    Pi_hat = -i k.N'/|k|^2 and -|u|^2/2 included)."""
+    tw, h = (0.1, 0.06) if n[0] == 32 else (0.15, 0.1)  # the pressure box must fit the grid
+    s = fsi.Solver(n, L, 0.02, 0.05, tw, h, fsi.PROFILE_COS, fsi.PREC_FP64, pressure=True)
+    rng = np.random.default_rng(21)
+    u0 = synth.random_solenoidal_compact(n, L, seed=8)
+    du = synth.random_solenoidal_compact(n, L, seed=9) if part == "u" else 0 * u0
+    if n[0] == 32:
+        x0, tri = tilted_plate()
+    else:
+        u_ax = np.array([1.0, 0.07, 0.03]) / np.linalg.norm([1.0, 0.07, 0.03])
+        v_ax = np.cross([0.02, -0.05, 1.0], u_ax)
+        v_ax /= np.linalg.norm(v_ax)
+        x0, tri = synth.flat_rectangle((4.013, 1.027, 0.7431), u_ax, v_ax, 1.0, 0.25, 9, 4)
+        x0 = x0 + 0.004 * rng.standard_normal(x0.shape)
+    v0 = rng.standard_normal(x0.shape)
+    dx = 0.01 * rng.standard_normal(x0.shape) if part == "x" else 0 * x0
+    dv = rng.standard_normal(x0.shape) if part == "v" else 0 * x0
+    g = rng.standard_normal(3)
+    lam_u = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    s.set_spectrum(u0)
+    s.set_wing(x0, v0, tri)
+    box0, _ = s.pressure_box(values=False)
+    s.step(0.01)
+    _, pb = s.pressure_box()
+    lam_p = rng.standard_normal(pb.shape)
+
+    def run(eps, save=False):
+        s.set_spectrum(u0 + eps * du)
+        s.set_wing(x0 + eps * dx, v0 + eps * dv, tri)
+        b0, _ = s.pressure_box(values=False)
+        assert np.array_equal(b0, box0)
+        if save:
+            s.save(0)
+        s.step(0.01)
+        _, p = s.pressure_box()
+        return float(np.sum(lam_p * p) + np.dot(g, s.info()["F"]) + cdot(lam_u, s.spectrum()))
+
+    eps = 1e-5
+    fd = (run(eps) - run(-eps)) / (2 * eps)
+    run(0.0, save=True)
+    s.set_wing(x0, v0, tri)
+    s.adjoint_set(lam_u, None)
+    s.adjoint_set_pressure_seed(box0, lam_p)
+    gx, gv = s.step_adjoint(0, 0.01, 0.01, 1, g)
+    lu0, _ = s.adjoint_get()
+    adj = cdot(lu0, du) + float(np.sum(gx * dx) + np.sum(gv * dv))
+    print("pressure seed %s %s: adjoint %.12e fd %.12e" % (part, n, adj, fd), flush=True)
+    assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
