@@ -46,8 +46,8 @@ def algorithmic_bytes(n, wsize, cells):
     zslab = n * nb * kx1 * c       # [z][iy][ix]
     yslab = n * n * kx1 * c        # [z][y][ix]
     return {
-        "z_inverse_curl": 3 * compact + 6 * zslab,
-        "y_inverse": 6 * zslab + 6 * yslab,
+        "z_inverse_curl": 3 * compact + 5 * zslab,
+        "y_inverse": 5 * zslab + 6 * yslab,
         "x_fused": 9 * yslab + 4 * cells * wsize,
         "y_forward": 3 * yslab + 3 * zslab,
         "z_forward_update": 3 * zslab + 12 * compact,

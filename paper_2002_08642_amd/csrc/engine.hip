@@ -611,17 +611,17 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[0], s));
     if (wing_nt > 0 && bcells > 0) FSI_TRY(run_mask());
     if (ev) FSI_HIP(hipEventRecord(ev[1], s));
-    // P1: z inverse of u and of omega = i k x u
+    // P1: z inverse of u and of omega_x, omega_y (omega = i k x u)
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = uh;
       a.in_fs = clen;
       a.out = A;
       a.out_fs = Alen;
-      FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
+      FSI_HIP(launch_col<T>(COL_INV_CURL5, a, 1, s));  // u, omega_x, omega_y
     }
     if (ev) FSI_HIP(hipEventRecord(ev[2], s));
-    // P2: y inverse of the six fields
+    // P2: y inverse of the five fields, omega_z = i (kx uy - ky ux) formed on the way
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = A;
@@ -630,8 +630,7 @@ class Engine : public EngineBase {
       a.out = B;
       a.out_fs = Blen;
       a.out_bs = (long long)ny * kxp;
-      a.nf = 6;
-      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
+      FSI_HIP(launch_col<T>(COL_INV_WZ, a, nz, s));
     }
     if (ev) FSI_HIP(hipEventRecord(ev[3], s));
     // P3: x C2R, nonlinear + penalization term, diagnostics, x R2C

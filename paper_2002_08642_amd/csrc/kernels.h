@@ -25,7 +25,9 @@ enum ColMode {
   COL_FWD_PROJECT = 3,
   COL_FWD_UPDATE = 4,
   COL_FWD_ACC = 5,       // adjoint: out[f] += m_k * forward(in[f])   (m_k = 1 at kx = 0, else 2)
-  COL_FWD_ACC_CURL = 6   // adjoint: out += m_k * (i k x forward(in[0..2]))
+  COL_FWD_ACC_CURL = 6,  // adjoint: out += m_k * (i k x forward(in[0..2]))
+  COL_INV_CURL5 = 7,     // z inverse of u and of omega_x, omega_y (5 outputs)
+  COL_INV_WZ = 8         // y inverse of 5 fields plus omega_z = i (kx uy - ky ux) (6 outputs)
 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 

@@ -31,11 +31,13 @@ namespace fsi {
 // all of its row loads in flight at once.
 
 template <typename T, int W, int NT, int MAXE, int MODE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void col_pass(ColArgs<T> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int RSTEP = NT / W;
-  constexpr int MAXO = (2 * MAXE) / 3 + 2;  // band rows per thread (2K+1 <= 2n/3 + 1/3)
+  // band rows per thread: 2K + 1 <= (2n + 1)/3 rows over RSTEP-row strides with
+  // n <= MAXE RSTEP gives at most floor(2 MAXE / 3) + 1
+  constexpr int MAXO = (2 * MAXE) / 3 + 1;
   const int tid = threadIdx.x;
   const int col = tid % W;
   const int r0 = tid / W;
@@ -52,6 +54,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
     // components, produced in the order ux, wy, uz, wx, uy, wz so that two
     // register sets hold every component while it is needed (four component
     // loads per workgroup instead of nine).
+    constexpr bool CURLM = (MODE == COL_INV_CURL);
     const int nout = (MODE == COL_INV_CURL) ? 6 : a.nf;
     cpx<T> RA[MAXO], RB[MAXO];
     // component loaded for output o (-1: none) and whether it goes to RB; the load
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
     // it is in flight while output o is transformed.
     auto load_for = [&](int o) {
       int lq = o, into_b = 0;
-      if (MODE == COL_INV_CURL) {
+      if (CURLM) {
         lq = (o == 0) ? 0 : (o == 1) ? 2 : (o == 3) ? 1 : (o == 5) ? 0 : -1;
         into_b = (o == 1 || o == 5) ? 1 : 0;
       }
@@ -83,10 +86,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
       // output field and combination: o = 0 ux = A; 1 wy = i(kz A - kx B); 2 uz = B;
       // 3 wx = i(ky B - kz A); 4 uy = A; 5 wz = i(kx A - ky B)
-      const int fo = (MODE == COL_INV_CURL) ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
+      const int fo = CURLM ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
       T ka = 0, kb = 0;
       bool kza = false, kzb = false, cross = false;
-      if (MODE == COL_INV_CURL && (o & 1)) {
+      if (CURLM && (o & 1)) {
         const int ix = c % a.kxp, iy = c / a.kxp;
         const T kx = a.kfx * (T)ix;
         const T ky = a.kfy * (T)band_mode(iy, a.Ky);
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
         else if (o == 3) { kb = ky; kza = true; }
         else { ka = kx; kb = ky; }
       }
-      const bool useb = (MODE == COL_INV_CURL) && (o == 2 || o == 3);
+      const bool useb = CURLM && (o == 2 || o == 3);
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
@@ -118,6 +121,95 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void co
       }
       __syncthreads();
       if (o + 1 < nout) load_for(o + 1);
+      fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
+      cpx<T>* out = a.out + fo * a.out_fs + ob;
+      if (cok) {
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          if (r < n) out[(long long)r * a.ld + c] = buf[r * W + col];
+        }
+      }
+      __syncthreads();
+    }
+  } else if constexpr (MODE == COL_INV_CURL5 || MODE == COL_INV_WZ) {
+    // Stored fields of the forward step.  omega_z = i (kx uy - ky ux) needs no z
+    // derivative, so the z pass (COL_INV_CURL5) stores ux, uy, uz, wx, wy and the
+    // y pass (COL_INV_WZ) forms wz from ux, uy on the way.  Two register sets A,
+    // B; the load for output o + 1 is issued right after output o is in LDS so
+    // that it is in flight during that output's transform:
+    //  z pass (output: value, [load issued]): ux:A [B = uz]  wy:i(kz A - kx B)
+    //         uz:B [A = uy]  wx:i(ky B - kz A)  uy:A           3 loads, 5 outputs
+    //  y pass: ux:A [B = uy]  uy:B  wz:i(kx B - ky A) [A = uz]  uz:A [B = wx]
+    //         wx:B [A = wy]  wy:A                              5 loads, 6 outputs
+    // Each destination set has its own load site: one load followed by a choice
+    // of destination would have to complete before the choice.
+    constexpr bool Z5 = (MODE == COL_INV_CURL5);
+    constexpr int nout = Z5 ? 5 : 6;
+    cpx<T> RA[MAXO], RB[MAXO];
+    auto load_into = [&](int lq, cpx<T>(&R)[MAXO]) {
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + tq % W, rq = tq / W;
+      const bool okq = cq < a.C && (cq % a.kxp) < a.kx1;
+      const cpx<T>* in = a.in + lq * a.in_fs + ib;
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = rq + k * RSTEP;
+        R[k] = (okq && i < nb) ? in[(long long)i * a.ld + cq] : mk<T>(0, 0);
+      }
+    };
+    load_into(0, RA);
+#pragma unroll 1
+    for (int o = 0; o < nout; ++o) {
+      const int tid = opaque((int)threadIdx.x);
+      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+      const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+      // output field and source (0: A, 1: B, 2: cross term)
+      const int fo = Z5 ? ((o == 1) ? 4 : (o == 3) ? 3 : (o == 4) ? 1 : o)
+                        : ((o == 2) ? 5 : (o > 2) ? o - 1 : o);
+      const int src = Z5 ? ((o == 2) ? 1 : (o == 1 || o == 3) ? 2 : 0) : ((o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0);
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = Z5 ? a.kfy * (T)band_mode(iy, a.Ky) : (T)0;
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (i < nb) {
+          cpx<T> val = (src == 1) ? RB[k] : RA[k];
+          if (src == 2) {
+            // per-row wavenumber: kz in the z pass, ky in the y pass
+            const T krow = (Z5 ? a.kfz : a.kfy) * (T)band_mode(i, K);
+            cpx<T> t;
+            if (Z5) {
+              if (o == 1) t = scl(RA[k], krow) - scl(RB[k], kx);  // wy: kz ux - kx uz
+              else t = scl(RB[k], ky) - scl(RA[k], krow);          // wx: ky uz - kz uy
+            } else {
+              t = scl(RB[k], kx) - scl(RA[k], krow);               // wz: kx uy - ky ux
+            }
+            val = mk<T>(-t.im, t.re);  // i t
+          }
+          buf[band_to_row(i, K, n) * W + col] = val;
+        }
+      }
+      __syncthreads();
+      // next load: z pass o = 0 -> B = uz, o = 2 -> A = uy; y pass o = 0 -> B = uy,
+      // o = 2 -> A = uz, o = 3 -> B = wx, o = 4 -> A = wy
+      const int lq = Z5 ? ((o == 0) ? 2 : (o == 2) ? 1 : -1)
+                        : ((o == 0) ? 1 : (o == 2) ? 2 : (o == 3) ? 3 : (o == 4) ? 4 : -1);
+      const bool to_b = Z5 ? (o == 0) : (o == 0 || o == 3);
+      if (lq >= 0) {
+        if (to_b) {
+          asm volatile("" ::: "memory");  // keeps the two load sites apart
+          load_into(lq, RB);
+        } else {
+          load_into(lq, RA);
+        }
+      }
       fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
       if (cok) {
@@ -905,6 +997,8 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   switch (mode) {
     FSI_COL_CASE(COL_INV_PLAIN)
     FSI_COL_CASE(COL_INV_CURL)
+    FSI_COL_CASE(COL_INV_CURL5)
+    FSI_COL_CASE(COL_INV_WZ)
     FSI_COL_CASE(COL_FWD_PLAIN)
     FSI_COL_CASE(COL_FWD_PROJECT)
     FSI_COL_CASE(COL_FWD_UPDATE)
