@@ -44,7 +44,7 @@ def host_cxx():
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     if src in HOST_SOURCES:
-        cmd = [host_cxx(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(HERE, "..", "include"),
+        cmd = [host_cxx(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(HERE, "..", "include"),
                "-c", os.path.join(CSRC, src), "-o", obj]
     else:
         cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]

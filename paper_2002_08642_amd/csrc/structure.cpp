@@ -51,6 +51,43 @@ struct Band {
     a.assign((size_t)n * w, 0.0);
   }
   double& operator()(int i, int j) { return a[(size_t)i * w + (j - i + kl)]; }
+  // Symmetric positive definite case (kl = ku): Cholesky A = L L^T on the lower
+  // band, then A x = b in place; false (matrix partly overwritten) if a pivot
+  // is not positive.
+  bool solve_spd(std::vector<double>& b) {
+    const int bw = kl;
+    // row r of the band as a pointer indexed by column: at(r)[c] = A(r, c)
+    auto at = [&](int r) { return a.data() + (size_t)r * w + kl - r; };
+    for (int j = 0; j < n; ++j) {
+      const int k0 = std::max(0, j - bw);
+      double* rj = at(j);
+      double d = rj[j];
+      for (int k = k0; k < j; ++k) d -= rj[k] * rj[k];
+      if (!(d > 0.0) || !std::isfinite(d)) return false;
+      d = sqrt(d);
+      rj[j] = d;
+      const int iend = std::min(n - 1, j + bw);
+      for (int i = j + 1; i <= iend; ++i) {
+        double* ri = at(i);
+        double sum = ri[j];
+        for (int k = std::max(k0, i - bw); k < j; ++k) sum -= ri[k] * rj[k];
+        ri[j] = sum / d;
+      }
+    }
+    for (int i = 0; i < n; ++i) {  // L y = b
+      const double* ri = at(i);
+      double sum = b[i];
+      for (int k = std::max(0, i - bw); k < i; ++k) sum -= ri[k] * b[k];
+      b[i] = sum / ri[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+      double sum = b[i];
+      for (int k = i + 1; k <= std::min(n - 1, i + bw); ++k) sum -= at(k)[i] * b[k];
+      b[i] = sum / at(i)[i];
+    }
+    return true;
+  }
+
   // LU with partial pivoting, solving A x = b in place; false if singular.
   bool solve(std::vector<double>& b) {
     const int ue = kl + ku;  // upper bandwidth after pivoting
@@ -334,7 +371,9 @@ struct NoSink {
   void operator()(int, int, const double (&)[3][3]) const {}
 };
 
-// Reverse Cuthill-McKee order of the free vertices over the spring graph.
+// Order of the free vertices for the band solver: the narrowest band among
+// reverse Cuthill-McKee over the spring graph, the index order, and the order
+// along the principal axis of the current positions (structured wing meshes).
 void build_order(fsi_ms& ms) {
   std::vector<std::vector<int>> adj(ms.nv);
   auto link = [&](int a, int b) {
@@ -352,36 +391,88 @@ void build_order(fsi_ms& ms) {
     std::sort(l.begin(), l.end());
     l.erase(std::unique(l.begin(), l.end()), l.end());
   }
-  std::vector<int> order;
-  std::vector<char> seen(ms.nv, 0);
-  for (;;) {
-    int start = -1;
+  auto bandwidth = [&](const std::vector<int>& order) {
+    std::vector<int> slot(ms.nv, -1);
+    for (size_t k = 0; k < order.size(); ++k) slot[order[k]] = (int)k;
+    int bw = 0;
+    for (int u = 0; u < ms.nv; ++u)
+      for (int w : adj[u]) bw = std::max(bw, std::abs(slot[u] - slot[w]));
+    return bw;
+  };
+  std::vector<std::vector<int>> cand;
+  {  // reverse Cuthill-McKee from a minimum-degree vertex of each component
+    std::vector<int> order;
+    std::vector<char> seen(ms.nv, 0);
+    for (;;) {
+      int start = -1;
+      for (int i = 0; i < ms.nv; ++i)
+        if (!ms.is_clamped[i] && !seen[i] && (start < 0 || adj[i].size() < adj[start].size())) start = i;
+      if (start < 0) break;
+      std::deque<int> qu{start};
+      seen[start] = 1;
+      while (!qu.empty()) {
+        const int u = qu.front();
+        qu.pop_front();
+        order.push_back(u);
+        std::vector<int> nb;
+        for (int w : adj[u])
+          if (!seen[w]) {
+            seen[w] = 1;
+            nb.push_back(w);
+          }
+        std::sort(nb.begin(), nb.end(), [&](int p, int q) { return adj[p].size() < adj[q].size(); });
+        for (int w : nb) qu.push_back(w);
+      }
+    }
+    std::reverse(order.begin(), order.end());
+    cand.push_back(order);
+  }
+  {  // index order
+    std::vector<int> order;
     for (int i = 0; i < ms.nv; ++i)
-      if (!ms.is_clamped[i] && !seen[i] && (start < 0 || adj[i].size() < adj[start].size())) start = i;
-    if (start < 0) break;
-    std::deque<int> qu{start};
-    seen[start] = 1;
-    while (!qu.empty()) {
-      const int u = qu.front();
-      qu.pop_front();
-      order.push_back(u);
-      std::vector<int> nb;
-      for (int w : adj[u])
-        if (!seen[w]) {
-          seen[w] = 1;
-          nb.push_back(w);
-        }
-      std::sort(nb.begin(), nb.end(), [&](int p, int q) { return adj[p].size() < adj[q].size(); });
-      for (int w : nb) qu.push_back(w);
+      if (!ms.is_clamped[i]) order.push_back(i);
+    cand.push_back(order);
+  }
+  {  // principal axis of the positions (power iteration on the covariance)
+    std::vector<int> order;
+    double mean[3] = {0, 0, 0};
+    for (int i = 0; i < ms.nv; ++i)
+      for (int q = 0; q < 3; ++q) mean[q] += ms.x[3 * i + q] / ms.nv;
+    double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int i = 0; i < ms.nv; ++i)
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) C[p][q] += (ms.x[3 * i + p] - mean[p]) * (ms.x[3 * i + q] - mean[q]);
+    double e[3] = {1.0, 0.7, 0.3};
+    for (int it = 0; it < 100; ++it) {
+      double y[3];
+      for (int p = 0; p < 3; ++p) y[p] = C[p][0] * e[0] + C[p][1] * e[1] + C[p][2] * e[2];
+      const double nrm = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+      if (!(nrm > 0.0)) break;
+      for (int p = 0; p < 3; ++p) e[p] = y[p] / nrm;
+    }
+    std::vector<std::pair<double, int>> key;
+    for (int i = 0; i < ms.nv; ++i)
+      if (!ms.is_clamped[i]) key.push_back({e[0] * ms.x[3 * i] + e[1] * ms.x[3 * i + 1] + e[2] * ms.x[3 * i + 2], i});
+    std::stable_sort(key.begin(), key.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+      return a.first < b.first - 1e-12 * (1.0 + fabs(a.first));
+    });
+    for (auto& k : key) order.push_back(k.second);
+    cand.push_back(order);
+  }
+  size_t best = 0;
+  int best_bw = bandwidth(cand[0]);
+  for (size_t c = 1; c < cand.size(); ++c) {
+    const int b = bandwidth(cand[c]);
+    if (b < best_bw) {
+      best_bw = b;
+      best = c;
     }
   }
-  std::reverse(order.begin(), order.end());
+  const std::vector<int>& order = cand[best];
   ms.slot.assign(ms.nv, -1);
   for (size_t k = 0; k < order.size(); ++k) ms.slot[order[k]] = (int)k;
   ms.nfree = (int)order.size();
-  ms.vbw = 0;
-  for (int u = 0; u < ms.nv; ++u)
-    for (int w : adj[u]) ms.vbw = std::max(ms.vbw, std::abs(ms.slot[u] - ms.slot[w]));
+  ms.vbw = best_bw;
   ms.order_valid = true;
 }
 
@@ -650,7 +741,15 @@ fsi_status fsi_ms_step(fsi_ms* ms, double dt, const double* frame, const double*
                           gdt * gdt * (f[3 * u + d] + fe));
       }
     }
-    if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular Newton matrix");
+    {
+      // A is symmetric; Cholesky, else pivoted LU on a fresh assembly
+      const std::vector<double> r0 = r;
+      if (!A.solve_spd(r)) {
+        assemble(*ms, x.data(), F, 1.0, gdt * gdt, A, f);
+        r = r0;
+        if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular Newton matrix");
+      }
+    }
     double dn = 0.0, qn = 0.0;
     for (int u = 0; u < nv; ++u) {
       const int su = ms->slot[u];
@@ -718,7 +817,14 @@ fsi_status fsi_ms_step_adjoint(fsi_ms* ms, double dt, double dt_prev, const doub
     if (su < 0) continue;
     for (int d = 0; d < 3; ++d) w3[3 * su + d] = gdt * lam_x[3 * u + d] + lam_v[3 * u + d];
   }
-  if (!A.solve(w3)) return fail(ms, FSI_ESTATE, "singular Newton matrix in the adjoint step");
+  {
+    const std::vector<double> w30 = w3;
+    if (!A.solve_spd(w3)) {
+      assemble(*ms, x_new, F, 1.0, gdt * gdt, A, f);
+      w3 = w30;
+      if (!A.solve(w3)) return fail(ms, FSI_ESTATE, "singular Newton matrix in the adjoint step");
+    }
+  }
   std::vector<double> w(3 * nv, 0.0);  // M^-1 mu_v on the free vertices, 0 on clamped ones
   for (int u = 0; u < nv; ++u)
     if (ms->slot[u] >= 0)
@@ -808,7 +914,14 @@ fsi_status fsi_ms_static(fsi_ms* ms, const double* frame, const double* f_ext, i
         // H dx = F_int + lam F_ext (Newton on F_int(x) + lam F_ext = 0, with dF_int/dx = -H)
         for (int d = 0; d < 3; ++d) r[3 * su + d] = f[3 * u + d] + lam * (f_ext ? f_ext[3 * u + d] : 0.0);
       }
-      if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular stiffness matrix");
+      {
+        const std::vector<double> r0 = r;
+        if (!A.solve_spd(r)) {
+          assemble(*ms, x.data(), F, 0.0, 1.0, A, f);
+          r = r0;
+          if (!A.solve(r)) return fail(ms, FSI_ESTATE, "singular stiffness matrix");
+        }
+      }
       double dn = 0.0, xn = 0.0;
       for (int u = 0; u < nv; ++u) {
         const int su = ms->slot[u];
