@@ -43,6 +43,41 @@ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> scl(cpx<T> a, T s) { return mk(a.re * s, a.im * s); }
+
+#ifndef FSI_NT
+#define FSI_NT 3
+#endif
+// Streamed global accesses: every element of a pass's fields is read or written
+// once.  FSI_NT bit 0 marks the stores non-temporal, bit 1 the loads.
+template <typename T>
+__device__ __forceinline__ void st_stream(cpx<T>* p, cpx<T> v) {
+#if FSI_NT & 1
+  typedef T V __attribute__((ext_vector_type(2)));
+  V w;
+  w.x = v.re;
+  w.y = v.im;
+  __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+#else
+  *p = v;
+#endif
+}
+template <bool NT, typename T>
+__device__ __forceinline__ cpx<T> ld_hint(const cpx<T>* p) {
+  if constexpr (NT) {
+    typedef T V __attribute__((ext_vector_type(2)));
+    const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    return mk<T>(w.x, w.y);
+  } else {
+    return *p;
+  }
+}
+// column-pass inputs, the state read by the update, x-pass inputs
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* p) { return ld_hint<(FSI_NT & 2) != 0>(p); }
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_state(const cpx<T>* p) { return ld_hint<(FSI_NT & 4) != 0>(p); }
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_xin(const cpx<T>* p) { return ld_hint<(FSI_NT & 8) != 0>(p); }
 template <typename T>
 __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.re, -a.im); }
 // multiply by +i (sgn = +1) or -i (sgn = -1)
@@ -214,6 +249,19 @@ __device__ void fft_lds(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
       default: fft_stage<T, 3, W, RS, NT, MAXE, INV>(buf, p.n, Ns, tw); break;
     }
     Ns *= R;
+  }
+}
+
+// Column transform: N = 512 uses three radix-8 stages with compile-time strides
+// (the 512^3 grids), any other N the run-time plan.
+template <typename T, int W, int NT, int MAXE, bool INV, int N>
+__device__ __forceinline__ void col_fft(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
+  if constexpr (N == 512) {
+    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 1, tw);
+    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 8, tw);
+    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 64, tw);
+  } else {
+    fft_lds<T, W, W, NT, MAXE, INV>(buf, p, tw);
   }
 }
 

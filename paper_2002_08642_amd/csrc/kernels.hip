@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_util.h"
 #include "kernels.h"
@@ -30,7 +31,7 @@ namespace fsi {
 // into registers before they are written to LDS, so that each thread keeps
 // all of its row loads in flight at once.
 
-template <typename T, int W, int NT, int MAXE, int MODE>
+template <typename T, int W, int NT, int MAXE, int MODE, int N>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -43,7 +44,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
   const int r0 = tid / W;
   const int c = blockIdx.x * W + col;
   const bool cok = c < a.C && (c % a.kxp) < a.kx1;
-  const int n = a.n, K = a.K, nb = 2 * K + 1;
+  // N = 512: the column length and its 2/3 band are compile-time constants
+  const int n = N ? N : a.n, K = N ? (N - 1) / 3 : a.K, nb = 2 * K + 1;
   const long long ib = (long long)blockIdx.y * a.in_bs;
   const long long ob = (long long)blockIdx.y * a.out_bs;
   cpx<T>* tws = buf + n * W;
@@ -69,12 +71,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       if (lq < 0) return;
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
-      const bool okq = cq < a.C && (cq % a.kxp) < a.kx1;
-      const cpx<T>* in = a.in + lq * a.in_fs + ib;
+      // unconditional loads from clamped rows and columns: a load under a branch
+      // makes the compiler wait for it where the branches join, which would end
+      // the overlap with the transform; invalid values are replaced by zero when
+      // they are written to LDS
+      const cpx<T>* in = a.in + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
       for (int k = 0; k < MAXO; ++k) {
         const int i = rq + k * RSTEP;
-        const cpx<T> val = (okq && i < nb) ? in[(long long)i * a.ld + cq] : mk<T>(0, 0);
+        const cpx<T> val = ld_stream(in + (long long)(i < nb ? i : 0) * a.ld);
         if (into_b) RB[k] = val;
         else RA[k] = val;
       }
@@ -116,18 +121,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             if (o == 3) t = mk<T>(-t.re, -t.im);
             val = mk<T>(-t.im, t.re);  // i t
           }
-          buf[band_to_row(i, K, n) * W + col] = val;
+          buf[band_to_row(i, K, n) * W + col] = cok ? val : mk<T>(0, 0);
         }
       }
       __syncthreads();
       if (o + 1 < nout) load_for(o + 1);
-      fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
+      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
       if (cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
-          if (r < n) out[(long long)r * a.ld + c] = buf[r * W + col];
+          if (r < n) st_stream(out + (long long)r * a.ld + c, buf[r * W + col]);
         }
       }
       __syncthreads();
@@ -142,32 +147,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     //         uz:B [A = uy]  wx:i(ky B - kz A)  uy:A           3 loads, 5 outputs
     //  y pass: ux:A [B = uy]  uy:B  wz:i(kx B - ky A) [A = uz]  uz:A [B = wx]
     //         wx:B [A = wy]  wy:A                              5 loads, 6 outputs
-    // Each destination set has its own load site: one load followed by a choice
-    // of destination would have to complete before the choice.
+    // The outputs are generated at compile time (one code path per output), so
+    // that no register set is merged across branches: a merge copies the
+    // registers and has to wait for loads still in flight.
     constexpr bool Z5 = (MODE == COL_INV_CURL5);
-    constexpr int nout = Z5 ? 5 : 6;
     cpx<T> RA[MAXO], RB[MAXO];
     auto load_into = [&](int lq, cpx<T>(&R)[MAXO]) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
-      const bool okq = cq < a.C && (cq % a.kxp) < a.kx1;
-      const cpx<T>* in = a.in + lq * a.in_fs + ib;
+      // unconditional loads (clamped rows and columns), zeroed when written to
+      // LDS: a load under a branch would also be waited for where the branches join
+      const cpx<T>* in = a.in + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
       for (int k = 0; k < MAXO; ++k) {
         const int i = rq + k * RSTEP;
-        R[k] = (okq && i < nb) ? in[(long long)i * a.ld + cq] : mk<T>(0, 0);
+        R[k] = ld_stream(in + (long long)(i < nb ? i : 0) * a.ld);
       }
     };
-    load_into(0, RA);
-#pragma unroll 1
-    for (int o = 0; o < nout; ++o) {
+    auto step = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      // output field, source (0: A, 1: B, 2: cross term), next load and its set
+      constexpr int fo = Z5 ? ((o == 1) ? 4 : (o == 3) ? 3 : (o == 4) ? 1 : o) : ((o == 2) ? 5 : (o > 2) ? o - 1 : o);
+      constexpr int src = Z5 ? ((o == 2) ? 1 : (o == 1 || o == 3) ? 2 : 0) : ((o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0);
+      constexpr int lq = Z5 ? ((o == 0) ? 2 : (o == 2) ? 1 : -1) : ((o == 0) ? 1 : (o == 2) ? 2 : (o == 3) ? 3 : (o == 4) ? 4 : -1);
+      constexpr bool to_b = Z5 ? (o == 0) : (o == 0 || o == 3);
       const int tid = opaque((int)threadIdx.x);
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
-      // output field and source (0: A, 1: B, 2: cross term)
-      const int fo = Z5 ? ((o == 1) ? 4 : (o == 3) ? 3 : (o == 4) ? 1 : o)
-                        : ((o == 2) ? 5 : (o > 2) ? o - 1 : o);
-      const int src = Z5 ? ((o == 2) ? 1 : (o == 1 || o == 3) ? 2 : 0) : ((o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0);
       const int ix = c % a.kxp, iy = c / a.kxp;
       const T kx = a.kfx * (T)ix;
       const T ky = Z5 ? a.kfy * (T)band_mode(iy, a.Ky) : (T)0;
@@ -181,46 +187,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         const int i = r0 + k * RSTEP;
         if (i < nb) {
           cpx<T> val = (src == 1) ? RB[k] : RA[k];
-          if (src == 2) {
+          if constexpr (src == 2) {
             // per-row wavenumber: kz in the z pass, ky in the y pass
             const T krow = (Z5 ? a.kfz : a.kfy) * (T)band_mode(i, K);
             cpx<T> t;
-            if (Z5) {
-              if (o == 1) t = scl(RA[k], krow) - scl(RB[k], kx);  // wy: kz ux - kx uz
-              else t = scl(RB[k], ky) - scl(RA[k], krow);          // wx: ky uz - kz uy
-            } else {
-              t = scl(RB[k], kx) - scl(RA[k], krow);               // wz: kx uy - ky ux
-            }
+            if constexpr (Z5 && o == 1) t = scl(RA[k], krow) - scl(RB[k], kx);  // wy: kz ux - kx uz
+            else if constexpr (Z5) t = scl(RB[k], ky) - scl(RA[k], krow);       // wx: ky uz - kz uy
+            else t = scl(RB[k], kx) - scl(RA[k], krow);                          // wz: kx uy - ky ux
             val = mk<T>(-t.im, t.re);  // i t
           }
-          buf[band_to_row(i, K, n) * W + col] = val;
+          buf[band_to_row(i, K, n) * W + col] = cok ? val : mk<T>(0, 0);
         }
       }
       __syncthreads();
-      // next load: z pass o = 0 -> B = uz, o = 2 -> A = uy; y pass o = 0 -> B = uy,
-      // o = 2 -> A = uz, o = 3 -> B = wx, o = 4 -> A = wy
-      const int lq = Z5 ? ((o == 0) ? 2 : (o == 2) ? 1 : -1)
-                        : ((o == 0) ? 1 : (o == 2) ? 2 : (o == 3) ? 3 : (o == 4) ? 4 : -1);
-      const bool to_b = Z5 ? (o == 0) : (o == 0 || o == 3);
-      if (lq >= 0) {
-        if (to_b) {
-          asm volatile("" ::: "memory");  // keeps the two load sites apart
-          load_into(lq, RB);
-        } else {
-          load_into(lq, RA);
-        }
+      if constexpr (lq >= 0) {
+        if constexpr (to_b) load_into(lq, RB);
+        else load_into(lq, RA);
       }
-      fft_lds<T, W, W, NT, MAXE, true>(buf, a.plan, tws);
+      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
       if (cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
-          if (r < n) out[(long long)r * a.ld + c] = buf[r * W + col];
+          if (r < n) st_stream(out + (long long)r * a.ld + c, buf[r * W + col]);
         }
       }
       __syncthreads();
-    }
+    };
+    load_into(0, RA);
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 1>{});
+    step(std::integral_constant<int, 2>{});
+    step(std::integral_constant<int, 3>{});
+    step(std::integral_constant<int, 4>{});
+    if constexpr (!Z5) step(std::integral_constant<int, 5>{});
   } else {
     // forward modes: all n rows in, band rows out
     const int nfield = (MODE == COL_FWD_PLAIN || MODE == COL_FWD_ACC) ? a.nf : 3;
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
-        tmp[k] = (cok && r < n) ? in[(long long)r * a.ld + c] : mk<T>(0, 0);
+        tmp[k] = (cok && r < n) ? ld_stream(in + (long long)r * a.ld + c) : mk<T>(0, 0);
       }
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
@@ -241,14 +242,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         if (r < n) buf[r * W + col] = tmp[k];
       }
       __syncthreads();
-      fft_lds<T, W, W, NT, MAXE, false>(buf, a.plan, tws);
+      col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       if (MODE == COL_FWD_PLAIN) {
         cpx<T>* out = a.out + f * a.out_fs + ob;
         if (cok) {
 #pragma unroll
           for (int k = 0; k < MAXO; ++k) {
             const int i = r0 + k * RSTEP;
-            if (i < nb) out[(long long)i * a.ld + c] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+            if (i < nb) st_stream(out + (long long)i * a.ld + c, scl(buf[band_to_row(i, K, n) * W + col], a.scale));
           }
         }
         __syncthreads();
@@ -352,18 +353,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             if (a.first) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                const cpx<T> u = a.uh[q * a.cfs + idx];
-                a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en);
-                a.nh[q * a.cfs + idx] = nn[q];
+                const cpx<T> u = ld_state(a.uh + q * a.cfs + idx);
+                st_stream(a.uh + q * a.cfs + idx, scl(u + scl(nn[q], c1), en));
+                st_stream(a.nh + q * a.cfs + idx, nn[q]);
               }
             } else {
               const T ee = en * dev_exp<T>(-a.nu * k2 * dtp);
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                const cpx<T> u = a.uh[q * a.cfs + idx];
-                const cpx<T> np = a.nh[q * a.cfs + idx];
-                a.uh[q * a.cfs + idx] = scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee);
-                a.nh[q * a.cfs + idx] = nn[q];
+                const cpx<T> u = ld_state(a.uh + q * a.cfs + idx);
+                const cpx<T> np = ld_state(a.nh + q * a.cfs + idx);
+                st_stream(a.uh + q * a.cfs + idx, scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee));
+                st_stream(a.nh + q * a.cfs + idx, nn[q]);
               }
             }
           }
@@ -988,11 +989,21 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   dim3 grid((a.C + W - 1) / W, slices);
   const size_t lds = (size_t)a.n * (W + 1) * sizeof(cpx<T>);
   hipError_t e = hipSuccess;
-#define FSI_COL_CASE(M)                                                           \
-  case M:                                                                         \
-    e = set_lds(col_pass<T, W, NT, MAXE, M>, lds);                                \
-    if (e != hipSuccess) return e;                                                \
-    hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M>), grid, dim3(NT), lds, s, a); \
+  // the width that holds 512-point columns gets the compile-time 512 transform
+  constexpr bool k512 = (W * 512 == NT * MAXE);
+  const bool use512 = k512 && a.n == 512 && a.K == 170;
+#define FSI_COL_CASE(M)                                                                \
+  case M:                                                                              \
+    if (use512) {                                                                      \
+      e = set_lds(col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>, lds);                   \
+      if (e != hipSuccess) return e;                                                   \
+      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>), grid, dim3(NT), \
+                         lds, s, a);                                                   \
+    } else {                                                                           \
+      e = set_lds(col_pass<T, W, NT, MAXE, M, 0>, lds);                                \
+      if (e != hipSuccess) return e;                                                   \
+      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, 0>), grid, dim3(NT), lds, s, a); \
+    }                                                                                  \
     break;
   switch (mode) {
     FSI_COL_CASE(COL_INV_PLAIN)

@@ -92,8 +92,8 @@ __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, 
     if (k <= K) {
       const cpx<T> zc = conj(p);
       const cpx<T> d = g[r] - zc;
-      dx[k] = scl(g[r] + zc, (T)0.5);
-      dy[k] = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+      st_stream(dx + k, scl(g[r] + zc, (T)0.5));
+      st_stream(dy + k, mk<T>((T)0.5 * d.im, (T)-0.5 * d.re));
     }
   }
 }
@@ -113,12 +113,12 @@ __device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int la
   for (int q = 0; q < 3; ++q) {
     const int k = lane + 64 * q;  // direct slots r = q
     const bool ok = k <= K;
-    w.a[q] = ok ? A[k] : mk<T>(0, 0);
-    w.b[q] = ok ? B[k] : mk<T>(0, 0);
+    w.a[q] = ok ? ld_xin(A + k) : mk<T>(0, 0);
+    w.b[q] = ok ? ld_xin(B + k) : mk<T>(0, 0);
     const int kp = lane + 64 * (5 + q);  // partner slots r = 5 + q
     const bool okp = kp >= n - K;
-    w.a[3 + q] = okp ? A[n - kp] : mk<T>(0, 0);
-    w.b[3 + q] = okp ? B[n - kp] : mk<T>(0, 0);
+    w.a[3 + q] = okp ? ld_xin(A + (n - kp)) : mk<T>(0, 0);
+    w.b[3 + q] = okp ? ld_xin(B + (n - kp)) : mk<T>(0, 0);
   }
 }
 
