@@ -226,22 +226,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     // forward modes: all n rows in, band rows out
     const int nfield = (MODE == COL_FWD_PLAIN || MODE == COL_FWD_ACC) ? a.nf : 3;
     cpx<T> st[2][MAXO];
-    for (int f = 0; f < nfield; ++f) {
-      const int tid = opaque((int)threadIdx.x);
-      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
-      const cpx<T>* in = a.in + f * a.in_fs + ib;
-      cpx<T> tmp[MAXE];
+    cpx<T> tmp[MAXE];
+    // rows of field f into tmp: unconditional loads (clamped row and column);
+    // columns outside the band are transformed but never stored
+    auto load_field = [&](int f) __attribute__((always_inline)) {
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + tq % W, rq = tq / W;
+      const cpx<T>* in = a.in + f * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
-        const int r = r0 + k * RSTEP;
-        tmp[k] = (cok && r < n) ? ld_stream(in + (long long)r * a.ld + c) : mk<T>(0, 0);
+        const int r = rq + k * RSTEP;
+        tmp[k] = ld_stream(in + (long long)(r < n ? r : 0) * a.ld);
       }
+    };
+    // field f from tmp: LDS, transform, band rows out (or stashed); with
+    // prefetch, the loads of field f + 1 are in flight during the transform
+    auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
+      const int tid = opaque((int)threadIdx.x);
+      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
         if (r < n) buf[r * W + col] = tmp[k];
       }
       __syncthreads();
+      if (prefetch) load_field(f + 1);
       col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       if (MODE == COL_FWD_PLAIN) {
         cpx<T>* out = a.out + f * a.out_fs + ob;
@@ -268,17 +277,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
         __syncthreads();
       } else if (f < 2) {
+        // one loop per stash (a run-time register index would go to scratch)
+        if (f == 0) {
 #pragma unroll
-        for (int k = 0; k < MAXO; ++k) {
-          const int i = r0 + k * RSTEP;
-          if (i < nb) {
-            // no run-time register index (it would spill to scratch)
-            const cpx<T> val = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
-            if (f == 0) st[0][k] = val;
-            else st[1][k] = val;
+          for (int k = 0; k < MAXO; ++k) {
+            const int i = r0 + k * RSTEP;
+            if (i < nb) st[0][k] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < MAXO; ++k) {
+            const int i = r0 + k * RSTEP;
+            if (i < nb) st[1][k] = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
           }
         }
         __syncthreads();
+      }
+    };
+    if constexpr (MODE != COL_FWD_PLAIN && MODE != COL_FWD_ACC) {
+      // three fields in a compile-time sequence: the prefetched registers are
+      // never merged across branches (a merge would wait for the loads)
+      load_field(0);
+      field(0, true);
+      field(1, true);
+      field(2, false);
+    } else if constexpr (N == 512) {
+      load_field(0);
+      if (nfield == 3) {
+        field(0, true);
+        field(1, true);
+        field(2, false);
+      } else if (nfield == 6) {
+        field(0, true);
+        field(1, true);
+        field(2, true);
+        field(3, true);
+        field(4, true);
+        field(5, false);
+      } else {
+        for (int f = 0; f < nfield; ++f) {
+          if (f > 0) load_field(f);
+          field(f, false);
+        }
+      }
+    } else {
+      for (int f = 0; f < nfield; ++f) {
+        load_field(f);
+        field(f, false);
       }
     }
     if constexpr (MODE == COL_FWD_ACC_CURL) {
@@ -1075,8 +1120,11 @@ hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s) {
 // Workgroups of the fused x pass for nlines lines of length n (bounded: each
 // workgroup leaves one row of partial sums).
 int xfused_grid(int n, long long nlines, int lines_per_group) {
+#ifndef FSI_XGRID
+#define FSI_XGRID 4096
+#endif
   const long long units = (n == 512) ? nlines / 8 : nlines / lines_per_group;
-  return (int)std::max(1LL, std::min(units, 4096LL));
+  return (int)std::max(1LL, std::min(units, (long long)FSI_XGRID));
 }
 
 template <typename T, int NF, int L>
