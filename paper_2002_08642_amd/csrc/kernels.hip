@@ -46,6 +46,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
   const bool cok = c < a.C && (c % a.kxp) < a.kx1;
   // N = 512: the column length and its 2/3 band are compile-time constants
   const int n = N ? N : a.n, K = N ? (N - 1) / 3 : a.K, nb = 2 * K + 1;
+  // the RSTEP-row strides of a thread cover the column exactly: no row test
+  constexpr bool FULL = N != 0 && N == MAXE * RSTEP;
   const long long ib = (long long)blockIdx.y * a.in_bs;
   const long long ob = (long long)blockIdx.y * a.out_bs;
   cpx<T>* tws = buf + n * W;
@@ -128,11 +130,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       if (o + 1 < nout) load_for(o + 1);
       col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
+      // every LDS read first, then the stores: reading each value just before
+      // its store would put an LDS round trip in front of every store
+      cpx<T> ov[MAXE];
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+      }
       if (cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
-          if (r < n) st_stream(out + (long long)r * a.ld + c, buf[r * W + col]);
+          if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
         }
       }
       __syncthreads();
@@ -206,11 +216,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       }
       col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
+      // every LDS read first, then the stores: reading each value just before
+      // its store would put an LDS round trip in front of every store
+      cpx<T> ov[MAXE];
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+      }
       if (cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
-          if (r < n) st_stream(out + (long long)r * a.ld + c, buf[r * W + col]);
+          if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
         }
       }
       __syncthreads();
@@ -236,7 +254,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = rq + k * RSTEP;
-        tmp[k] = ld_stream(in + (long long)(r < n ? r : 0) * a.ld);
+        tmp[k] = ld_stream(in + (long long)((FULL || r < n) ? r : 0) * a.ld);
       }
     };
     // field f from tmp: LDS, transform, band rows out (or stashed); with
@@ -247,32 +265,44 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
-        if (r < n) buf[r * W + col] = tmp[k];
+        if (FULL || r < n) buf[r * W + col] = tmp[k];
       }
       __syncthreads();
       if (prefetch) load_field(f + 1);
       col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       if (MODE == COL_FWD_PLAIN) {
         cpx<T>* out = a.out + f * a.out_fs + ob;
+        cpx<T> ov[MAXO];  // LDS reads first, then the stores
+#pragma unroll
+        for (int k = 0; k < MAXO; ++k) {
+          const int i = r0 + k * RSTEP;
+          ov[k] = buf[band_to_row(i < nb ? i : 0, K, n) * W + col];
+        }
         if (cok) {
 #pragma unroll
           for (int k = 0; k < MAXO; ++k) {
             const int i = r0 + k * RSTEP;
-            if (i < nb) st_stream(out + (long long)i * a.ld + c, scl(buf[band_to_row(i, K, n) * W + col], a.scale));
+            if (i < nb) st_stream(out + (long long)i * a.ld + c, scl(ov[k], a.scale));
           }
         }
         __syncthreads();
       } else if (MODE == COL_FWD_ACC) {
         cpx<T>* out = a.out + f * a.cfs;
         const T m = a.scale * (T)((c % a.kxp) == 0 ? 1 : 2);
+        // all loads before the stores (a load after a store that may alias it
+        // waits for the store)
+        cpx<T> ov[MAXO];
+        const int cl = c < a.C ? c : 0;
+#pragma unroll
+        for (int k = 0; k < MAXO; ++k) {
+          const int i = r0 + k * RSTEP;
+          ov[k] = out[(long long)(i < nb ? i : 0) * a.ld + cl];
+        }
         if (cok) {
 #pragma unroll
           for (int k = 0; k < MAXO; ++k) {
             const int i = r0 + k * RSTEP;
-            if (i < nb) {
-              const long long idx = (long long)i * a.ld + c;
-              out[idx] = out[idx] + scl(buf[band_to_row(i, K, n) * W + col], m);
-            }
+            if (i < nb) out[(long long)i * a.ld + c] = ov[k] + scl(buf[band_to_row(i, K, n) * W + col], m);
           }
         }
         __syncthreads();
@@ -367,48 +397,66 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
           c2 = (T)(d_n * 0.5 * xi);
         }
       }
+      // Rows in chunks of KC: every load of a chunk is issued before its first
+      // store.  The stores may alias the loads as far as the compiler can tell,
+      // so a load placed after a store waits for that store's round trip.
+      constexpr int KC = sizeof(T) == 4 ? 3 : 1;
+      const int cl = c < a.C ? c : 0;  // clamped column of the unconditional loads
 #pragma unroll
-      for (int k = 0; k < MAXO; ++k) {
-        const int i = r0 + k * RSTEP;
-        if (cok && i < nb) {
-          const T kz = a.kfz * (T)band_mode(i, K);
-          cpx<T> n0 = st[0][k], n1 = st[1][k];
-          cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
-          const T k2 = kx * kx + ky * ky + kz * kz;
-          const long long idx = (long long)i * a.ld + c;
-          if (k2 > (T)0) {
-            const T ik2 = (T)1 / k2;
-            cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
-            n0 = n0 - scl(sp, kx);
-            n1 = n1 - scl(sp, ky);
-            n2 = n2 - scl(sp, kz);
-            if constexpr (MODE == COL_FWD_UPDATE) {
-              if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
-            }
-          } else if constexpr (MODE == COL_FWD_UPDATE) {
-            if (a.pi) a.pi[idx] = mk<T>(0, 0);
-          }
-          if constexpr (MODE == COL_FWD_PROJECT) {
-            a.out[idx] = n0;
-            a.out[a.cfs + idx] = n1;
-            a.out[2 * a.cfs + idx] = n2;
-          } else {
-            const T en = dev_exp<T>(-a.nu * k2 * dtn);
-            const cpx<T> nn[3] = {n0, n1, n2};
-            if (a.first) {
+      for (int k0 = 0; k0 < MAXO; k0 += KC) {
+        cpx<T> uo[KC][3], po[KC][3];
+        if constexpr (MODE == COL_FWD_UPDATE) {
+#pragma unroll
+          for (int kk = 0; kk < KC; ++kk) {
+            const int k = k0 + kk;
+            if (k < MAXO) {
+              const int i = r0 + k * RSTEP;
+              const long long idx = (long long)(i < nb ? i : 0) * a.ld + cl;
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                const cpx<T> u = ld_state(a.uh + q * a.cfs + idx);
-                st_stream(a.uh + q * a.cfs + idx, scl(u + scl(nn[q], c1), en));
-                st_stream(a.nh + q * a.cfs + idx, nn[q]);
+                uo[kk][q] = ld_state(a.uh + q * a.cfs + idx);
+                po[kk][q] = ld_state(a.nh + q * a.cfs + idx);  // unused on the first step
               }
+            }
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+          const int k = k0 + kk;
+          if (k >= MAXO) break;
+          const int i = r0 + k * RSTEP;
+          if (cok && i < nb) {
+            const T kz = a.kfz * (T)band_mode(i, K);
+            cpx<T> n0 = st[0][k], n1 = st[1][k];
+            cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+            const T k2 = kx * kx + ky * ky + kz * kz;
+            const long long idx = (long long)i * a.ld + c;
+            if (k2 > (T)0) {
+              const T ik2 = (T)1 / k2;
+              cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
+              n0 = n0 - scl(sp, kx);
+              n1 = n1 - scl(sp, ky);
+              n2 = n2 - scl(sp, kz);
+              if constexpr (MODE == COL_FWD_UPDATE) {
+                if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
+              }
+            } else if constexpr (MODE == COL_FWD_UPDATE) {
+              if (a.pi) a.pi[idx] = mk<T>(0, 0);
+            }
+            if constexpr (MODE == COL_FWD_PROJECT) {
+              a.out[idx] = n0;
+              a.out[a.cfs + idx] = n1;
+              a.out[2 * a.cfs + idx] = n2;
             } else {
-              const T ee = en * dev_exp<T>(-a.nu * k2 * dtp);
+              const T en = dev_exp<T>(-a.nu * k2 * dtn);
+              const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
+              const cpx<T> nn[3] = {n0, n1, n2};
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                const cpx<T> u = ld_state(a.uh + q * a.cfs + idx);
-                const cpx<T> np = ld_state(a.nh + q * a.cfs + idx);
-                st_stream(a.uh + q * a.cfs + idx, scl(u + scl(nn[q], c1), en) - scl(np, c2 * ee));
+                const cpx<T> u1 = scl(uo[kk][q] + scl(nn[q], c1), en);
+                // first step: Euler, the stored previous term is not read
+                const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
+                st_stream(a.uh + q * a.cfs + idx, u2);
                 st_stream(a.nh + q * a.cfs + idx, nn[q]);
               }
             }
