@@ -673,7 +673,8 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
 #pragma unroll
     for (int j = 0; j < 8; ++j) P[p][j] = v[j];
   }
-  if (next >= 0) load512_sig<T>(a, next, 0, lane, pf);
+  // unconditional (the last line reloads itself): see load512
+  load512_sig<T>(a, next >= 0 ? next : line, 0, lane, pf);
   // pointwise: G = u x omega - (chi/eta)(u - u_s) and the diagnostics
   cpx<T> g[8];
 #pragma unroll

@@ -100,35 +100,40 @@ __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, 
 
 // Raw spectral values a lane needs for one packed signal of one line: A, B at
 // k = lane + 64 r (r = 0, 1, 2) and at the Hermitian partners n - k of
-// k = lane + 64 r (r = 5, 6, 7); slots outside the 2/3 band are zero.
+// k = lane + 64 r (r = 5, 6, 7); slots outside the 2/3 band are zeroed by pack512.
 template <typename T>
 struct Raw512 {
   cpx<T> a[6], b[6];
 };
 
+// The loads are unconditional (slots outside the band read index 0): a load
+// under a branch leaves the number of loads in flight unknown to the compiler,
+// which then waits for all of them, including a prefetch, at the next use.
 template <typename T>
 __device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int lane, Raw512<T>& w) {
   constexpr int n = 512, K = 170;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int k = lane + 64 * q;  // direct slots r = q
-    const bool ok = k <= K;
-    w.a[q] = ok ? ld_xin(A + k) : mk<T>(0, 0);
-    w.b[q] = ok ? ld_xin(B + k) : mk<T>(0, 0);
+    const int kc = k <= K ? k : 0;
+    w.a[q] = ld_xin(A + kc);
+    w.b[q] = ld_xin(B + kc);
     const int kp = lane + 64 * (5 + q);  // partner slots r = 5 + q
-    const bool okp = kp >= n - K;
-    w.a[3 + q] = okp ? ld_xin(A + (n - kp)) : mk<T>(0, 0);
-    w.b[3 + q] = okp ? ld_xin(B + (n - kp)) : mk<T>(0, 0);
+    const int kpc = kp >= n - K ? n - kp : 0;
+    w.a[3 + q] = ld_xin(A + kpc);
+    w.b[3 + q] = ld_xin(B + kpc);
   }
 }
 
 // Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout v[r] = Z[lane + 64 r].
 template <typename T>
 __device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v)[8]) {
+  constexpr int n = 512, K = 170;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
-    v[5 + q] = mk<T>(w.a[3 + q].re + w.b[3 + q].im, w.b[3 + q].re - w.a[3 + q].im);
+    const bool ok = lane + 64 * q <= K, okp = lane + 64 * (5 + q) >= n - K;
+    v[q] = ok ? mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re) : mk<T>(0, 0);
+    v[5 + q] = okp ? mk<T>(w.a[3 + q].re + w.b[3 + q].im, w.b[3 + q].re - w.a[3 + q].im) : mk<T>(0, 0);
   }
   if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
   v[3] = mk<T>(0, 0);
