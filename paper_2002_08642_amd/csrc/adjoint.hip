@@ -321,7 +321,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void xadj_wave512(XAdjArgs<T> a) {
   __shared__ cpx<T> xbuf[4][kXBuf];
   __shared__ cpx<T> tws[3][512];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform: as a scalar, every line address is a scalar
+  // base plus a 32-bit lane offset (no 64-bit vector address arithmetic)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cpx<T>* X = xbuf[wv];
   wave512_twiddles<T, 256>(tws, a.tw);
   __syncthreads();

@@ -731,13 +731,18 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void xpass_wave512(XArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void xpass_wave512(XArgs<T> a) {
   __shared__ cpx<T> xbuf[4][kXBuf];
   // per-lane twiddle sets, [j][lane]: exp(+2 pi i lane j / 512), exp(-2 pi i lo j / 64),
   // exp(-2 pi i (lo + 8 j) hi / 512) with lo = lane & 7, hi = lane >> 3
   __shared__ cpx<T> tws[3][512];
   __shared__ double red[5 * 4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // Gz of the first line of a pair waits here (lane-private slots) while the
+  // second line is transformed: registers are what limits the waves per SIMD
+  __shared__ T gzs[4][8][64];
+  // the wave index is uniform: as a scalar, every line address is a scalar
+  // base plus a 32-bit lane offset (no 64-bit vector address arithmetic)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cpx<T>* X = xbuf[wv];
   constexpr int K = 170;
   wave512_twiddles<T, 256>(tws, a.tw);
@@ -752,14 +757,19 @@ __global__ __launch_bounds__(256) void xpass_wave512(XArgs<T> a) {
   if (pr0 < npairs) load512_sig<T>(a, 2 * pr0, 0, lane, pf);
 #pragma unroll 1
   for (int pr = pr0; pr < npairs; pr += gridDim.x * 4) {
-    T gza[8], gzb[8];
     const int nxt = (pr + gridDim.x * 4 < npairs) ? 2 * (pr + gridDim.x * 4) : -1;
     const int ln = opaque(lane);
-    wave512_line<T>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM);
+    {
+      T gza[8];
+      wave512_line<T>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) gzs[wv][j][lane] = gza[j];
+    }
+    T gzb[8];
     wave512_line<T>(a, 2 * pr + 1, nxt, opaque(lane), X, tIB, tC, tFB, pf, gzb, aF0, aF1, aF2, aE, aM);
     cpx<T> g[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) g[j] = mk<T>(gza[j], gzb[j]);
+    for (int j = 0; j < 8; ++j) g[j] = mk<T>(gzs[wv][j][lane], gzb[j]);
     const int l3 = opaque(lane);
     fwd512<T>(g, X, l3, tC, tFB);
     unpack_store512<T>(g, l3, K, a.spec + 2 * a.sfs + (long long)(2 * pr) * a.ld,

@@ -92,37 +92,51 @@ __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, 
     if (k <= K) {
       const cpx<T> zc = conj(p);
       const cpx<T> d = g[r] - zc;
-      st_stream(dx + k, scl(g[r] + zc, (T)0.5));
-      st_stream(dy + k, mk<T>((T)0.5 * d.im, (T)-0.5 * d.re));
+      st_stream(at_u32(dx, k), scl(g[r] + zc, (T)0.5));
+      st_stream(at_u32(dy, k), mk<T>((T)0.5 * d.im, (T)-0.5 * d.re));
     }
   }
 }
 
 // Raw spectral values a lane needs for one packed signal of one line: A, B at
-// k = lane + 64 r (r = 0, 1, 2) and at the Hermitian partners n - k of
-// k = lane + 64 r (r = 5, 6, 7); slots outside the 2/3 band are zeroed by pack512.
+// k = lane + 64 r (r = 0, 1, 2).  The Hermitian partners n - k of
+// k = lane + 64 r (r = 5, 6, 7) are the same values held by lane 64 - lane
+// (r = 2, 1, 0) and are fetched across lanes by pack512; slots outside the
+// 2/3 band are zeroed there.
 template <typename T>
 struct Raw512 {
-  cpx<T> a[6], b[6];
+  cpx<T> a[3], b[3];
 };
+
+// base[i] through a 32-bit unsigned byte offset: with a wave-uniform base the
+// address is a scalar base plus a vector offset (no 64-bit vector arithmetic)
+template <typename T>
+__device__ __forceinline__ const cpx<T>* at_u32(const cpx<T>* base, int i) {
+  return reinterpret_cast<const cpx<T>*>(reinterpret_cast<const char*>(base) + (unsigned)i * (unsigned)sizeof(cpx<T>));
+}
+template <typename T>
+__device__ __forceinline__ cpx<T>* at_u32(cpx<T>* base, int i) {
+  return reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(base) + (unsigned)i * (unsigned)sizeof(cpx<T>));
+}
 
 // The loads are unconditional (slots outside the band read index 0): a load
 // under a branch leaves the number of loads in flight unknown to the compiler,
 // which then waits for all of them, including a prefetch, at the next use.
 template <typename T>
 __device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int lane, Raw512<T>& w) {
-  constexpr int n = 512, K = 170;
+  constexpr int K = 170;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int k = lane + 64 * q;  // direct slots r = q
     const int kc = k <= K ? k : 0;
-    w.a[q] = ld_xin(A + kc);
-    w.b[q] = ld_xin(B + kc);
-    const int kp = lane + 64 * (5 + q);  // partner slots r = 5 + q
-    const int kpc = kp >= n - K ? n - kp : 0;
-    w.a[3 + q] = ld_xin(A + kpc);
-    w.b[3 + q] = ld_xin(B + kpc);
+    w.a[q] = ld_xin(at_u32(A, kc));
+    w.b[q] = ld_xin(at_u32(B, kc));
   }
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src) {
+  return mk<T>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 
 // Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout v[r] = Z[lane + 64 r].
@@ -133,7 +147,15 @@ __device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v
   for (int q = 0; q < 3; ++q) {
     const bool ok = lane + 64 * q <= K, okp = lane + 64 * (5 + q) >= n - K;
     v[q] = ok ? mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re) : mk<T>(0, 0);
-    v[5 + q] = okp ? mk<T>(w.a[3 + q].re + w.b[3 + q].im, w.b[3 + q].re - w.a[3 + q].im) : mk<T>(0, 0);
+    // A[n - k], k = lane + 64 (5 + q): slot 2 - q of lane 64 - lane; lane 0
+    // holds it itself in slot 3 - q (for q = 0 that slot is outside the band)
+    const int src = (64 - lane) & 63;
+    cpx<T> pa = shfl_cpx(w.a[2 - q], src), pb = shfl_cpx(w.b[2 - q], src);
+    if (q > 0 && lane == 0) {
+      pa = w.a[3 - q];
+      pb = w.b[3 - q];
+    }
+    v[5 + q] = okp ? mk<T>(pa.re + pb.im, pb.re - pa.im) : mk<T>(0, 0);
   }
   if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
   v[3] = mk<T>(0, 0);
