@@ -45,12 +45,15 @@ def algorithmic_bytes(n, wsize, cells):
     compact = nb * nb * kx1 * c
     zslab = n * nb * kx1 * c       # [z][iy][ix]
     yslab = n * n * kx1 * c        # [z][y][ix]
+    # After the first step the z inverse of the next step (5 z-slab fields written)
+    # runs inside the z-forward/update pass, from the new velocity in registers;
+    # "z_inverse_curl" is the stand-alone pass of a first step.
     return {
         "z_inverse_curl": 3 * compact + 5 * zslab,
         "y_inverse": 5 * zslab + 6 * yslab,
         "x_fused": 9 * yslab + 4 * cells * wsize,
         "y_forward": 3 * yslab + 3 * zslab,
-        "z_forward_update": 3 * zslab + 12 * compact,
+        "z_forward_update": 3 * zslab + 12 * compact + 5 * zslab,
     }
 
 
@@ -64,6 +67,14 @@ def step_model_bytes(n, wsize):
     yslab = n * n * kx1 * c
     return (3 * compact + 5 * zslab) + (5 * zslab + 6 * yslab) + 9 * yslab + (3 * yslab + 3 * zslab) \
         + (3 * zslab + 12 * compact)
+
+
+def design_step_bytes(n, wsize):
+    """Bytes a step of this design moves: the pass model without P1's reads of the
+    three compact components (the fused update pass has them in registers)."""
+    K = (n - 1) // 3
+    kx1, nb = K + 1, 2 * K + 1
+    return step_model_bytes(n, wsize) - 3 * nb * nb * kx1 * 2 * wsize
 
 
 def kernel_source_hash():
@@ -308,8 +319,12 @@ def main():
             "launch_ms": round(pass32[dominant], 4),
         },
         "step_roofline": {
+            # model_bytes: one HBM round trip per axis pass (frac: the equivalent
+            # rate); design_bytes: what this implementation moves per step
             "model_bytes": model,
             "frac": round(model / ms32 / 1e9 / HBM_PEAK_GBS, 4),
+            "design_bytes": design_step_bytes(n, 4),
+            "design_frac": round(design_step_bytes(n, 4) / ms32 / 1e9 / HBM_PEAK_GBS, 4),
             "pass_ms": {k: round(v, 4) for k, v in pass32.items()},
         },
         "fp64": None if ms64 is None else {

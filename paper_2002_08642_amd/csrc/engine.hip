@@ -201,6 +201,7 @@ class Engine : public EngineBase {
     memset(h.data(), 0, sizeof(cpx<T>) * 3 * clen);
     for (int q = 0; q < 3; ++q) pad(in + 2 * q * clen_ext, h.data() + q * clen);
     FSI_HIP(hipMemcpyAsync(uh, h.data(), sizeof(cpx<T>) * 3 * clen, hipMemcpyHostToDevice, s));
+    zs_valid = false;
     FSI_TRY(run_inverse(uh, clen, 3, phys));
     return finish_set_velocity();
   }
@@ -611,8 +612,10 @@ class Engine : public EngineBase {
     if (ev) FSI_HIP(hipEventRecord(ev[0], s));
     if (wing_nt > 0 && bcells > 0) FSI_TRY(run_mask());
     if (ev) FSI_HIP(hipEventRecord(ev[1], s));
-    // P1: z inverse of u and of omega_x, omega_y (omega = i k x u)
-    {
+    // P1: z inverse of u and of omega_x, omega_y (omega = i k x u); the
+    // previous step's last pass has already produced it unless u_hat has been
+    // replaced or A used since
+    if (!zs_valid) {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = uh;
       a.in_fs = clen;
@@ -620,6 +623,7 @@ class Engine : public EngineBase {
       a.out_fs = Alen;
       FSI_HIP(launch_col<T>(COL_INV_CURL5, a, 1, s));  // u, omega_x, omega_y
     }
+    zs_valid = false;
     if (ev) FSI_HIP(hipEventRecord(ev[2], s));
     // P2: y inverse of the five fields, omega_z = i (kx uy - ky ux) formed on the way
     {
@@ -708,7 +712,12 @@ class Engine : public EngineBase {
       a.nu = (T)d.nu;
       a.scale = (T)(1.0 / (double)npts);
       a.pi = d.fsi_pressure ? pi_ : nullptr;
-      FSI_HIP(launch_col<T>(COL_FWD_UPDATE, a, 1, s));
+      // and P1 of the next step on the same columns (in place: each workgroup
+      // has read all rows of its columns of A before it writes them)
+      a.zout = A;
+      a.zout_fs = Alen;
+      FSI_HIP(launch_col<T>(COL_FWD_UPDATE_Z, a, 1, s));
+      zs_valid = true;
     }
     if (ev) FSI_HIP(hipEventRecord(ev[7], s));
     FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
@@ -793,6 +802,7 @@ class Engine : public EngineBase {
       return FSI_ESTATE;
     }
     FSI_HIP(hipMemcpyAsync(uh, sl.uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    zs_valid = false;
     FSI_HIP(hipMemcpyAsync(nh, sl.nh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
     FSI_HIP(hipMemcpyAsync(sc, sl.sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
     FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
@@ -1274,20 +1284,29 @@ class Engine : public EngineBase {
     return a;
   }
 
+  // z-slab work fields of the helper transforms: a single field uses the sixth
+  // field of A, which leaves the z inverse kept for the next step (fields 0-4) intact
+  cpx<T>* zwork(int nf) {
+    if (nf == 1) return A + 5 * Alen;
+    zs_valid = false;
+    return A;
+  }
+
   // compact (nf fields, stride cstride) -> physical (nf fields)
   fsi_status run_inverse(const cpx<T>* comp, long long cstride, int nf, T* out) {
+    cpx<T>* Aw = zwork(nf);
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = comp;
       a.in_fs = cstride;
-      a.out = A;
+      a.out = Aw;
       a.out_fs = Alen;
       a.nf = nf;
       FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
     }
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
-      a.in = A;
+      a.in = Aw;
       a.in_fs = Alen;
       a.in_bs = C1;
       a.out = B;
@@ -1310,6 +1329,7 @@ class Engine : public EngineBase {
   // physical (nf fields) -> compact; mode COL_FWD_PLAIN (nf = 1, into cout) or
   // COL_FWD_PROJECT (nf = 3, into cout = uh)
   fsi_status run_forward(T* in, int nf, cpx<T>* cout, int zmode) {
+    cpx<T>* Aw = zwork(nf);
     {
       XArgs<T> a = x_base();
       a.spec = B;
@@ -1323,7 +1343,7 @@ class Engine : public EngineBase {
       a.in = B;
       a.in_fs = Blen;
       a.in_bs = (long long)ny * kxp;
-      a.out = A;
+      a.out = Aw;
       a.out_fs = Alen;
       a.out_bs = C1;
       a.nf = nf;
@@ -1331,7 +1351,7 @@ class Engine : public EngineBase {
     }
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
-      a.in = A;
+      a.in = Aw;
       a.in_fs = Alen;
       a.out = cout;
       a.out_fs = clen;
@@ -1409,6 +1429,7 @@ class Engine : public EngineBase {
   int ngroups = 0, npart = 0, nfused = 0;
   cpx<T>*twx = nullptr, *twy = nullptr, *twz = nullptr;
   cpx<T>*uh = nullptr, *nh = nullptr, *A = nullptr, *B = nullptr, *cwork = nullptr;
+  bool zs_valid = false;  // A[0..4] holds the z inverse (P1) of the current u_hat
   T* phys = nullptr;
   double* partials = nullptr;
   DevScalars* sc = nullptr;

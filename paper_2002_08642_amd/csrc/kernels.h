@@ -27,7 +27,8 @@ enum ColMode {
   COL_FWD_ACC = 5,       // adjoint: out[f] += m_k * forward(in[f])   (m_k = 1 at kx = 0, else 2)
   COL_FWD_ACC_CURL = 6,  // adjoint: out += m_k * (i k x forward(in[0..2]))
   COL_INV_CURL5 = 7,     // z inverse of u and of omega_x, omega_y (5 outputs)
-  COL_INV_WZ = 8         // y inverse of 5 fields plus omega_z = i (kx uy - ky ux) (6 outputs)
+  COL_INV_WZ = 8,        // y inverse of 5 fields plus omega_z = i (kx uy - ky ux) (6 outputs)
+  COL_FWD_UPDATE_Z = 9   // COL_FWD_UPDATE, then COL_INV_CURL5 of the new velocity into zout
 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 
@@ -67,6 +68,8 @@ struct ColArgs {
   int first;  // 1: integrating-factor Euler step
   T nu;
   cpx<T>* pi;  // update pass: total pressure Pi_hat = -i k.N'/|k|^2 (compact), NULL = not kept
+  cpx<T>* zout;       // COL_FWD_UPDATE_Z: the five z-inverse fields of the new velocity
+  long long zout_fs;  // their field stride (row pitch ld, as the input)
 };
 
 template <typename T>

@@ -31,6 +31,14 @@ namespace fsi {
 // into registers before they are written to LDS, so that each thread keeps
 // all of its row loads in flight at once.
 
+// a s - b t with both products rounded (no fused multiply-add): the stand-alone
+// z-inverse pass and the one fused into the update pass then form the same bits
+template <typename T>
+__device__ __forceinline__ cpx<T> scaled_diff(cpx<T> a, T s, cpx<T> b, T t) {
+#pragma clang fp contract(off)
+  return mk<T>(a.re * s - b.re * t, a.im * s - b.im * t);
+}
+
 template <typename T, int W, int NT, int MAXE, int MODE, int N>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void col_pass(ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -201,8 +209,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             // per-row wavenumber: kz in the z pass, ky in the y pass
             const T krow = (Z5 ? a.kfz : a.kfy) * (T)band_mode(i, K);
             cpx<T> t;
-            if constexpr (Z5 && o == 1) t = scl(RA[k], krow) - scl(RB[k], kx);  // wy: kz ux - kx uz
-            else if constexpr (Z5) t = scl(RB[k], ky) - scl(RA[k], krow);       // wx: ky uz - kz uy
+            if constexpr (Z5 && o == 1) t = scaled_diff(RA[k], krow, RB[k], kx);  // wy: kz ux - kx uz
+            else if constexpr (Z5) t = scaled_diff(RB[k], ky, RA[k], krow);       // wx: ky uz - kz uy
             else t = scl(RB[k], kx) - scl(RA[k], krow);                          // wz: kx uy - ky ux
             val = mk<T>(-t.im, t.re);  // i t
           }
@@ -378,12 +386,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
       }
     }
-    if constexpr (MODE == COL_FWD_PROJECT || MODE == COL_FWD_UPDATE) {
+    constexpr bool UPD = (MODE == COL_FWD_UPDATE || MODE == COL_FWD_UPDATE_Z);
+    if constexpr (MODE == COL_FWD_PROJECT || UPD) {
+      // COL_FWD_UPDATE_Z keeps the new velocity of the thread's rows for the
+      // z inverse of the next step
+      cpx<T> U[3][MAXO];
       const int ix = c % a.kxp, iy = c / a.kxp;
       const T kx = a.kfx * (T)ix;
       const T ky = a.kfy * (T)band_mode(iy, a.Ky);
       T dtn = 0, dtp = 0, c1 = 0, c2 = 0;
-      if constexpr (MODE == COL_FWD_UPDATE) {
+      if constexpr (UPD) {
         const double d_n = a.sc->dt[a.cur];
         const double d_p = a.sc->dt[a.cur ^ 1];
         dtn = (T)d_n;
@@ -405,7 +417,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
       for (int k0 = 0; k0 < MAXO; k0 += KC) {
         cpx<T> uo[KC][3], po[KC][3];
-        if constexpr (MODE == COL_FWD_UPDATE) {
+        if constexpr (UPD) {
 #pragma unroll
           for (int kk = 0; kk < KC; ++kk) {
             const int k = k0 + kk;
@@ -437,10 +449,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
               n0 = n0 - scl(sp, kx);
               n1 = n1 - scl(sp, ky);
               n2 = n2 - scl(sp, kz);
-              if constexpr (MODE == COL_FWD_UPDATE) {
+              if constexpr (UPD) {
                 if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
               }
-            } else if constexpr (MODE == COL_FWD_UPDATE) {
+            } else if constexpr (UPD) {
               if (a.pi) a.pi[idx] = mk<T>(0, 0);
             }
             if constexpr (MODE == COL_FWD_PROJECT) {
@@ -458,10 +470,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
                 const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
                 st_stream(a.uh + q * a.cfs + idx, u2);
                 st_stream(a.nh + q * a.cfs + idx, nn[q]);
+                if constexpr (MODE == COL_FWD_UPDATE_Z) U[q][k] = u2;
               }
             }
           }
         }
+      }
+      if constexpr (MODE == COL_FWD_UPDATE_Z) {
+        // The first pass of the next step on the same columns: z inverse of
+        // u^{n+1} and of omega_x, omega_y = (i k x u)_x,y, in the order of
+        // COL_INV_CURL5 (ux, wy, uz, wx, uy), from registers instead of memory.
+        __syncthreads();
+        auto zstep = [&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          constexpr int fo = (o == 1) ? 4 : (o == 4) ? 1 : o;
+          const int tid = opaque((int)threadIdx.x);
+          const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+          const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+#pragma unroll
+          for (int k = 0; k < MAXE; ++k) {
+            const int r = r0 + k * RSTEP;
+            if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+          }
+#pragma unroll
+          for (int k = 0; k < MAXO; ++k) {
+            const int i = r0 + k * RSTEP;
+            if (i < nb) {
+              cpx<T> val;
+              if constexpr (o == 0) val = U[0][k];
+              else if constexpr (o == 2) val = U[2][k];
+              else if constexpr (o == 4) val = U[1][k];
+              else {
+                const T kz = a.kfz * (T)band_mode(i, K);
+                // wy = i (kz ux - kx uz), wx = i (ky uz - kz uy)
+                const cpx<T> t = (o == 1) ? scaled_diff(U[0][k], kz, U[2][k], kx) : scaled_diff(U[2][k], ky, U[1][k], kz);
+                val = mk<T>(-t.im, t.re);
+              }
+              buf[band_to_row(i, K, n) * W + col] = cok ? val : mk<T>(0, 0);
+            }
+          }
+          __syncthreads();
+          col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+          cpx<T>* out = a.zout + fo * a.zout_fs;
+          cpx<T> ov[MAXE];  // LDS reads first, then the stores
+#pragma unroll
+          for (int k = 0; k < MAXE; ++k) {
+            const int r = r0 + k * RSTEP;
+            ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+          }
+          if (cok) {
+#pragma unroll
+            for (int k = 0; k < MAXE; ++k) {
+              const int r = r0 + k * RSTEP;
+              if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
+            }
+          }
+          __syncthreads();
+        };
+        zstep(std::integral_constant<int, 0>{});
+        zstep(std::integral_constant<int, 1>{});
+        zstep(std::integral_constant<int, 2>{});
+        zstep(std::integral_constant<int, 3>{});
+        zstep(std::integral_constant<int, 4>{});
       }
     }
   }
@@ -1117,6 +1187,7 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
     FSI_COL_CASE(COL_FWD_PLAIN)
     FSI_COL_CASE(COL_FWD_PROJECT)
     FSI_COL_CASE(COL_FWD_UPDATE)
+    FSI_COL_CASE(COL_FWD_UPDATE_Z)
     FSI_COL_CASE(COL_FWD_ACC)
     FSI_COL_CASE(COL_FWD_ACC_CURL)
     default: return hipErrorInvalidValue;
