@@ -31,6 +31,15 @@ namespace fsi {
 // into registers before they are written to LDS, so that each thread keeps
 // all of its row loads in flight at once.
 
+// f(integral_constant<int, I>) for I = B .. E - 1, in order
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // a s - b t with both products rounded (no fused multiply-add): the stand-alone
 // z-inverse pass and the one fused into the update pass then form the same bits
 template <typename T>
@@ -72,6 +81,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     // component loaded for output o (-1: none) and whether it goes to RB; the load
     // for output o + 1 is issued right after output o has been written to LDS, so
     // it is in flight while output o is transformed.
+    // unconditional loads (clamped rows and columns), zeroed when written to LDS
+    auto load_into = [&](int lq, cpx<T>(&R)[MAXO]) __attribute__((always_inline)) {
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + tq % W, rq = tq / W;
+      const cpx<T>* in = a.in + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = rq + k * RSTEP;
+        R[k] = ld_stream(in + (long long)(i < nb ? i : 0) * a.ld);
+      }
+    };
     auto load_for = [&](int o) {
       int lq = o, into_b = 0;
       if (CURLM) {
@@ -94,26 +114,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         else RA[k] = val;
       }
     };
-    load_for(0);
-    for (int o = 0; o < nout; ++o) {
+    // one output: LDS fill (with the curl combination), the next output's load,
+    // the transform, the stores.  With a compile-time o (the static sequences
+    // below) no prefetched register set is merged across branches.
+    auto ostep = [&](auto oc, auto nc) __attribute__((always_inline)) {
+      constexpr int o = decltype(oc)::value, NO = decltype(nc)::value;
+      constexpr int fo = CURLM ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
+      // source: 0 = A, 1 = B, 2 = curl combination of A and B
+      constexpr int src = CURLM ? ((o & 1) ? 2 : (o == 2) ? 1 : 0) : (o & 1);
+      // the load issued after this output is in LDS: field and set
+      constexpr int nlq = CURLM ? ((o == 0) ? 2 : (o == 2) ? 1 : (o == 4) ? 0 : -1) : (o + 1 < NO ? o + 1 : -1);
+      constexpr bool nb_set = CURLM ? (o == 0 || o == 4) : ((o + 1) & 1);
       const int tid = opaque((int)threadIdx.x);
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
-      // output field and combination: o = 0 ux = A; 1 wy = i(kz A - kx B); 2 uz = B;
-      // 3 wx = i(ky B - kz A); 4 uy = A; 5 wz = i(kx A - ky B)
-      const int fo = CURLM ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
-      T ka = 0, kb = 0;
-      bool kza = false, kzb = false, cross = false;
-      if (CURLM && (o & 1)) {
-        const int ix = c % a.kxp, iy = c / a.kxp;
-        const T kx = a.kfx * (T)ix;
-        const T ky = a.kfy * (T)band_mode(iy, a.Ky);
-        cross = true;
-        if (o == 1) { kza = true; kb = kx; }
-        else if (o == 3) { kb = ky; kza = true; }
-        else { ka = kx; kb = ky; }
-      }
-      const bool useb = CURLM && (o == 2 || o == 3);
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = a.kfy * (T)band_mode(iy, a.Ky);
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
@@ -123,24 +140,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       for (int k = 0; k < MAXO; ++k) {
         const int i = r0 + k * RSTEP;
         if (i < nb) {
-          cpx<T> val = useb ? RB[k] : RA[k];
-          if (cross) {
+          cpx<T> val = (src == 1) ? RB[k] : RA[k];
+          if constexpr (src == 2) {
             const T kz = a.kfz * (T)band_mode(i, K);
-            // o = 1: kz A - kx B; o = 3: ky B - kz A = -(kz A - ky B); o = 5: kx A - ky B
-            cpx<T> t = scl(RA[k], kza ? kz : ka) - scl(RB[k], kb);
-            if (o == 3) t = mk<T>(-t.re, -t.im);
+            cpx<T> t;
+            if constexpr (o == 1) t = scaled_diff(RA[k], kz, RB[k], kx);       // wy: kz ux - kx uz
+            else if constexpr (o == 3) t = scaled_diff(RB[k], ky, RA[k], kz);  // wx: ky uz - kz uy
+            else t = scaled_diff(RA[k], kx, RB[k], ky);                        // wz: kx uy - ky ux
             val = mk<T>(-t.im, t.re);  // i t
           }
           buf[band_to_row(i, K, n) * W + col] = cok ? val : mk<T>(0, 0);
         }
       }
       __syncthreads();
-      if (o + 1 < nout) load_for(o + 1);
+      if constexpr (nlq >= 0) {
+        if constexpr (nb_set) {
+          asm volatile("" ::: "memory");  // keeps the two load sites apart
+          load_into(nlq, RB);
+        } else {
+          load_into(nlq, RA);
+        }
+      }
       col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
       cpx<T>* out = a.out + fo * a.out_fs + ob;
-      // every LDS read first, then the stores: reading each value just before
-      // its store would put an LDS round trip in front of every store
-      cpx<T> ov[MAXE];
+      cpx<T> ov[MAXE];  // LDS reads first, then the stores
 #pragma unroll
       for (int k = 0; k < MAXE; ++k) {
         const int r = r0 + k * RSTEP;
@@ -154,6 +177,86 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
       }
       __syncthreads();
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I3 = std::integral_constant<int, 3>;
+    using I6 = std::integral_constant<int, 6>;
+    using I9 = std::integral_constant<int, 9>;
+    // run-time output loop (other lengths and field counts)
+    auto generic = [&]() {
+      load_for(0);
+      for (int o = 0; o < nout; ++o) {
+        const int tid = opaque((int)threadIdx.x);
+        const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+        const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+        // output field and combination: o = 0 ux = A; 1 wy = i(kz A - kx B); 2 uz = B;
+        // 3 wx = i(ky B - kz A); 4 uy = A; 5 wz = i(kx A - ky B)
+        const int fo = CURLM ? ((o == 1) ? 4 : (o == 4) ? 1 : o) : o;
+        T ka = 0, kb = 0;
+        bool kza = false, kzb = false, cross = false;
+        if (CURLM && (o & 1)) {
+          const int ix = c % a.kxp, iy = c / a.kxp;
+          const T kx = a.kfx * (T)ix;
+          const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+          cross = true;
+          if (o == 1) { kza = true; kb = kx; }
+          else if (o == 3) { kb = ky; kza = true; }
+          else { ka = kx; kb = ky; }
+        }
+        const bool useb = CURLM && (o == 2 || o == 3);
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < MAXO; ++k) {
+          const int i = r0 + k * RSTEP;
+          if (i < nb) {
+            cpx<T> val = useb ? RB[k] : RA[k];
+            if (cross) {
+              const T kz = a.kfz * (T)band_mode(i, K);
+              // o = 1: kz A - kx B; o = 3: ky B - kz A = -(kz A - ky B); o = 5: kx A - ky B
+              cpx<T> t = scl(RA[k], kza ? kz : ka) - scl(RB[k], kb);
+              if (o == 3) t = mk<T>(-t.re, -t.im);
+              val = mk<T>(-t.im, t.re);  // i t
+            }
+            buf[band_to_row(i, K, n) * W + col] = cok ? val : mk<T>(0, 0);
+          }
+        }
+        __syncthreads();
+        if (o + 1 < nout) load_for(o + 1);
+        col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+        cpx<T>* out = a.out + fo * a.out_fs + ob;
+        // every LDS read first, then the stores: reading each value just before
+        // its store would put an LDS round trip in front of every store
+        cpx<T> ov[MAXE];
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+        }
+        if (cok) {
+#pragma unroll
+          for (int k = 0; k < MAXE; ++k) {
+            const int r = r0 + k * RSTEP;
+            if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
+          }
+        }
+        __syncthreads();
+      }
+    };
+    if constexpr (N == 512 && CURLM) {
+      load_into(0, RA);
+      static_for<0, 6>([&](auto oc) { ostep(oc, I6{}); });
+    } else if constexpr (N == 512) {
+      if (nout == 1 || nout == 3 || nout == 9) load_into(0, RA);
+      if (nout == 1) static_for<0, 1>([&](auto oc) { ostep(oc, I1{}); });
+      else if (nout == 3) static_for<0, 3>([&](auto oc) { ostep(oc, I3{}); });
+      else if (nout == 9) static_for<0, 9>([&](auto oc) { ostep(oc, I9{}); });
+      else generic();
+    } else {
+      generic();
     }
   } else if constexpr (MODE == COL_INV_CURL5 || MODE == COL_INV_WZ) {
     // Stored fields of the forward step.  omega_z = i (kx uy - ky ux) needs no z
