@@ -147,7 +147,10 @@ fsi_status fsi_step_adaptive(fsi_ctx* ctx, double cfl, double c_eta, double dt_m
  * F = force on the body (1/eta) * integral of chi (u - u_s) dV, dt used,
  * E = kinetic energy (1/2) integral |u|^2 dV, umax = max |u|_2 over the grid
  * points, t = time after the step, nstep = steps since fsi_set_velocity.
- * Any pointer may be NULL. Synchronizes; FSI_ENAN if a non-finite value was met. */
+ * Any pointer may be NULL. Waits until these values of the last step are on the
+ * host (after a step, the step's last passes may still run on the stream; every
+ * call that reads or replaces device state orders itself after them);
+ * FSI_ENAN if a non-finite value was met. */
 fsi_status fsi_get_step_info(fsi_ctx* ctx, double F[3], double* dt_used, double* E,
                              double* umax, double* t, int64_t* nstep);
 

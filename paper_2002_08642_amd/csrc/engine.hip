@@ -683,6 +683,12 @@ class Engine : public EngineBase {
       f.inv_eta = 1.0 / d.eta;
       FSI_HIP(launch_finalize(f, s));
     }
+    // the diagnostics and dt_n are final here: the read-back does not wait for
+    // the last two passes, so the caller can prepare the next step meanwhile
+    FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    if (!info_ev) FSI_HIP(hipEventCreateWithFlags(&info_ev, hipEventDisableTiming));
+    FSI_HIP(hipEventRecord(info_ev, s));
+    info_pending = true;
     if (ev) FSI_HIP(hipEventRecord(ev[5], s));
     // P4: y forward of G, truncated to the y band
     {
@@ -720,7 +726,6 @@ class Engine : public EngineBase {
       zs_valid = true;
     }
     if (ev) FSI_HIP(hipEventRecord(ev[7], s));
-    FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     ++nstep;
     have_prev = true;
     p_ready = d.fsi_pressure && wing_nt > 0 && bcells > 0;
@@ -728,7 +733,8 @@ class Engine : public EngineBase {
   }
 
   fsi_status step_info(double F[3], double* dt, double* E, double* umax, double* t, long long* ns) override {
-    FSI_HIP(hipStreamSynchronize(s));
+    if (info_pending) FSI_HIP(hipEventSynchronize(info_ev));
+    else FSI_HIP(hipStreamSynchronize(s));
     if (F) {
       F[0] = sc_host->info[0];
       F[1] = sc_host->info[1];
@@ -806,6 +812,7 @@ class Engine : public EngineBase {
     FSI_HIP(hipMemcpyAsync(nh, sl.nh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
     FSI_HIP(hipMemcpyAsync(sc, sl.sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
     FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    info_pending = false;
     nstep = sl.nstep;
     have_prev = sl.have_prev;
     p_ready = false;
@@ -1168,6 +1175,8 @@ class Engine : public EngineBase {
     stage = nullptr;
     if (stage_ev) (void)hipEventDestroy(stage_ev);
     stage_ev = nullptr;
+    if (info_ev) (void)hipEventDestroy(info_ev);
+    info_ev = nullptr;
     for (auto& e : events)
       for (hipEvent_t h : e) (void)hipEventDestroy(h);
     events.clear();
@@ -1187,6 +1196,9 @@ class Engine : public EngineBase {
   }
 
   fsi_status reset_scalars() {
+    // a step's read-back into sc_host may still be in flight
+    FSI_HIP(hipStreamSynchronize(s));
+    info_pending = false;
     DevScalars z;
     memset(&z, 0, sizeof(z));
     *sc_host = z;
@@ -1441,6 +1453,8 @@ class Engine : public EngineBase {
   void* stage = nullptr;
   size_t stage_cap = 0;
   hipEvent_t stage_ev = nullptr;
+  hipEvent_t info_ev = nullptr;  // recorded after the step's read-back of the device scalars
+  bool info_pending = false;
   bool stage_pending = false;
   int bx0 = 0, by0 = 0, bz0 = 0, bnx = 0, bny = 0, bnz = 0;
   long long bcells = 0, box_cap = 0;
