@@ -4,7 +4,8 @@ Sec. 4.1 (penalized NS equations): the code advances
     du/dt = u x omega - grad(Pi) + nu lap(u) - (chi/C_eta)(u - u_s),  div u = 0,
 with Pi = p + |u|^2/2, a Fourier pseudo-spectral discretization, adaptive
 time stepping and an Adams-Bashforth scheme (Sec. 4.1, last paragraph).  The
-sponge term is not part of this step (no sponge in these workloads).
+vorticity sponge term of the same equation is optional (set_sponge; off by
+default, as in the paper's workloads): oracle.sponge.
 
 Algorithm of one step n (state: u_hat^n, N_hat^{n-1}, dt_{n-1}, t^n):
  1. u = IDFT(u_hat), omega = IDFT(i k x u_hat);
@@ -14,7 +15,8 @@ Algorithm of one step n (state: u_hat^n, N_hat^{n-1}, dt_{n-1}, t^n):
     u_max = max |u|_2, E = dV/2 sum |u|^2;
  5. dt_n given, or adaptive: min(CFL dx_min / u_max, C_eta eta, dt_max),
     the CFL term being +inf when u_max = 0;
- 6. N_hat' = D DFT(G) (2/3 band), N_hat = P N_hat' (Leray projection);
+ 6. N_hat' = D (DFT(G) + T_hat) (2/3 band; T_hat the sponge term, if set),
+    N_hat = P N_hat' (Leray projection);
  6b. the total pressure of the step, Pi_hat = -i k.N_hat' / |k|^2, and
     p = Pi - |u|^2/2 are kept for the wing loads (oracle.pressure);
  7. integrating-factor AB2 with variable step (IF-Euler at n = 0):
@@ -35,7 +37,7 @@ static mask equals (dV/eta) U sum chi; adaptive dt matches its closed form.
 
 import numpy as np
 
-from . import dft, spectral, pressure, mask as mask_mod
+from . import dft, spectral, pressure, mask as mask_mod, sponge as sponge_mod
 
 
 class OracleNS:
@@ -58,6 +60,11 @@ class OracleNS:
         self.nstep = 0
         self.wing = None
         self.p_last = None  # p = Pi - |u|^2/2 of the last step (oracle.pressure)
+        self.sponge = None  # (chi_sp, C_sp)
+
+    def set_sponge(self, c_sp, gx=None, gy=None, gz=None):
+        """Vorticity sponge with chi_sp = max(gx[x], gy[y], gz[z]); c_sp <= 0 removes it."""
+        self.sponge = None if c_sp <= 0 else (sponge_mod.sponge_mask(self.n, gx, gy, gz), float(c_sp))
 
     # -- state ---------------------------------------------------------------
     def set_velocity(self, u):
@@ -108,7 +115,10 @@ class OracleNS:
             "E": 0.5 * self.dV * float(np.sum(speed2)),
             "umax": float(np.sqrt(np.max(speed2))),
         }
-        nh = spectral.dealias(dft.forward(g), self.n)
+        gh = dft.forward(g)
+        if self.sponge is not None:
+            gh = gh + sponge_mod.sponge_term_hat(self.uh, self.sponge[0], self.sponge[1], self.n, self.L)
+        nh = spectral.dealias(gh, self.n)
         # pressure of this step (FSI coupling): Pi from the unprojected term
         self.p_last = pressure.pressure_field(pressure.total_pressure_hat(nh, self.n, self.L), u)
         nh = spectral.project(nh, self.n, self.L)
