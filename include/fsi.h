@@ -116,6 +116,21 @@ fsi_status fsi_set_velocity_device(fsi_ctx* ctx, const void* u_dev, int32_t dtyp
  * like fsi_set_velocity. Synchronizes. */
 fsi_status fsi_set_spectrum(fsi_ctx* ctx, const double* uhat_host);
 
+/* Vorticity sponge (Sec. 4.1, the sponge term of the penalized equations: a
+ * vorticity damping against the periodicity of the Fourier discretization).
+ * Readings: the term added to du/dt is T = -(1/C_sp) curl((-lap)^-1 (chi_sp
+ * omega)), i.e. T_hat = -(1/C_sp) i k x S_hat / |k|^2 with S = chi_sp omega and
+ * T_hat(0) = 0 (the sign that damps: chi_sp = 1 gives T = -u/C_sp); the sponge
+ * mask is chi_sp(x, y, z) = max(gx[ix], gy[iy], gz[iz]) from per-axis profiles
+ * on the grid points (gx: nx values, gy: ny, gz: nz, each >= 0; NULL = 0).
+ * T enters the nonlinear term before the 2/3 truncation and the projection.
+ * c_sp <= 0 (or all profiles NULL) switches the sponge off (the default).
+ * Copied; FSI_EINVAL for a non-finite c_sp or a negative or non-finite
+ * profile value.  While it is on, fsi_step_adjoint returns FSI_ESTATE (the
+ * adjoint does not include the sponge). */
+fsi_status fsi_set_sponge(fsi_ctx* ctx, double c_sp, const double* gx, const double* gy,
+                          const double* gz);
+
 /* Physical velocity u[3][nz][ny][nx] of the current state. Synchronizes. */
 fsi_status fsi_get_velocity(fsi_ctx* ctx, double* u_host);
 

@@ -119,6 +119,11 @@ fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double*
   return ctx->eng->set_wing(nv, x, v, nt, tri);
 }
 
+fsi_status fsi_set_sponge(fsi_ctx* ctx, double c_sp, const double* gx, const double* gy, const double* gz) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->set_sponge(c_sp, gx, gy, gz);
+}
+
 fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us) {
   if (guard(ctx) != FSI_OK || !chi || !us) return FSI_EINVAL;
   return ctx->eng->get_mask(chi, us);

@@ -587,6 +587,41 @@ class Engine : public EngineBase {
   }
 
   // -- one step ------------------------------------------------------------------
+  // vorticity sponge: chi_sp = max(gx[x], gy[y], gz[z]) (NULL profile = 0), c_sp <= 0: off
+  fsi_status set_sponge(double c_sp, const double* gx, const double* gy, const double* gz) override {
+    if (!std::isfinite(c_sp)) {
+      err = "c_sp must be finite";
+      return FSI_EINVAL;
+    }
+    if (c_sp <= 0.0 || (!gx && !gy && !gz)) {
+      sponge_on = false;
+      return FSI_OK;
+    }
+    std::vector<T> g((size_t)nx + ny + nz, (T)0);
+    const double* src[3] = {gx, gy, gz};
+    const int len[3] = {nx, ny, nz};
+    size_t o = 0;
+    for (int q = 0; q < 3; ++q) {
+      for (int i = 0; i < len[q]; ++i) {
+        const double v = src[q] ? src[q][i] : 0.0;
+        if (!(v >= 0.0) || !std::isfinite(v)) {
+          err = "sponge profiles must be finite and >= 0";
+          return FSI_EINVAL;
+        }
+        g[o + i] = (T)v;
+      }
+      o += len[q];
+    }
+    FSI_TRY(ensure_phys());
+    if (!spg_) FSI_TRY(alloc(&spg_, (long long)nx + ny + nz));
+    if (!tsp_) FSI_TRY(alloc(&tsp_, 3 * clen));
+    FSI_HIP(hipMemcpyAsync(spg_, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    csp = c_sp;
+    sponge_on = true;
+    return FSI_OK;
+  }
+
   fsi_status step(bool adaptive, double dt, double cfl, double c_eta, double dt_max) override {
     if (adaptive) {
       if (!(cfl > 0) || !(c_eta > 0) || !(dt_max > 0) || !std::isfinite(cfl) || !std::isfinite(dt_max)) {
@@ -667,6 +702,25 @@ class Engine : public EngineBase {
       a.inv_eta = (T)(1.0 / d.eta);
       FSI_HIP(launch_xfused<T>(a, nfused, s));
     }
+    // sponge: S = chi_sp omega from the x-spectral omega left in fields 3-5 of B
+    // (x inverse, mask, x forward, back into the same fields)
+    if (sponge_on) {
+      XArgs<T> a = x_base();
+      a.spec = B + 3 * Blen;
+      a.sfs = Blen;
+      a.phys = phys;
+      a.pfs = npts;
+      FSI_HIP(launch_xplain<T>(X_C2R, 3, a, npart, s));
+      SpongeArgs<T> m;
+      m.phys = phys;
+      m.npts = npts;
+      m.nx = nx;
+      m.ny = ny;
+      m.nz = nz;
+      m.g = spg_;
+      FSI_HIP(launch_sponge_mask<T>(m, s));
+      FSI_HIP(launch_xplain<T>(X_R2C, 3, a, npart, s));
+    }
     if (ev) FSI_HIP(hipEventRecord(ev[4], s));
     // diagnostics and dt_n
     {
@@ -699,9 +753,19 @@ class Engine : public EngineBase {
       a.out = A;
       a.out_fs = Alen;
       a.out_bs = C1;
-      a.nf = 3;
+      a.nf = sponge_on ? 6 : 3;  // G, and S with the sponge
       a.scale = (T)1;
       FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    if (sponge_on) {  // z forward of S and the sponge term T_hat = -(1/C_sp) i k x S_hat / |k|^2
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = A + 3 * Alen;
+      a.in_fs = Alen;
+      a.out = tsp_;
+      a.cfs = clen;
+      a.scale = (T)(1.0 / (double)npts);
+      a.csp_inv = (T)(1.0 / csp);
+      FSI_HIP(launch_col<T>(COL_FWD_SPONGE, a, 1, s));
     }
     if (ev) FSI_HIP(hipEventRecord(ev[6], s));
     // P5: z forward, dealias, Leray projection, integrating-factor AB2
@@ -718,6 +782,7 @@ class Engine : public EngineBase {
       a.nu = (T)d.nu;
       a.scale = (T)(1.0 / (double)npts);
       a.pi = d.fsi_pressure ? pi_ : nullptr;
+      a.tsp = sponge_on ? tsp_ : nullptr;
       // and P1 of the next step on the same columns (in place: each workgroup
       // has read all rows of its columns of A before it writes them)
       a.zout = A;
@@ -870,6 +935,10 @@ class Engine : public EngineBase {
                           double* dJdv) override {
     if (slot < 0 || slot >= (int)slots.size() || !slots[slot].used) {
       err = "tape slot is empty";
+      return FSI_ESTATE;
+    }
+    if (sponge_on) {
+      err = "the adjoint step does not include the sponge term";
       return FSI_ESTATE;
     }
     if (!(dt > 0) || (!first && !(dtp > 0))) {
@@ -1142,6 +1211,8 @@ class Engine : public EngineBase {
     free_dev(twz);
     free_dev(phys);
     free_dev(cwork);
+    free_dev(spg_);
+    free_dev(tsp_);
     free_dev(dx_);
     free_dev(dv_);
     free_dev(dtri_);
@@ -1442,6 +1513,10 @@ class Engine : public EngineBase {
   cpx<T>*twx = nullptr, *twy = nullptr, *twz = nullptr;
   cpx<T>*uh = nullptr, *nh = nullptr, *A = nullptr, *B = nullptr, *cwork = nullptr;
   bool zs_valid = false;  // A[0..4] holds the z inverse (P1) of the current u_hat
+  bool sponge_on = false;
+  double csp = 0.0;
+  T* spg_ = nullptr;        // sponge profiles gx, gy, gz
+  cpx<T>* tsp_ = nullptr;   // [3][clen] sponge term of the step
   T* phys = nullptr;
   double* partials = nullptr;
   DevScalars* sc = nullptr;

@@ -28,7 +28,8 @@ enum ColMode {
   COL_FWD_ACC_CURL = 6,  // adjoint: out += m_k * (i k x forward(in[0..2]))
   COL_INV_CURL5 = 7,     // z inverse of u and of omega_x, omega_y (5 outputs)
   COL_INV_WZ = 8,        // y inverse of 5 fields plus omega_z = i (kx uy - ky ux) (6 outputs)
-  COL_FWD_UPDATE_Z = 9   // COL_FWD_UPDATE, then COL_INV_CURL5 of the new velocity into zout
+  COL_FWD_UPDATE_Z = 9,  // COL_FWD_UPDATE, then COL_INV_CURL5 of the new velocity into zout
+  COL_FWD_SPONGE = 10    // sponge term -(1/C_sp) i k x forward(in[0..2]) / |k|^2 into out (compact)
 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 
@@ -70,6 +71,18 @@ struct ColArgs {
   cpx<T>* pi;  // update pass: total pressure Pi_hat = -i k.N'/|k|^2 (compact), NULL = not kept
   cpx<T>* zout;       // COL_FWD_UPDATE_Z: the five z-inverse fields of the new velocity
   long long zout_fs;  // their field stride (row pitch ld, as the input)
+  const cpx<T>* tsp;  // update passes: sponge term added before the projection, NULL = none
+  T csp_inv;          // COL_FWD_SPONGE: 1 / C_sp
+};
+
+// Sponge mask on the physical grid: phys[f] *= max(gx[x], gy[y], gz[z]), f < 3.
+template <typename T>
+struct SpongeArgs {
+  T* phys;
+  long long npts;
+  int nx, ny;
+  const T* g;  // gx (nx values), then gy (ny), then gz (nz)
+  int nz;
 };
 
 template <typename T>

@@ -489,6 +489,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
       }
     }
+    if constexpr (MODE == COL_FWD_SPONGE) {
+      // T_hat = -(1/C_sp) i k x S_hat / |k|^2 (zero at k = 0), S the masked vorticity
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (cok && i < nb) {
+          const T kz = a.kfz * (T)band_mode(i, K);
+          const cpx<T> v0 = st[0][k], v1 = st[1][k];
+          const cpx<T> v2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
+          const T k2 = kx * kx + ky * ky + kz * kz;
+          const T f = k2 > (T)0 ? -a.csp_inv / k2 : (T)0;
+          const cpx<T> t0 = scl(v2, ky) - scl(v1, kz);  // i k x v = i t
+          const cpx<T> t1 = scl(v0, kz) - scl(v2, kx);
+          const cpx<T> t2 = scl(v1, kx) - scl(v0, ky);
+          const long long idx = (long long)i * a.ld + c;
+          a.out[idx] = scl(mk<T>(-t0.im, t0.re), f);
+          a.out[a.cfs + idx] = scl(mk<T>(-t1.im, t1.re), f);
+          a.out[2 * a.cfs + idx] = scl(mk<T>(-t2.im, t2.re), f);
+        }
+      }
+    }
     constexpr bool UPD = (MODE == COL_FWD_UPDATE || MODE == COL_FWD_UPDATE_Z);
     if constexpr (MODE == COL_FWD_PROJECT || UPD) {
       // COL_FWD_UPDATE_Z keeps the new velocity of the thread's rows for the
@@ -546,6 +570,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             cpx<T> n2 = scl(buf[band_to_row(i, K, n) * W + col], a.scale);
             const T k2 = kx * kx + ky * ky + kz * kz;
             const long long idx = (long long)i * a.ld + c;
+            if constexpr (UPD) {
+              if (a.tsp) {  // vorticity sponge (solenoidal: the projection keeps it)
+                n0 = n0 + a.tsp[idx];
+                n1 = n1 + a.tsp[a.cfs + idx];
+                n2 = n2 + a.tsp[2 * a.cfs + idx];
+              }
+            }
             if (k2 > (T)0) {
               const T ik2 = (T)1 / k2;
               cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
@@ -1255,6 +1286,28 @@ hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(kNT) void sponge_mask(SpongeArgs<T> a) {
+  const T* gy = a.g + a.nx;
+  const T* gz = gy + a.ny;
+  for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < a.npts; i += (long long)gridDim.x * kNT) {
+    const int x = (int)(i % a.nx);
+    const long long r = i / a.nx;
+    const int y = (int)(r % a.ny), z = (int)(r / a.ny);
+    const T m = fmax(fmax(a.g[x], gy[y]), gz[z]);
+    a.phys[i] *= m;
+    a.phys[a.npts + i] *= m;
+    a.phys[2 * a.npts + i] *= m;
+  }
+}
+
+template <typename T>
+hipError_t launch_sponge_mask(const SpongeArgs<T>& a, hipStream_t s) {
+  const long long nb = std::min((a.npts + kNT - 1) / kNT, 8192LL);
+  hipLaunchKernelGGL(sponge_mask<T>, dim3((unsigned)std::max(nb, 1LL)), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename K>
 static hipError_t set_lds(K kernel, size_t lds) {
   if (lds > 65536) return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1291,6 +1344,7 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
     FSI_COL_CASE(COL_FWD_PROJECT)
     FSI_COL_CASE(COL_FWD_UPDATE)
     FSI_COL_CASE(COL_FWD_UPDATE_Z)
+    FSI_COL_CASE(COL_FWD_SPONGE)
     FSI_COL_CASE(COL_FWD_ACC)
     FSI_COL_CASE(COL_FWD_ACC_CURL)
     default: return hipErrorInvalidValue;
@@ -1423,6 +1477,8 @@ template hipError_t launch_xplain<double>(int, int, const XArgs<double>&, int, h
 template hipError_t launch_pbox<float>(int, const BoxArgs<float>&, hipStream_t);
 template hipError_t launch_pbox<double>(int, const BoxArgs<double>&, hipStream_t);
 template hipError_t launch_psample<float>(const PressArgs<float>&, hipStream_t);
+template hipError_t launch_sponge_mask<float>(const SpongeArgs<float>&, hipStream_t);
+template hipError_t launch_sponge_mask<double>(const SpongeArgs<double>&, hipStream_t);
 template hipError_t launch_psample<double>(const PressArgs<double>&, hipStream_t);
 template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);
 template hipError_t launch_mask<double>(const MaskArgs<double>&, hipStream_t);

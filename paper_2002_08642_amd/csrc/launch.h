@@ -60,6 +60,8 @@ hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
 template <typename T>
+hipError_t launch_sponge_mask(const SpongeArgs<T>& a, hipStream_t s);
+template <typename T>
 hipError_t launch_pbox(int embed, const BoxArgs<T>& a, hipStream_t s);
 
 template <typename T>

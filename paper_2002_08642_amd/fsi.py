@@ -35,7 +35,7 @@ EXPORTS = [
     "fsi_loads_adjoint",
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
-    "fsi_set_wing", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
+    "fsi_set_wing", "fsi_set_sponge", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
@@ -87,6 +87,7 @@ def load_library():
     lib.fsi_get_velocity.argtypes = [P, D]
     lib.fsi_get_spectrum.argtypes = [P, D]
     lib.fsi_set_wing.argtypes = [P, I32, D, D, I32, ctypes.POINTER(I32)]
+    lib.fsi_set_sponge.argtypes = [P, ctypes.c_double, D, D, D]
     lib.fsi_get_mask.argtypes = [P, D, D]
     lib.fsi_step.argtypes = [P, ctypes.c_double]
     lib.fsi_step_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -296,6 +297,16 @@ class Solver:
         self._check(self.lib.fsi_set_wing(self.ctx, nv, _dptr(x), _dptr(v), nt,
                                           tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         self._nv = nv if nt > 0 else 0
+
+    def set_sponge(self, c_sp, gx=None, gy=None, gz=None):
+        """Vorticity sponge: chi_sp = max(gx[x], gy[y], gz[z]) (None = 0); c_sp <= 0 switches it off."""
+        prof = [None if g is None else _f64(g).ravel() for g in (gx, gy, gz)]
+        for g, m in zip(prof, self.n):
+            if g is not None and g.size != m:
+                raise ValueError("sponge profile length must match the grid")
+        self._check(self.lib.fsi_set_sponge(self.ctx, float(c_sp),
+                                            *[None if g is None else _dptr(g) for g in prof]))
+        self._sponge_keep = prof
 
     def clear_wing(self):
         self._check(self.lib.fsi_set_wing(self.ctx, 0, None, None, 0, None))
