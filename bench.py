@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -85,12 +87,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def run_gpu(n, prec, steps, warmup, timing):
+def sponge_layers(n):
+    """Sponge of the optional leg: cosine layers n/8 deep at the two x faces and at the top z face."""
+    w = max(2, n // 8)
+    i = np.arange(n)
+    d = np.minimum(i, n - i) / float(w)
+    gx = np.where(d < 1.0, 0.5 * (1.0 + np.cos(np.pi * d)), 0.0)
+    dz = (n - 1 - i) / float(w)
+    gz = np.where(dz < 1.0, 0.5 * (1.0 + np.cos(np.pi * dz)), 0.0)
+    return gx, gz
+
+
+SPONGE_C = 1e-2  # C_sp of the sponge leg (dt / C_sp ~ 0.01 on this workload)
+
+
+def run_gpu(n, prec, steps, warmup, timing, sponge=False):
     from paper_2002_08642_amd import fsi
     import synth
     cfg = workload(n)
     s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
     s.set_spectrum(synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0))
+    if sponge:
+        gx, gz = sponge_layers(n)
+        s.set_sponge(SPONGE_C, gx=gx, gz=gz)
     t = 0.0
 
     def one_step(t):
@@ -247,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-k", type=int, default=10,
                     help="steps in the timed adjoint segment (0 skips the adjoint/forward leg)")
+    ap.add_argument("--sponge-steps", type=int, default=10,
+                    help="timed steps of the leg with the vorticity sponge on (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--no-torch", action="store_true",
@@ -270,6 +291,13 @@ def main():
         ms64, pass64, _ = run_gpu(n, fsi.PREC_FP64, args.fp64_steps, 2, True)
 
     adj = run_adjoint(n, fsi.PREC_FP32, args.adjoint_k) if args.adjoint_k > 0 else None
+    spg = None
+    if args.sponge_steps > 0:
+        mss, passs, _ = run_gpu(n, fsi.PREC_FP32, args.sponge_steps, 2, True, sponge=True)
+        spg = {"value": round(n ** 3 / mss / 1e6, 1), "unit": "Mpts/s", "ms_per_step": round(mss * 1e3, 4),
+               "steps": args.sponge_steps, "c_sp": SPONGE_C,
+               "layers": "cosine layers n/8 deep at both x faces and the top z face",
+               "pass_ms": {k: round(v, 4) for k, v in passs.items()}}
 
     dominant = max(pass32, key=pass32.get)
     cfg = workload(n)
@@ -334,6 +362,7 @@ def main():
             "pass_ms": {k: round(v, 4) for k, v in pass64.items()},
         },
         "adjoint": adj,
+        "sponge": spg,
         "last_step": {"dt": info32["dt"], "umax": info32["umax"], "E": info32["E"],
                       "F": [float(f) for f in info32["F"]]},
         "cpu_baseline": None,

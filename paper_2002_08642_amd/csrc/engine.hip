@@ -704,7 +704,12 @@ class Engine : public EngineBase {
     }
     // sponge: S = chi_sp omega from the x-spectral omega left in fields 3-5 of B
     // (x inverse, mask, x forward, back into the same fields)
-    if (sponge_on) {
+    if (sponge_on && nx == 512) {  // register transforms, in place
+      XArgs<T> a = x_base();
+      a.spec = B;
+      a.sfs = Blen;
+      FSI_HIP(launch_xsponge<T>(a, spg_, nfused, s));
+    } else if (sponge_on) {
       XArgs<T> a = x_base();
       a.spec = B + 3 * Blen;
       a.sfs = Blen;

@@ -996,6 +996,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
   }
 }
 
+// Masked vorticity of the sponge at nx = 512: the x-spectral omega (fields 3-5
+// of a line pair) is transformed to the grid, multiplied by chi_sp = max(gx[x],
+// gy[y], gz[z]) and transformed back into the same fields.  One wavefront per
+// line pair, the register transforms of the fused pass: (wx + i wy) of each
+// line and (wz of line 0 + i wz of line 1), three inverse and three forward
+// transforms per pair; every input of a pair is read before its outputs are
+// stored, so the pass runs in place.
+template <typename T>
+__global__ __launch_bounds__(256) void xsponge_wave512(XArgs<T> a, const T* g) {
+  __shared__ cpx<T> xbuf[4][kXBuf];
+  __shared__ cpx<T> tws[3][512];
+  __shared__ T gxs[512];
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  cpx<T>* X = xbuf[wv];
+  constexpr int K = 170;
+  wave512_twiddles<T, 256>(tws, a.tw);
+  for (int i = threadIdx.x; i < 512; i += 256) gxs[i] = g[i];
+  __syncthreads();
+  const T* gy = g + 512;
+  const T* gz = gy + a.ny;
+  const int npairs = a.nlines / 2;
+#pragma unroll 1
+  for (int pr = blockIdx.x * 4 + wv; pr < npairs; pr += gridDim.x * 4) {
+    const int l0 = 2 * pr, l1 = 2 * pr + 1;
+    const T m0 = fmax(gy[l0 % a.ny], gz[l0 / a.ny]);
+    const T m1 = fmax(gy[l1 % a.ny], gz[l1 / a.ny]);
+    Raw512<T> w0, w1, w2;
+    const long long o0 = (long long)l0 * a.ld, o1 = (long long)l1 * a.ld;
+    load512<T>(a.spec + 3 * a.sfs + o0, a.spec + 4 * a.sfs + o0, lane, w0);
+    load512<T>(a.spec + 3 * a.sfs + o1, a.spec + 4 * a.sfs + o1, lane, w1);
+    load512<T>(a.spec + 5 * a.sfs + o0, a.spec + 5 * a.sfs + o1, lane, w2);
+    cpx<T> v[8];
+    // lane holds the grid points x = (lane >> 3) + 8 (lane & 7) + 64 j
+    pack512<T>(w0, lane, v);
+    inv512<T>(v, X, lane, tws[0], tws[1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = scl(v[j], fmax(gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j], m0));
+    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    unpack_store512<T>(v, lane, K, a.spec + 3 * a.sfs + o0, a.spec + 4 * a.sfs + o0);
+    pack512<T>(w1, lane, v);
+    inv512<T>(v, X, lane, tws[0], tws[1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = scl(v[j], fmax(gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j], m1));
+    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    unpack_store512<T>(v, lane, K, a.spec + 3 * a.sfs + o1, a.spec + 4 * a.sfs + o1);
+    pack512<T>(w2, lane, v);
+    inv512<T>(v, X, lane, tws[0], tws[1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const T gxv = gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j];
+      v[j] = mk<T>(v[j].re * fmax(gxv, m0), v[j].im * fmax(gxv, m1));
+    }
+    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    unpack_store512<T>(v, lane, K, a.spec + 5 * a.sfs + o0, a.spec + 5 * a.sfs + o1);
+  }
+}
+
 // Plain real transforms along x for NF fields of L lines: real signal r = l * NF + f,
 // complex signal j packs real signals 2j (real part) and 2j + 1 (imaginary part).
 template <typename T, int NF, int L, int NT, int MAXE, int MODE>
@@ -1302,6 +1359,13 @@ __global__ __launch_bounds__(kNT) void sponge_mask(SpongeArgs<T> a) {
 }
 
 template <typename T>
+hipError_t launch_xsponge(const XArgs<T>& a, const T* g, int grid, hipStream_t s) {
+  if (a.n != 512 || a.nlines % 2 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(xsponge_wave512<T>, dim3(grid), dim3(256), 0, s, a, g);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_sponge_mask(const SpongeArgs<T>& a, hipStream_t s) {
   const long long nb = std::min((a.npts + kNT - 1) / kNT, 8192LL);
   hipLaunchKernelGGL(sponge_mask<T>, dim3((unsigned)std::max(nb, 1LL)), dim3(kNT), 0, s, a);
@@ -1478,6 +1542,8 @@ template hipError_t launch_pbox<float>(int, const BoxArgs<float>&, hipStream_t);
 template hipError_t launch_pbox<double>(int, const BoxArgs<double>&, hipStream_t);
 template hipError_t launch_psample<float>(const PressArgs<float>&, hipStream_t);
 template hipError_t launch_sponge_mask<float>(const SpongeArgs<float>&, hipStream_t);
+template hipError_t launch_xsponge<float>(const XArgs<float>&, const float*, int, hipStream_t);
+template hipError_t launch_xsponge<double>(const XArgs<double>&, const double*, int, hipStream_t);
 template hipError_t launch_sponge_mask<double>(const SpongeArgs<double>&, hipStream_t);
 template hipError_t launch_psample<double>(const PressArgs<double>&, hipStream_t);
 template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);

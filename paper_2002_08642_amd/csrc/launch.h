@@ -62,6 +62,8 @@ hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_sponge_mask(const SpongeArgs<T>& a, hipStream_t s);
 template <typename T>
+hipError_t launch_xsponge(const XArgs<T>& a, const T* g, int grid, hipStream_t s);
+template <typename T>
 hipError_t launch_pbox(int embed, const BoxArgs<T>& a, hipStream_t s);
 
 template <typename T>

@@ -36,13 +36,19 @@ def top_taper(m, width):
     return np.where(d < 1.0, 0.5 * (1.0 + np.cos(np.pi * d)), 0.0)
 
 
-CASES = [((32, 24, 20), (2.0, 1.5, 1.25)), ((16, 12, 512), (1.0, 0.75, 32.0))]
+# (512, 16, 12): the register-resident sponge x pass; (16, 12, 512): the
+# compile-time 512-point column kernels
+CASES = [((32, 24, 20), (2.0, 1.5, 1.25)), ((16, 12, 512), (1.0, 0.75, 32.0)), ((512, 16, 12), (8.0, 0.25, 0.1875))]
+# wing thickness, smoothing and plate sides per case (the thin box needs a small plate)
+GEOM = {(32, 24, 20): (0.05, 0.03, 0.3, 0.2), (16, 12, 512): (0.05, 0.03, 0.3, 0.2),
+        (512, 16, 12): (0.03, 0.016, 0.3, 0.025)}
 
 
 @pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
 @pytest.mark.parametrize("n,L", CASES)
 def test_sponge_parity(n, L, prec):
-    nu, eta, tw, h, c_sp = 0.01, 0.05, 0.05, 0.03, 0.08
+    tw, h, pa, pb = GEOM[n]
+    nu, eta, c_sp = 0.01, 0.05, 0.08
     print("sponge", n, prec, flush=True)
     o = ons.OracleNS(n, L, nu, eta, tw, h, 0)
     s = fsi.Solver(n, L, nu, eta, tw, h, 0, prec)
@@ -55,7 +61,7 @@ def test_sponge_parity(n, L, prec):
     centre = (0.5 * L[0] + 0.013, 0.5 * L[1] + 0.021, 0.5 * L[2] - 0.007)
     ua = np.array([1.0, 0.05, 0.02]) / np.linalg.norm([1.0, 0.05, 0.02])
     va = np.array([0.0, 0.3, 1.0]) / np.linalg.norm([0.0, 0.3, 1.0])
-    x, tri = synth.flat_rectangle(centre, ua, va, 0.3, 0.2, 6, 4)
+    x, tri = synth.flat_rectangle(centre, ua, va, pa, pb, 6, 4)
     v = np.tile(np.array([0.2, -0.1, 0.05]), (len(x), 1))
     o.set_wing(x, v, tri)
     s.set_wing(x, v, tri)
