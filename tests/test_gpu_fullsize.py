@@ -1,0 +1,154 @@
+"""Parity at the full 512^3 size in the launch configuration bench.py times.
+
+At this size the FP64 oracle cannot run a whole step inside a test, so the
+checks are outputs it computes one by one, closed forms, and identities of the
+discrete method that hold at any size:
+
+* 2-D Taylor-Green at 512^3: the step (all passes, the compile-time 512-point
+  kernels, the fused update/z-inverse pass) reproduces the exact decay
+  exp(-2 nu t) for a random dt sequence (closed form, FP32 and FP64);
+* the bench workload (k^-5/3 field, revolving plate at full speed, adaptive dt),
+  first step in FP32:
+  - mask chi and u_s at sampled grid points against the oracle's distance to
+    the triangles (brute force over all triangles, point by point);
+  - the velocity at sampled points against the direct sum over the stored
+    spectrum (point by point, FP64);
+  - E, u_max, the force and dt against their definitions on the device's own
+    velocity and mask (the reductions and the CFL rule at full size);
+  - the nonlinear term is solenoidal and does exactly the penalization work
+    Re sum w conj(u_hat).N_hat = -(1/(eta N^3)) sum chi u.(u - u_s) (u x omega
+    does none);
+  - the update is the first (Euler) integrating-factor step of that term.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mask as omask
+from paper_2002_08642_amd import fsi
+from tests.helpers import rel_max
+import bench
+import synth
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+
+
+def compact_wavenumbers(s, L):
+    """kx, ky, kz broadcastable to the compact shape (iz, iy, ix), band order."""
+    nz_b, ny_b, nx_b = s.compact_shape
+    Kz, Ky = (nz_b - 1) // 2, (ny_b - 1) // 2
+    mz = np.concatenate([np.arange(Kz + 1), np.arange(-Kz, 0)])
+    my = np.concatenate([np.arange(Ky + 1), np.arange(-Ky, 0)])
+    mx = np.arange(nx_b)
+    return (2 * np.pi * mx / L[0])[None, None, :], (2 * np.pi * my / L[1])[None, :, None], \
+        (2 * np.pi * mz / L[2])[:, None, None]
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP32, fsi.PREC_FP64])
+def test_fullsize_taylor_green_exact_decay(prec):
+    n, L, nu = (N, N, N), (2 * np.pi,) * 3, 0.05
+    print("512^3 Taylor-Green", prec, flush=True)
+    s = fsi.Solver(n, L, nu, 1.0, precision=prec)
+    u0 = synth.taylor_green_2d(n, L)
+    s.set_velocity(u0)
+    t = 0.0
+    for dt in np.random.default_rng(9).uniform(1e-3, 2e-2, 4):
+        s.step(dt)
+        t += dt
+    err = rel_max(s.velocity(), np.exp(-2 * nu * t) * u0)
+    print("512^3 Taylor-Green prec %d: %.3e" % (prec, err), flush=True)
+    assert err < (1e-12 if prec == fsi.PREC_FP64 else 2e-6)
+
+
+def test_fullsize_bench_first_step():
+    cfg = bench.workload(N)
+    n, L = cfg["n"], cfg["L"]
+    print("512^3 bench workload, first step", flush=True)
+    s = fsi.Solver(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], fsi.PREC_FP32)
+    uh0 = synth.random_solenoidal_compact(n, L, seed=0)
+    s.set_spectrum(uh0)
+    x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], 0.0, cfg["alpha"], cfg["omega"], 0.0,
+                             cfg["axis_point"])
+    tri = np.asarray(cfg["tri"])
+    s.set_wing(x, v, tri)
+    uh0 = s.spectrum()  # the stored (FP32-rounded) initial spectrum
+    u0 = s.velocity()
+    chi, us = s.mask()
+    dx = L[0] / N
+    rng = np.random.default_rng(17)
+
+    # mask at sampled points: oracle distance to every triangle, lowest index wins ties
+    inside = np.argwhere(chi > 0)
+    pick = inside[rng.choice(len(inside), 300, replace=False)]
+    lo = np.floor((x.min(0) - cfg["tw"] - cfg["h"]) / dx).astype(int)
+    hi = np.ceil((x.max(0) + cfg["tw"] + cfg["h"]) / dx).astype(int)
+    extra = np.stack([rng.integers(lo[2], hi[2], 100), rng.integers(lo[1], hi[1], 100),
+                      rng.integers(lo[0], hi[0], 100)], axis=1)
+    idx = np.concatenate([pick, extra])  # (z, y, x)
+    pts = idx[:, ::-1] * dx
+    best = np.full(len(pts), np.inf)
+    wb = np.zeros((len(pts), 3))
+    tb = np.zeros(len(pts), dtype=np.int64)
+    for t in range(len(tri)):
+        d, w = omask.point_triangle(pts, x[tri[t, 0]], x[tri[t, 1]], x[tri[t, 2]])
+        upd = d < best
+        best[upd], wb[upd], tb[upd] = d[upd], w[upd], t
+    r = omask.support_radius(cfg["tw"], cfg["h"], cfg["profile"])
+    ins = best < r
+    chi_o = np.where(ins, omask.chi_profile(np.where(ins, best, 0.0), cfg["tw"], cfg["h"], cfg["profile"]), 0.0)
+    us_o = np.where(ins[:, None], np.einsum("pk,pkc->pc", wb, v[tri[tb]]), 0.0)
+    chi_g = chi[idx[:, 0], idx[:, 1], idx[:, 2]]
+    us_g = us[:, idx[:, 0], idx[:, 1], idx[:, 2]].T
+    e_chi = np.max(np.abs(chi_g - chi_o))
+    e_us = np.max(np.abs(us_g - us_o)) / np.max(np.abs(v))
+    print("mask at %d points: chi %.3e u_s %.3e" % (len(pts), e_chi, e_us), flush=True)
+    assert e_chi < 1e-6 and e_us < 1e-5
+
+    # velocity at sampled points: direct FP64 sum over the stored band
+    kx, ky, kz = compact_wavenumbers(s, L)
+    wgt = np.where(kx == 0, 1.0, 2.0)
+    umax_abs = np.max(np.abs(u0))
+    for p in rng.integers(0, N, (3, 3)):
+        ph = np.exp(1j * (kx * (p[0] * dx) + ky * (p[1] * dx) + kz * (p[2] * dx))) * wgt
+        uo = np.array([np.sum(uh0[c] * ph).real for c in range(3)])
+        eu = np.max(np.abs(u0[:, p[2], p[1], p[0]] - uo)) / umax_abs
+        assert eu < 1e-5, (p, eu)
+
+    s.step_adaptive(cfg["cfl"], cfg["c_eta"], cfg["dt_max"])
+    info = s.info()
+    nh0 = s.nonlinear()
+    uh1 = s.spectrum()
+
+    # reductions and the CFL rule on the device's own fields
+    dV = dx ** 3
+    speed2 = np.sum(u0 * u0, axis=0)
+    E = 0.5 * dV * np.sum(speed2)
+    umax = np.sqrt(np.max(speed2))
+    slip = u0 - us
+    F = (dV / cfg["eta"]) * np.array([np.sum(chi * slip[c]) for c in range(3)])
+    dt = min(cfg["cfl"] * dx / info["umax"], cfg["c_eta"] * cfg["eta"], cfg["dt_max"])
+    print("E %.3e umax %.3e F %.3e dt %.3e" % (abs(info["E"] / E - 1), abs(info["umax"] / umax - 1),
+                                               rel_max(np.asarray(info["F"]), F), abs(info["dt"] / dt - 1)),
+          flush=True)
+    assert info["E"] == pytest.approx(E, rel=1e-6)
+    assert info["umax"] == pytest.approx(umax, rel=1e-6)
+    assert rel_max(np.asarray(info["F"]), F) < 1e-5
+    assert info["dt"] == pytest.approx(dt, rel=1e-12)
+
+    # the nonlinear term: solenoidal, and the work it does is the penalization's
+    k2 = kx * kx + ky * ky + kz * kz
+    div = np.abs(kx * nh0[0] + ky * nh0[1] + kz * nh0[2])
+    assert np.max(div) <= 1e-5 * np.max(np.sqrt(k2) * np.max(np.abs(nh0), axis=0))
+    work = float(np.sum(wgt * np.real(np.conj(uh0) * nh0)))
+    pen = -float(np.sum(chi * np.sum(u0 * slip, axis=0))) / (cfg["eta"] * N ** 3)
+    scale = float(np.sum(wgt * np.abs(uh0) * np.abs(nh0)))
+    print("work %.6e penalization %.6e (scale %.3e)" % (work, pen, scale), flush=True)
+    assert abs(work - pen) < 1e-5 * scale
+
+    # first step: integrating-factor Euler
+    expect = np.exp(-cfg["nu"] * k2 * info["dt"]) * (uh0 + info["dt"] * nh0)
+    eup = rel_max(uh1, expect)
+    print("update %.3e" % eup, flush=True)
+    assert eup < 1e-6
