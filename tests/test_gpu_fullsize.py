@@ -6,7 +6,8 @@ discrete method that hold at any size:
 
 * 2-D Taylor-Green at 512^3: the step (all passes, the compile-time 512-point
   kernels, the fused update/z-inverse pass) reproduces the exact decay
-  exp(-2 nu t) for a random dt sequence (closed form, FP32 and FP64);
+  exp(-2 nu t) for a random dt sequence (closed form, FP32 and FP64); the same
+  at 800^3 (FP32), the largest configuration;
 * the bench workload (k^-5/3 field, revolving plate at full speed, adaptive dt),
   first step in FP32:
   - mask chi and u_s at sampled grid points against the oracle's distance to
@@ -46,10 +47,11 @@ def compact_wavenumbers(s, L):
         (2 * np.pi * mz / L[2])[:, None, None]
 
 
-@pytest.mark.parametrize("prec", [fsi.PREC_FP32, fsi.PREC_FP64])
-def test_fullsize_taylor_green_exact_decay(prec):
-    n, L, nu = (N, N, N), (2 * np.pi,) * 3, 0.05
-    print("512^3 Taylor-Green", prec, flush=True)
+# 800^3 (= 2^5 5^2, the largest configuration: run-time mixed-radix plans) in FP32
+@pytest.mark.parametrize("m,prec", [(N, fsi.PREC_FP32), (N, fsi.PREC_FP64), (800, fsi.PREC_FP32)])
+def test_fullsize_taylor_green_exact_decay(m, prec):
+    n, L, nu = (m, m, m), (2 * np.pi,) * 3, 0.05
+    print("%d^3 Taylor-Green" % m, prec, flush=True)
     s = fsi.Solver(n, L, nu, 1.0, precision=prec)
     u0 = synth.taylor_green_2d(n, L)
     s.set_velocity(u0)
@@ -58,7 +60,7 @@ def test_fullsize_taylor_green_exact_decay(prec):
         s.step(dt)
         t += dt
     err = rel_max(s.velocity(), np.exp(-2 * nu * t) * u0)
-    print("512^3 Taylor-Green prec %d: %.3e" % (prec, err), flush=True)
+    print("%d^3 Taylor-Green prec %d: %.3e" % (m, prec, err), flush=True)
     assert err < (1e-12 if prec == fsi.PREC_FP64 else 2e-6)
 
 
