@@ -31,6 +31,39 @@ namespace fsi {
 // into registers before they are written to LDS, so that each thread keeps
 // all of its row loads in flight at once.
 
+// Two adjacent complex FP32 values moved as one 16-byte access (the 512-point
+// column passes: a lane carries two columns, halving the memory instructions).
+struct cpx2f {
+  cpx<float> a, b;
+};
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ cpx2f ld_stream2(const cpx<float>* p) {
+  const v4f w = (FSI_NT & 2) ? __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p))
+                             : *reinterpret_cast<const v4f*>(p);
+  return cpx2f{mk<float>(w.x, w.y), mk<float>(w.z, w.w)};
+}
+__device__ __forceinline__ void st_stream2(cpx<float>* p, cpx2f v) {
+  v4f w;
+  w.x = v.a.re;
+  w.y = v.a.im;
+  w.z = v.b.re;
+  w.w = v.b.im;
+  if (FSI_NT & 1) __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
+  else *reinterpret_cast<v4f*>(p) = w;
+}
+__device__ __forceinline__ cpx2f ld_lds2(const cpx<float>* p) {
+  const v4f w = *reinterpret_cast<const v4f*>(p);
+  return cpx2f{mk<float>(w.x, w.y), mk<float>(w.z, w.w)};
+}
+__device__ __forceinline__ void st_lds2(cpx<float>* p, cpx2f v) {
+  v4f w;
+  w.x = v.a.re;
+  w.y = v.a.im;
+  w.z = v.b.re;
+  w.w = v.b.im;
+  *reinterpret_cast<v4f*>(p) = w;
+}
+
 // f(integral_constant<int, I>) for I = B .. E - 1, in order
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -65,6 +98,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
   const int n = N ? N : a.n, K = N ? (N - 1) / 3 : a.K, nb = 2 * K + 1;
   // the RSTEP-row strides of a thread cover the column exactly: no row test
   constexpr bool FULL = N != 0 && N == MAXE * RSTEP;
+  // two columns per lane, 16-byte loads and stores (y passes at 512 points, FP32)
+  constexpr bool PAIR = FULL && N == 512 && sizeof(T) == 4 && W == 16;
   const long long ib = (long long)blockIdx.y * a.in_bs;
   const long long ob = (long long)blockIdx.y * a.out_bs;
   cpx<T>* tws = buf + n * W;
@@ -258,6 +293,76 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     } else {
       generic();
     }
+  } else if constexpr (MODE == COL_INV_WZ && PAIR) {
+    // COL_INV_WZ below with two columns per lane (same outputs, order and loads)
+    constexpr int WP = W / 2, RS2 = NT / WP, ME2 = MAXE / 2;
+    constexpr int MO2 = (2 * ((N - 1) / 3) + 1 + RS2 - 1) / RS2;
+    cpx2f RA[MO2], RB[MO2];
+    auto load_into = [&](int lq, cpx2f(&R)[MO2]) {
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
+      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
+#pragma unroll
+      for (int k = 0; k < MO2; ++k) {
+        const int i = rq + k * RS2;
+        R[k] = ld_stream2(in + (long long)(i < nb ? i : 0) * a.ld);
+      }
+    };
+    cpx<float>* bf = reinterpret_cast<cpx<float>*>(buf);
+    auto step = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      constexpr int fo = (o == 2) ? 5 : (o > 2) ? o - 1 : o;
+      constexpr int src = (o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0;
+      constexpr int lq = (o == 0) ? 1 : (o == 2) ? 2 : (o == 3) ? 3 : (o == 4) ? 4 : -1;
+      constexpr bool to_b = (o == 0 || o == 3);
+      const int tid = opaque((int)threadIdx.x);
+      const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
+      const bool ok0 = c < a.C && (c % a.kxp) < a.kx1, ok1 = c + 1 < a.C && ((c + 1) % a.kxp) < a.kx1;
+      const float kx0 = (float)a.kfx * (float)(c % a.kxp), kx1 = kx0 + (float)a.kfx;
+      const cpx2f zero{mk<float>(0, 0), mk<float>(0, 0)};
+#pragma unroll
+      for (int k = 0; k < ME2; ++k) {
+        const int r = rp + k * RS2;
+        if (r > K && r < n - K) st_lds2(bf + r * W + 2 * cp, zero);
+      }
+#pragma unroll
+      for (int k = 0; k < MO2; ++k) {
+        const int i = rp + k * RS2;
+        if (i < nb) {
+          cpx2f val = (src == 1) ? RB[k] : RA[k];
+          if constexpr (src == 2) {  // wz = i (kx uy - ky ux)
+            const float krow = (float)a.kfy * (float)band_mode(i, K);
+            const cpx<float> t0 = scl(RB[k].a, kx0) - scl(RA[k].a, krow);
+            const cpx<float> t1 = scl(RB[k].b, kx1) - scl(RA[k].b, krow);
+            val = cpx2f{mk<float>(-t0.im, t0.re), mk<float>(-t1.im, t1.re)};
+          }
+          if (!ok0) val.a = mk<float>(0, 0);
+          if (!ok1) val.b = mk<float>(0, 0);
+          st_lds2(bf + band_to_row(i, K, n) * W + 2 * cp, val);
+        }
+      }
+      __syncthreads();
+      if constexpr (lq >= 0) {
+        if constexpr (to_b) {
+          asm volatile("" ::: "memory");  // keeps the two load sites apart
+          load_into(lq, RB);
+        } else {
+          load_into(lq, RA);
+        }
+      }
+      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+      cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs + ob;
+      cpx2f ov[ME2];  // LDS reads first, then the stores (columns out of the band hold zeros)
+#pragma unroll
+      for (int k = 0; k < ME2; ++k) ov[k] = ld_lds2(bf + (rp + k * RS2) * W + 2 * cp);
+      if (c < a.C) {
+#pragma unroll
+        for (int k = 0; k < ME2; ++k) st_stream2(out + (long long)(rp + k * RS2) * a.ld + c, ov[k]);
+      }
+      __syncthreads();
+    };
+    load_into(0, RA);
+    static_for<0, 6>([&](auto oc) { step(oc); });
   } else if constexpr (MODE == COL_INV_CURL5 || MODE == COL_INV_WZ) {
     // Stored fields of the forward step.  omega_z = i (kx uy - ky ux) needs no z
     // derivative, so the z pass (COL_INV_CURL5) stores ux, uy, uz, wx, wy and the
@@ -351,6 +456,63 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     step(std::integral_constant<int, 3>{});
     step(std::integral_constant<int, 4>{});
     if constexpr (!Z5) step(std::integral_constant<int, 5>{});
+  } else if constexpr (MODE == COL_FWD_PLAIN && PAIR) {
+    // y forward (P4 and the helper transforms) with two columns per lane
+    constexpr int WP = W / 2, RS2 = NT / WP, ME2 = MAXE / 2;
+    constexpr int MO2 = (2 * ((N - 1) / 3) + 1 + RS2 - 1) / RS2;
+    const int nfield = a.nf;
+    cpx2f tmp[ME2];
+    cpx<float>* bf = reinterpret_cast<cpx<float>*>(buf);
+    auto load_field = [&](int f) __attribute__((always_inline)) {
+      const int tq = opaque((int)threadIdx.x);
+      const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
+      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs + ib + (cq < a.C ? cq : 0);
+#pragma unroll
+      for (int k = 0; k < ME2; ++k) tmp[k] = ld_stream2(in + (long long)(rq + k * RS2) * a.ld);
+    };
+    auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
+      const int tid = opaque((int)threadIdx.x);
+      const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
+#pragma unroll
+      for (int k = 0; k < ME2; ++k) st_lds2(bf + (rp + k * RS2) * W + 2 * cp, tmp[k]);
+      __syncthreads();
+      if (prefetch) load_field(f + 1);
+      col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
+      cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + f * a.out_fs + ob;
+      const float sc = (float)a.scale;
+      cpx2f ov[MO2];  // LDS reads first, then the stores
+#pragma unroll
+      for (int k = 0; k < MO2; ++k) {
+        const int i = rp + k * RS2;
+        ov[k] = ld_lds2(bf + band_to_row(i < nb ? i : 0, K, n) * W + 2 * cp);
+      }
+      if (c < a.C) {
+#pragma unroll
+        for (int k = 0; k < MO2; ++k) {
+          const int i = rp + k * RS2;
+          if (i < nb) st_stream2(out + (long long)i * a.ld + c, cpx2f{scl(ov[k].a, sc), scl(ov[k].b, sc)});
+        }
+      }
+      __syncthreads();
+    };
+    load_field(0);
+    if (nfield == 3) {
+      field(0, true);
+      field(1, true);
+      field(2, false);
+    } else if (nfield == 6) {
+      field(0, true);
+      field(1, true);
+      field(2, true);
+      field(3, true);
+      field(4, true);
+      field(5, false);
+    } else {
+      for (int f = 0; f < nfield; ++f) {
+        if (f > 0) load_field(f);
+        field(f, false);
+      }
+    }
   } else {
     // forward modes: all n rows in, band rows out
     const int nfield = (MODE == COL_FWD_PLAIN || MODE == COL_FWD_ACC) ? a.nf : 3;
