@@ -237,6 +237,13 @@ fsi_status fsi_get_nonlinear(fsi_ctx* ctx, double* nhat_host);
 fsi_status fsi_adjoint_set(fsi_ctx* ctx, const double* lam_uhat, const double* lam_nprev);
 /* Read the cotangent state (either pointer may be NULL). Synchronizes. */
 fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev);
+/* Zero the cotangent state (the start of a reverse sweep). Synchronizes. */
+fsi_status fsi_adjoint_reset(fsi_ctx* ctx);
+
+/* Forward step with its tape: saves the state at the start of the step in
+ * tape_slot (as fsi_save_state) and takes the step (as fsi_step), so that
+ * fsi_step_adjoint(tape_slot, ...) can reverse it later.  Errors as the two. */
+fsi_status fsi_step_record(fsi_ctx* ctx, double dt, int32_t tape_slot);
 
 /* Reverse one step. tape_slot holds the state saved (fsi_save_state) at the
  * start of the step; the wing of that step must be set (fsi_set_wing); dt is

@@ -200,6 +200,18 @@ fsi_status fsi_adjoint_set(fsi_ctx* ctx, const double* lam_uhat, const double* l
   return ctx->eng->adjoint_set(lam_uhat, lam_nprev);
 }
 
+fsi_status fsi_adjoint_reset(fsi_ctx* ctx) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->adjoint_set(nullptr, nullptr);
+}
+
+fsi_status fsi_step_record(fsi_ctx* ctx, double dt, int32_t tape_slot) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  const fsi_status st = ctx->eng->save_state(tape_slot);
+  if (st != FSI_OK) return st;
+  return ctx->eng->step(false, dt, 0.0, 0.0, 0.0);
+}
+
 fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev) {
   if (guard(ctx) != FSI_OK) return FSI_EINVAL;
   return ctx->eng->adjoint_get(lam_uhat, lam_nprev);

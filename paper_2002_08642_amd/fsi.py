@@ -35,7 +35,8 @@ EXPORTS = [
     "fsi_loads_adjoint",
     "fsi_version", "fsi_create", "fsi_destroy", "fsi_last_error", "fsi_create_error", "fsi_band",
     "fsi_set_velocity", "fsi_set_velocity_device", "fsi_set_spectrum", "fsi_get_velocity", "fsi_get_spectrum",
-    "fsi_set_wing", "fsi_set_sponge", "fsi_get_mask", "fsi_step", "fsi_step_adaptive", "fsi_get_step_info",
+    "fsi_set_wing", "fsi_set_sponge", "fsi_get_mask", "fsi_step", "fsi_step_record", "fsi_adjoint_reset",
+    "fsi_step_adaptive", "fsi_get_step_info",
     "fsi_fft_r2c", "fsi_fft_c2r", "fsi_save_state", "fsi_load_state", "fsi_synchronize",
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
@@ -88,6 +89,8 @@ def load_library():
     lib.fsi_get_spectrum.argtypes = [P, D]
     lib.fsi_set_wing.argtypes = [P, I32, D, D, I32, ctypes.POINTER(I32)]
     lib.fsi_set_sponge.argtypes = [P, ctypes.c_double, D, D, D]
+    lib.fsi_step_record.argtypes = [P, ctypes.c_double, I32]
+    lib.fsi_adjoint_reset.argtypes = [P]
     lib.fsi_get_mask.argtypes = [P, D, D]
     lib.fsi_step.argtypes = [P, ctypes.c_double]
     lib.fsi_step_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -266,6 +269,13 @@ class Solver:
             return None
         a = np.asarray(a, dtype=np.complex128).reshape((3,) + self.compact_shape)
         return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
+
+    def adjoint_reset(self):
+        self._check(self.lib.fsi_adjoint_reset(self.ctx))
+
+    def step_record(self, dt, slot):
+        """fsi_step_record: save the state in tape slot `slot`, then step."""
+        self._check(self.lib.fsi_step_record(self.ctx, float(dt), int(slot)))
 
     def adjoint_set(self, lam_u=None, lam_n=None):
         bu, bn = self._cbuf(lam_u), self._cbuf(lam_n)
