@@ -986,32 +986,9 @@ class Engine : public EngineBase {
       FSI_TRY(run_forward(phys, 1, piadj_, COL_FWD_PLAIN));
     }
     seed_pending = false;
-    // update transpose and projection: mu = P(lambda_N) / (m_k N^3)
-    {
-      AdjSpecArgs<T> a;
-      memset(&a, 0, sizeof(a));
-      a.lu = lu_;
-      a.lnp = lnp_;
-      a.mu = mu_;
-      a.cfs = clen;
-      a.nrows = nbz * nby;
-      a.nby = nby;
-      a.kx1 = kx1;
-      a.kxp = kxp;
-      a.Ky = Ky;
-      a.Kz = Kz;
-      a.kfx = (T)(2.0 * M_PI / d.lx);
-      a.kfy = (T)(2.0 * M_PI / d.ly);
-      a.kfz = (T)(2.0 * M_PI / d.lz);
-      a.nu = (T)d.nu;
-      a.dt = dt;
-      a.dtp = first ? dt : dtp;
-      a.first = first ? 1 : 0;
-      a.invN3 = 1.0 / (double)npts;
-      a.lpi = seed ? piadj_ : nullptr;
-      FSI_HIP(launch_adj_spectral<T>(a, s));
-    }
-    // inverse transforms: u, omega of the taped state and lambda_G = C2R(mu)
+    // inverse transforms: u, omega of the taped state, and the update and
+    // projection transposes with mu = P(lambda_N)/(m_k N^3) followed by
+    // lambda_G = C2R(mu) in one pass (z inverse of mu from registers)
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
       a.in = slots[slot].uh;
@@ -1019,10 +996,19 @@ class Engine : public EngineBase {
       a.out = A9;
       a.out_fs = Alen;
       FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
-      a.in = mu_;
-      a.out = A9 + 6 * Alen;
-      a.nf = 3;
-      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
+      ColArgs<T> m = col_base(pz, twz, nz, Kz, C1, C1);
+      m.uh = lu_;
+      m.nh = lnp_;
+      m.cfs = clen;
+      m.nu = (T)d.nu;
+      m.adt = dt;
+      m.adtp = first ? dt : dtp;
+      m.first = first ? 1 : 0;
+      m.invN3 = 1.0 / (double)npts;
+      m.lpi = seed ? piadj_ : nullptr;
+      m.out = A9 + 6 * Alen;
+      m.out_fs = Alen;
+      FSI_HIP(launch_col<T>(COL_ADJ_MU, m, 1, s));
     }
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);

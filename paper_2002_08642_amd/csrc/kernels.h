@@ -29,7 +29,9 @@ enum ColMode {
   COL_INV_CURL5 = 7,     // z inverse of u and of omega_x, omega_y (5 outputs)
   COL_INV_WZ = 8,        // y inverse of 5 fields plus omega_z = i (kx uy - ky ux) (6 outputs)
   COL_FWD_UPDATE_Z = 9,  // COL_FWD_UPDATE, then COL_INV_CURL5 of the new velocity into zout
-  COL_FWD_SPONGE = 10    // sponge term -(1/C_sp) i k x forward(in[0..2]) / |k|^2 into out (compact)
+  COL_FWD_SPONGE = 10,   // sponge term -(1/C_sp) i k x forward(in[0..2]) / |k|^2 into out (compact)
+  COL_ADJ_MU = 11        // adjoint: update/projection transpose on (uh = lambda_u, nh = lambda_N)
+                         // in place, then z inverse of mu = P(lambda_N)/(m_k N^3) into out (3 fields)
 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 
@@ -73,6 +75,11 @@ struct ColArgs {
   long long zout_fs;  // their field stride (row pitch ld, as the input)
   const cpx<T>* tsp;  // update passes: sponge term added before the projection, NULL = none
   T csp_inv;          // COL_FWD_SPONGE: 1 / C_sp
+  // COL_ADJ_MU (uh, nh: the cotangents of u_hat and of the previous nonlinear
+  // term; first, nu, cfs as for the update)
+  double adt, adtp;      // dt of the reversed step and the one before
+  double invN3;          // 1 / (nx ny nz)
+  const cpx<T>* lpi;     // pressure seed (normalized R2C of the cotangent of Pi), NULL = none
 };
 
 // Sponge mask on the physical grid: phys[f] *= max(gx[x], gy[y], gz[z]), f < 3.

@@ -293,6 +293,118 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     } else {
       generic();
     }
+  } else if constexpr (MODE == COL_ADJ_MU) {
+    // Reverse of the update and the projection (per mode) on the thread's band
+    // rows: lambda_N^n = a E lambda_u + lambda_N', the new lambda_N^{n-1} =
+    // -b E E_prev lambda_u, lambda_u <- E lambda_u, mu = P(lambda_N^n)/(m_k N^3)
+    // (+ i k lambda_Pi / |k|^2 with a pressure seed); then the z inverse of mu
+    // from registers (three outputs), as COL_INV_PLAIN would from memory.
+    const int ix = c % a.kxp, iy = c / a.kxp;
+    const T kx = a.kfx * (T)ix;
+    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+    T an, bn;
+    if (a.first) {
+      an = (T)a.adt;
+      bn = 0;
+    } else {
+      const double xi = a.adt / a.adtp;
+      an = (T)(a.adt * (1.0 + 0.5 * xi));
+      bn = (T)(a.adt * 0.5 * xi);
+    }
+    const T sc = (T)(a.invN3 / (ix == 0 ? 1.0 : 2.0));
+    cpx<T> M[3][MAXO];
+    constexpr int KC = sizeof(T) == 4 ? 3 : 1;
+    const int cl = c < a.C ? c : 0;
+#pragma unroll
+    for (int k0 = 0; k0 < MAXO; k0 += KC) {
+      cpx<T> uo[KC][3], po[KC][3];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {  // loads of the chunk before its stores
+        const int k = k0 + kk;
+        if (k < MAXO) {
+          const int i = r0 + k * RSTEP;
+          const long long idx = (long long)(i < nb ? i : 0) * a.ld + cl;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            uo[kk][q] = a.uh[q * a.cfs + idx];
+            po[kk][q] = a.nh[q * a.cfs + idx];
+          }
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        if (k >= MAXO) break;
+        const int i = r0 + k * RSTEP;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) M[q][k] = mk<T>(0, 0);
+        if (cok && i < nb) {
+          const T kz = a.kfz * (T)band_mode(i, K);
+          const T k2 = kx * kx + ky * ky + kz * kz;
+          const T en = dev_exp<T>(-a.nu * k2 * (T)a.adt);
+          const T ep = a.first ? (T)0 : dev_exp<T>(-a.nu * k2 * (T)a.adtp);
+          const long long idx = (long long)i * a.ld + c;
+          cpx<T> ln[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ln[q] = scl(uo[kk][q], an * en) + po[kk][q];             // cotangent of N_hat^n
+            a.nh[q * a.cfs + idx] = scl(uo[kk][q], -bn * en * ep);  // of N_hat^{n-1}
+            a.uh[q * a.cfs + idx] = scl(uo[kk][q], en);             // update share of u_hat^n
+          }
+          cpx<T> extra[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+          if (k2 > (T)0) {
+            const cpx<T> sp = scl(scl(ln[0], kx) + scl(ln[1], ky) + scl(ln[2], kz), (T)1 / k2);
+            ln[0] = ln[0] - scl(sp, kx);
+            ln[1] = ln[1] - scl(sp, ky);
+            ln[2] = ln[2] - scl(sp, kz);
+            if (a.lpi) {  // Pi_hat = -i k.N'_hat / |k|^2: its transpose adds i k lambda_Pi / |k|^2
+              const cpx<T> lp = a.lpi[idx];
+              const T ik2 = (T)1 / k2;
+              extra[0] = mk<T>(-kx * lp.im * ik2, kx * lp.re * ik2);
+              extra[1] = mk<T>(-ky * lp.im * ik2, ky * lp.re * ik2);
+              extra[2] = mk<T>(-kz * lp.im * ik2, kz * lp.re * ik2);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 3; ++q) M[q][k] = scl(ln[q], sc) + extra[q];
+        }
+      }
+    }
+    __syncthreads();
+    auto mstep = [&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const int tid = opaque((int)threadIdx.x);
+      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+      const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < MAXO; ++k) {
+        const int i = r0 + k * RSTEP;
+        if (i < nb) buf[band_to_row(i, K, n) * W + col] = cok ? M[o][k] : mk<T>(0, 0);
+      }
+      __syncthreads();
+      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+      cpx<T>* out = a.out + o * a.out_fs + ob;
+      cpx<T> ov[MAXE];  // LDS reads first, then the stores
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        const int r = r0 + k * RSTEP;
+        ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+      }
+      if (cok) {
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
+        }
+      }
+      __syncthreads();
+    };
+    static_for<0, 3>([&](auto oc) { mstep(oc); });
   } else if constexpr (MODE == COL_INV_WZ && PAIR) {
     // COL_INV_WZ below with two columns per lane (same outputs, order and loads)
     constexpr int WP = W / 2, RS2 = NT / WP, ME2 = MAXE / 2;
@@ -1571,6 +1683,7 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
     FSI_COL_CASE(COL_FWD_UPDATE)
     FSI_COL_CASE(COL_FWD_UPDATE_Z)
     FSI_COL_CASE(COL_FWD_SPONGE)
+    FSI_COL_CASE(COL_ADJ_MU)
     FSI_COL_CASE(COL_FWD_ACC)
     FSI_COL_CASE(COL_FWD_ACC_CURL)
     default: return hipErrorInvalidValue;
