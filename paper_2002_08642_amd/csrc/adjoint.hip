@@ -9,7 +9,8 @@
 //   R2C^T(mu)     = N^-3 C2R(mu / m_k),          m_k = 1 at kx = 0, else 2,
 //   (i k x)^T = i k x,  (u x omega)^T: lambda_u = omega x lambda, lambda_omega = lambda x u,
 // and the Leray projection, the 2/3 band and the integrating factors are real
-// symmetric per mode.
+// symmetric per mode.  The spectral part (update and projection transposes) is
+// the column pass COL_ADJ_MU (kernels.hip), fused with the z inverse of its output.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -21,63 +22,6 @@
 #include "wave512.h"
 
 namespace fsi {
-
-// ---------------------------------------------------------------------------
-// spectral part: update transpose and projection
-// ---------------------------------------------------------------------------
-
-template <typename T>
-__global__ __launch_bounds__(256) void adj_spectral(AdjSpecArgs<T> a) {
-  const long long total = (long long)a.nrows * a.kxp;
-  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
-    const int ix = (int)(e % a.kxp);
-    if (ix >= a.kx1) continue;
-    const long long row = e / a.kxp;
-    const int iy = (int)(row % a.nby), iz = (int)(row / a.nby);
-    const T kx = a.kfx * (T)ix;
-    const T ky = a.kfy * (T)band_mode(iy, a.Ky);
-    const T kz = a.kfz * (T)band_mode(iz, a.Kz);
-    const T k2 = kx * kx + ky * ky + kz * kz;
-    const T en = dev_exp<T>(-a.nu * k2 * (T)a.dt);
-    T an, bn;
-    if (a.first) {
-      an = (T)a.dt;
-      bn = 0;
-    } else {
-      const double xi = a.dt / a.dtp;
-      an = (T)(a.dt * (1.0 + 0.5 * xi));
-      bn = (T)(a.dt * 0.5 * xi);
-    }
-    const T ep = a.first ? (T)0 : dev_exp<T>(-a.nu * k2 * (T)a.dtp);
-    cpx<T> ln[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const cpx<T> lu = a.lu[q * a.cfs + e];
-      const cpx<T> lp = a.lnp[q * a.cfs + e];
-      ln[q] = scl(lu, an * en) + lp;                  // cotangent of N_hat^n
-      a.lnp[q * a.cfs + e] = scl(lu, -bn * en * ep);  // cotangent of N_hat^{n-1}
-      a.lu[q * a.cfs + e] = scl(lu, en);              // update share of u_hat^n
-    }
-    if (k2 > (T)0) {
-      const cpx<T> s = scl(scl(ln[0], kx) + scl(ln[1], ky) + scl(ln[2], kz), (T)1 / k2);
-      ln[0] = ln[0] - scl(s, kx);
-      ln[1] = ln[1] - scl(s, ky);
-      ln[2] = ln[2] - scl(s, kz);
-    }
-    const T sc = (T)(a.invN3 / (ix == 0 ? 1.0 : 2.0));
-    cpx<T> extra[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
-    if (a.lpi && k2 > (T)0) {
-      // Pi_hat = -i k.N'_hat / |k|^2: its transpose adds i k lambda_Pi_hat / |k|^2
-      const cpx<T> lp = a.lpi[e];
-      const T ik2 = (T)1 / k2;
-      const T kk[3] = {kx, ky, kz};
-#pragma unroll
-      for (int q = 0; q < 3; ++q) extra[q] = mk<T>(-kk[q] * lp.im * ik2, kk[q] * lp.re * ik2);
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) a.mu[q * a.cfs + e] = scl(ln[q], sc) + extra[q];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // fused x pass of the reverse step (two lines per workgroup, LDS transforms)
@@ -498,14 +442,6 @@ int xadj_supported(int n) {
 }
 
 template <typename T>
-hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s) {
-  long long blocks = ((long long)a.nrows * a.kxp + 255) / 256;
-  blocks = std::max(1LL, std::min(blocks, 16384LL));
-  hipLaunchKernelGGL(adj_spectral<T>, dim3((unsigned)blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_xadj(const XAdjArgs<T>& a, int grid, hipStream_t s) {
   if (a.n == 512 && a.nlines % 2 == 0) {
     hipLaunchKernelGGL(xadj_wave512<T>, dim3(grid), dim3(256), 0, s, a);
@@ -529,8 +465,6 @@ hipError_t launch_mask_adj(const MaskAdjArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_adj_spectral<float>(const AdjSpecArgs<float>&, hipStream_t);
-template hipError_t launch_adj_spectral<double>(const AdjSpecArgs<double>&, hipStream_t);
 template hipError_t launch_xadj<float>(const XAdjArgs<float>&, int, hipStream_t);
 template hipError_t launch_xadj<double>(const XAdjArgs<double>&, int, hipStream_t);
 template int xadj_supported<float>(int);

@@ -894,12 +894,10 @@ class Engine : public EngineBase {
     if (!lu_) {
       FSI_TRY(alloc(&lu_, 3 * clen));
       FSI_TRY(alloc(&lnp_, 3 * clen));
-      FSI_TRY(alloc(&mu_, 3 * clen));
       FSI_TRY(alloc(&A9, 9 * Alen));
       FSI_TRY(alloc(&B9, 9 * Blen));
       FSI_HIP(hipMemsetAsync(lu_, 0, sizeof(cpx<T>) * 3 * clen, s));
       FSI_HIP(hipMemsetAsync(lnp_, 0, sizeof(cpx<T>) * 3 * clen, s));
-      FSI_HIP(hipMemsetAsync(mu_, 0, sizeof(cpx<T>) * 3 * clen, s));
     }
     return FSI_OK;
   }
@@ -1211,7 +1209,6 @@ class Engine : public EngineBase {
     free_dev(key2);
     free_dev(lu_);
     free_dev(lnp_);
-    free_dev(mu_);
     free_dev(A9);
     free_dev(B9);
     free_dev(lchi_);
@@ -1527,7 +1524,7 @@ class Engine : public EngineBase {
   unsigned long long *key1 = nullptr, *key2 = nullptr;
   std::vector<int> tri_host;
   // adjoint state and work buffers (allocated on first use)
-  cpx<T>*lu_ = nullptr, *lnp_ = nullptr, *mu_ = nullptr, *A9 = nullptr, *B9 = nullptr;
+  cpx<T>*lu_ = nullptr, *lnp_ = nullptr, *A9 = nullptr, *B9 = nullptr;
   T *lchi_ = nullptr, *lus_ = nullptr;
   long long adj_box_cap = 0;
   double* tgrad_ = nullptr;

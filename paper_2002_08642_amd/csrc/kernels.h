@@ -171,27 +171,8 @@ struct MaskArgs {
 // adjoint of one step (dt held fixed)
 // ---------------------------------------------------------------------------
 
-// Spectral part of the reverse step, per compact mode: from the cotangents of
-// (u_hat^{n+1}, N_hat^n) it forms the cotangent of N_hat^n's forward transform
-// (projected and scaled for the transpose of the R2C transform), the update's
-// share of the cotangent of u_hat^n, and the cotangent of N_hat^{n-1}.
-template <typename T>
-struct AdjSpecArgs {
-  cpx<T>* lu;    // [3][cfs] cotangent of u_hat (in: step n+1, out: update share at step n)
-  cpx<T>* lnp;   // [3][cfs] cotangent of the previous nonlinear term (in / out)
-  cpx<T>* mu;    // [3][cfs] out: P(lambda_N) / (m_k N^3)
-  long long cfs;
-  int nrows;     // (2Kz+1)(2Ky+1)
-  int nby, kx1, kxp, Ky, Kz;
-  T kfx, kfy, kfz;
-  T nu;
-  double dt, dtp;
-  int first;
-  double invN3;
-  // pressure seed (FSI coupling): normalized R2C of the cotangent of Pi on the
-  // grid; mu gains i k lpi / |k|^2 (NULL: none)
-  const cpx<T>* lpi;
-};
+// The spectral part of the reverse step (per compact mode) is the column pass
+// COL_ADJ_MU (ColArgs above).
 
 // Fused x pass of the reverse step: C2R of u, omega and lambda_G (9 fields),
 // lambda_u = omega x lambda_G - (chi/eta) lambda_G + (dV/eta) chi g,

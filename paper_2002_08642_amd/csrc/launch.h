@@ -67,8 +67,6 @@ template <typename T>
 hipError_t launch_pbox(int embed, const BoxArgs<T>& a, hipStream_t s);
 
 template <typename T>
-hipError_t launch_adj_spectral(const AdjSpecArgs<T>& a, hipStream_t s);
-template <typename T>
 hipError_t launch_xadj(const XAdjArgs<T>& a, int grid, hipStream_t s);
 template <typename T>
 int xadj_supported(int n);
