@@ -267,4 +267,85 @@ __device__ __forceinline__ void col_fft(cpx<T>* buf, const FftPlan& p, const cpx
   }
 }
 
+// 512-point transforms of the W columns of a workgroup (the three radix-8
+// stages of col_fft, same arithmetic in the same order) with the first and the
+// last stage on registers.  Thread t carries columns cs = 2 (t % (W/2)) and
+// cs + 1 (arrays v0, v1) at index js = t / (W/2) in [0, 64) (NT = 32 W
+// threads cover every column and index once): on entry vs[r] = x[js + 64 r],
+// on return vs[r] = X[js + 64 r].  The span-1 stage needs exactly the inputs
+// js + 64 r and the span-64 stage produces exactly those outputs, so only the
+// middle stage goes through LDS: two buffer writes and two reads instead of
+// four each, and three barriers instead of eight.  The two columns of a thread
+// are adjacent in LDS (one ds_write2 / ds_read2 moves both) and share their
+// twiddles.  Row R of buf lives at R ^ ((R >> 3) & 1): the rows 8 js + r that
+// the lanes of a wave write in the first stage then fill both halves of the
+// LDS banks instead of one (every other access touches runs of consecutive
+// rows either way).  Begins with a barrier, so buf may still be being read by
+// a previous transform.
+template <typename T, int W, bool INV>
+__device__ __forceinline__ void fft512_reg(cpx<T> (&v0)[8], cpx<T> (&v1)[8], cpx<T>* buf, const cpx<T>* tw) {
+  constexpr int SGN = INV ? 1 : -1;
+  // LDS addresses from an opaque thread id: computed per stage, not hoisted
+  // and kept live across the kernel
+  auto slot = [&](int& cs, int& js) __attribute__((always_inline)) {
+    const int t = opaque((int)threadIdx.x);
+    cs = 2 * (t % (W / 2));
+    js = t / (W / 2);
+  };
+  auto twiddle = [&](cpx<T>(&x)[8], int step) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      cpx<T> w = tw[step * r];
+      if (INV) w.im = -w.im;
+      x[r] = cmul(x[r], w);
+    }
+  };
+  auto at = [&](int row, int cs) __attribute__((always_inline)) { return buf + (row ^ ((row >> 3) & 1)) * W + cs; };
+  int cs, js;
+  Bfly<T, 8, SGN>::run(v0);
+  Bfly<T, 8, SGN>::run(v1);
+  __syncthreads();
+  slot(cs, js);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    cpx<T>* p = at(js * 8 + r, cs);
+    p[0] = v0[r];
+    p[1] = v1[r];
+  }
+  __syncthreads();
+  slot(cs, js);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const cpx<T>* p = at(js + 64 * r, cs);
+    v0[r] = p[0];
+    v1[r] = p[1];
+  }
+  __syncthreads();
+  slot(cs, js);
+  const int jm = js & 7;
+  twiddle(v0, 8 * jm);
+  twiddle(v1, 8 * jm);
+  Bfly<T, 8, SGN>::run(v0);
+  Bfly<T, 8, SGN>::run(v1);
+  const int d0 = (js - jm) * 8 + jm;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    cpx<T>* p = at(d0 + 8 * r, cs);
+    p[0] = v0[r];
+    p[1] = v1[r];
+  }
+  __syncthreads();
+  slot(cs, js);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const cpx<T>* p = at(js + 64 * r, cs);
+    v0[r] = p[0];
+    v1[r] = p[1];
+  }
+  twiddle(v0, js);
+  twiddle(v1, js);
+  Bfly<T, 8, SGN>::run(v0);
+  Bfly<T, 8, SGN>::run(v1);
+}
+
 }  // namespace fsi

@@ -407,21 +407,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     static_for<0, 3>([&](auto oc) { mstep(oc); });
   } else if constexpr (MODE == COL_INV_WZ && PAIR) {
     // COL_INV_WZ below with two columns per lane (same outputs, order and loads)
-    constexpr int WP = W / 2, RS2 = NT / WP, ME2 = MAXE / 2;
-    constexpr int MO2 = (2 * ((N - 1) / 3) + 1 + RS2 - 1) / RS2;
-    cpx2f RA[MO2], RB[MO2];
-    auto load_into = [&](int lq, cpx2f(&R)[MO2]) {
+    // on the lane's own rows rp + 64 m (m = 0..7) of fft512_reg:
+    // the band rows (K = 170) are m = 0, 1, 6, 7, m = 2 when rp <= 42 and m = 5
+    // when rp >= 22 (band slot e = 0..5 for m = 0, 1, 2, 5, 6, 7), band index
+    // rp + 64 m (m <= 2) or rp + 64 m - 171 (m >= 5)
+    constexpr int WP = W / 2;
+    cpx2f RA[6], RB[6];
+    auto load_into = [&](int lq, cpx2f(&R)[6]) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
       const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
-      for (int k = 0; k < MO2; ++k) {
-        const int i = rq + k * RS2;
-        R[k] = ld_stream2(in + (long long)(i < nb ? i : 0) * a.ld);
+      for (int e = 0; e < 6; ++e) {
+        const int m = e < 3 ? e : e + 2;
+        // rows out of the band are loaded from row 0 (one line for the whole
+        // wave) and replaced by zero
+        const bool inb = (m == 2) ? rq <= 42 : (m == 5) ? rq >= 22 : true;
+        R[e] = ld_stream2(in + (long long)(inb ? (m <= 2 ? rq + 64 * m : rq + 64 * m - 171) : 0) * a.ld);
       }
     };
-    cpx<float>* bf = reinterpret_cast<cpx<float>*>(buf);
-    auto step = [&](auto oc) {
+    auto step = [&](auto oc) __attribute__((always_inline)) {
       constexpr int o = decltype(oc)::value;
       constexpr int fo = (o == 2) ? 5 : (o > 2) ? o - 1 : o;
       constexpr int src = (o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0;
@@ -431,30 +436,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
       const bool ok0 = c < a.C && (c % a.kxp) < a.kx1, ok1 = c + 1 < a.C && ((c + 1) % a.kxp) < a.kx1;
       const float kx0 = (float)a.kfx * (float)(c % a.kxp), kx1 = kx0 + (float)a.kfx;
-      const cpx2f zero{mk<float>(0, 0), mk<float>(0, 0)};
+      const bool in2 = rp <= 42, in5 = rp >= 22;
+      cpx<float> v0[8], v1[8];
 #pragma unroll
-      for (int k = 0; k < ME2; ++k) {
-        const int r = rp + k * RS2;
-        if (r > K && r < n - K) st_lds2(bf + r * W + 2 * cp, zero);
+      for (int m = 0; m < 8; ++m) {
+        v0[m] = mk<float>(0, 0);
+        v1[m] = mk<float>(0, 0);
       }
-#pragma unroll
-      for (int k = 0; k < MO2; ++k) {
-        const int i = rp + k * RS2;
-        if (i < nb) {
-          cpx2f val = (src == 1) ? RB[k] : RA[k];
-          if constexpr (src == 2) {  // wz = i (kx uy - ky ux)
-            const float krow = (float)a.kfy * (float)band_mode(i, K);
-            const cpx<float> t0 = scl(RB[k].a, kx0) - scl(RA[k].a, krow);
-            const cpx<float> t1 = scl(RB[k].b, kx1) - scl(RA[k].b, krow);
-            val = cpx2f{mk<float>(-t0.im, t0.re), mk<float>(-t1.im, t1.re)};
-          }
-          if (!ok0) val.a = mk<float>(0, 0);
-          if (!ok1) val.b = mk<float>(0, 0);
-          st_lds2(bf + band_to_row(i, K, n) * W + 2 * cp, val);
+      static_for<0, 6>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value, m = e < 3 ? e : e + 2;
+        cpx2f val = (src == 1) ? RB[e] : RA[e];
+        if constexpr (src == 2) {  // wz = i (kx uy - ky ux)
+          const int i = m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
+          const float krow = (float)a.kfy * (float)band_mode(i, K);
+          const cpx<float> t0 = scl(RB[e].a, kx0) - scl(RA[e].a, krow);
+          const cpx<float> t1 = scl(RB[e].b, kx1) - scl(RA[e].b, krow);
+          val = cpx2f{mk<float>(-t0.im, t0.re), mk<float>(-t1.im, t1.re)};
         }
-      }
-      __syncthreads();
-      if constexpr (lq >= 0) {
+        const bool inb = (m == 2) ? in2 : (m == 5) ? in5 : true;
+        // component selects (a select of the whole pair keeps the array in memory)
+        const bool k0 = ok0 && inb, k1 = ok1 && inb;
+        v0[m] = mk<float>(k0 ? val.a.re : 0.f, k0 ? val.a.im : 0.f);
+        v1[m] = mk<float>(k1 ? val.b.re : 0.f, k1 ? val.b.im : 0.f);
+      });
+      if constexpr (lq >= 0) {  // in flight during the transform
         if constexpr (to_b) {
           asm volatile("" ::: "memory");  // keeps the two load sites apart
           load_into(lq, RB);
@@ -462,16 +467,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
           load_into(lq, RA);
         }
       }
-      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+      fft512_reg<float, W, true>(v0, v1, reinterpret_cast<cpx<float>*>(buf), reinterpret_cast<const cpx<float>*>(tws));
       cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs + ob;
-      cpx2f ov[ME2];  // LDS reads first, then the stores (columns out of the band hold zeros)
+      if (c < a.C) {  // columns out of the band hold zeros
 #pragma unroll
-      for (int k = 0; k < ME2; ++k) ov[k] = ld_lds2(bf + (rp + k * RS2) * W + 2 * cp);
-      if (c < a.C) {
-#pragma unroll
-        for (int k = 0; k < ME2; ++k) st_stream2(out + (long long)(rp + k * RS2) * a.ld + c, ov[k]);
+        for (int m = 0; m < 8; ++m) st_stream2(out + (long long)(rp + 64 * m) * a.ld + c, cpx2f{v0[m], v1[m]});
       }
-      __syncthreads();
     };
     load_into(0, RA);
     static_for<0, 6>([&](auto oc) { step(oc); });
@@ -569,43 +570,40 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     step(std::integral_constant<int, 4>{});
     if constexpr (!Z5) step(std::integral_constant<int, 5>{});
   } else if constexpr (MODE == COL_FWD_PLAIN && PAIR) {
-    // y forward (P4 and the helper transforms) with two columns per lane
-    constexpr int WP = W / 2, RS2 = NT / WP, ME2 = MAXE / 2;
-    constexpr int MO2 = (2 * ((N - 1) / 3) + 1 + RS2 - 1) / RS2;
+    // y forward (P4 and the helper transforms) with two columns per lane, on the
+    // lane's own rows rp + 64 m of fft512_reg; band rows out as in
+    // COL_INV_WZ above
+    constexpr int WP = W / 2;
     const int nfield = a.nf;
-    cpx2f tmp[ME2];
-    cpx<float>* bf = reinterpret_cast<cpx<float>*>(buf);
+    cpx2f tmp[8];
     auto load_field = [&](int f) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
       const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
-      for (int k = 0; k < ME2; ++k) tmp[k] = ld_stream2(in + (long long)(rq + k * RS2) * a.ld);
+      for (int m = 0; m < 8; ++m) tmp[m] = ld_stream2(in + (long long)(rq + 64 * m) * a.ld);
     };
     auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
+      cpx<float> v0[8], v1[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        v0[m] = tmp[m].a;
+        v1[m] = tmp[m].b;
+      }
+      if (prefetch) load_field(f + 1);  // in flight during the transform
+      fft512_reg<float, W, false>(v0, v1, reinterpret_cast<cpx<float>*>(buf), reinterpret_cast<const cpx<float>*>(tws));
       const int tid = opaque((int)threadIdx.x);
       const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
-#pragma unroll
-      for (int k = 0; k < ME2; ++k) st_lds2(bf + (rp + k * RS2) * W + 2 * cp, tmp[k]);
-      __syncthreads();
-      if (prefetch) load_field(f + 1);
-      col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + f * a.out_fs + ob;
       const float sc = (float)a.scale;
-      cpx2f ov[MO2];  // LDS reads first, then the stores
-#pragma unroll
-      for (int k = 0; k < MO2; ++k) {
-        const int i = rp + k * RS2;
-        ov[k] = ld_lds2(bf + band_to_row(i < nb ? i : 0, K, n) * W + 2 * cp);
-      }
       if (c < a.C) {
 #pragma unroll
-        for (int k = 0; k < MO2; ++k) {
-          const int i = rp + k * RS2;
-          if (i < nb) st_stream2(out + (long long)i * a.ld + c, cpx2f{scl(ov[k].a, sc), scl(ov[k].b, sc)});
+        for (int m = 0; m < 8; ++m) {
+          if (m == 3 || m == 4 || (m == 2 && rp > 42) || (m == 5 && rp < 22)) continue;
+          const int i = m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
+          st_stream2(out + (long long)i * a.ld + c, cpx2f{scl(v0[m], sc), scl(v1[m], sc)});
         }
       }
-      __syncthreads();
     };
     load_field(0);
     if (nfield == 3) {
