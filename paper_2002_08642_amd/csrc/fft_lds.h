@@ -300,26 +300,36 @@ __device__ __forceinline__ void fft512_reg(cpx<T> (&v0)[8], cpx<T> (&v1)[8], cpx
       x[r] = cmul(x[r], w);
     }
   };
-  auto at = [&](int row, int cs) __attribute__((always_inline)) { return buf + (row ^ ((row >> 3) & 1)) * W + cs; };
   int cs, js;
   Bfly<T, 8, SGN>::run(v0);
   Bfly<T, 8, SGN>::run(v1);
   __syncthreads();
   slot(cs, js);
+  {
+    // rows 8 js + r: stored at 8 js + (r ^ b), b = js & 1 (bit 3 of the row),
+    // from one base per parity of r and immediate offsets
+    const int b = js & 1;
+    cpx<T>* pe = buf + (8 * js + b) * W + cs;
+    cpx<T>* po = buf + (8 * js + 1 - b) * W + cs;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    cpx<T>* p = at(js * 8 + r, cs);
-    p[0] = v0[r];
-    p[1] = v1[r];
+    for (int r = 0; r < 8; ++r) {
+      cpx<T>* p = (r & 1) ? po + (r - 1) * W : pe + r * W;
+      p[0] = v0[r];
+      p[1] = v1[r];
+    }
   }
+  // rows js + 64 r: bit 3 is that of js
+  auto read_cols = [&]() __attribute__((always_inline)) {
+    slot(cs, js);
+    const cpx<T>* p = buf + (js ^ ((js >> 3) & 1)) * W + cs;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      v0[r] = p[64 * r * W];
+      v1[r] = p[64 * r * W + 1];
+    }
+  };
   __syncthreads();
-  slot(cs, js);
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const cpx<T>* p = at(js + 64 * r, cs);
-    v0[r] = p[0];
-    v1[r] = p[1];
-  }
+  read_cols();
   __syncthreads();
   slot(cs, js);
   const int jm = js & 7;
@@ -327,21 +337,20 @@ __device__ __forceinline__ void fft512_reg(cpx<T> (&v0)[8], cpx<T> (&v1)[8], cpx
   twiddle(v1, 8 * jm);
   Bfly<T, 8, SGN>::run(v0);
   Bfly<T, 8, SGN>::run(v1);
-  const int d0 = (js - jm) * 8 + jm;
+  {
+    // rows d0 + 8 r, d0 = 64 (js >> 3) + jm (bit 3 clear): bit 3 of the row is r & 1
+    const int d0 = (js - jm) * 8 + jm;
+    cpx<T>* pe = buf + d0 * W + cs;
+    cpx<T>* po = buf + (d0 ^ 1) * W + cs;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    cpx<T>* p = at(d0 + 8 * r, cs);
-    p[0] = v0[r];
-    p[1] = v1[r];
+    for (int r = 0; r < 8; ++r) {
+      cpx<T>* p = ((r & 1) ? po : pe) + 8 * r * W;
+      p[0] = v0[r];
+      p[1] = v1[r];
+    }
   }
   __syncthreads();
-  slot(cs, js);
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const cpx<T>* p = at(js + 64 * r, cs);
-    v0[r] = p[0];
-    v1[r] = p[1];
-  }
+  read_cols();
   twiddle(v0, js);
   twiddle(v1, js);
   Bfly<T, 8, SGN>::run(v0);

@@ -416,14 +416,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     auto load_into = [&](int lq, cpx2f(&R)[6]) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
-      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
+      // uniform base and 32-bit element offsets within the slice (scalar-base
+      // addressing; a 512-row slice of a y pass is far below 4 GB)
+      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs + ib;
+      const int cc = cq < a.C ? cq : 0;
 #pragma unroll
       for (int e = 0; e < 6; ++e) {
         const int m = e < 3 ? e : e + 2;
         // rows out of the band are loaded from row 0 (one line for the whole
         // wave) and replaced by zero
         const bool inb = (m == 2) ? rq <= 42 : (m == 5) ? rq >= 22 : true;
-        R[e] = ld_stream2(in + (long long)(inb ? (m <= 2 ? rq + 64 * m : rq + 64 * m - 171) : 0) * a.ld);
+        R[e] = ld_stream2(at_u32(in, (inb ? (m <= 2 ? rq + 64 * m : rq + 64 * m - 171) : 0) * a.ld + cc));
       }
     };
     auto step = [&](auto oc) __attribute__((always_inline)) {
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs + ob;
       if (c < a.C) {  // columns out of the band hold zeros
 #pragma unroll
-        for (int m = 0; m < 8; ++m) st_stream2(out + (long long)(rp + 64 * m) * a.ld + c, cpx2f{v0[m], v1[m]});
+        for (int m = 0; m < 8; ++m) st_stream2(at_u32(out, (rp + 64 * m) * a.ld + c), cpx2f{v0[m], v1[m]});
       }
     };
     load_into(0, RA);
@@ -579,9 +582,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     auto load_field = [&](int f) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
-      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs + ib + (cq < a.C ? cq : 0);
+      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs + ib;  // as in COL_INV_WZ
+      const int cc = cq < a.C ? cq : 0;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) tmp[m] = ld_stream2(in + (long long)(rq + 64 * m) * a.ld);
+      for (int m = 0; m < 8; ++m) tmp[m] = ld_stream2(at_u32(in, (rq + 64 * m) * a.ld + cc));
     };
     auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
       cpx<float> v0[8], v1[8];
@@ -601,7 +605,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         for (int m = 0; m < 8; ++m) {
           if (m == 3 || m == 4 || (m == 2 && rp > 42) || (m == 5 && rp < 22)) continue;
           const int i = m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
-          st_stream2(out + (long long)i * a.ld + c, cpx2f{scl(v0[m], sc), scl(v1[m], sc)});
+          st_stream2(at_u32(out, i * a.ld + c), cpx2f{scl(v0[m], sc), scl(v1[m], sc)});
         }
       }
     };
