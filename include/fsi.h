@@ -126,8 +126,8 @@ fsi_status fsi_set_spectrum(fsi_ctx* ctx, const double* uhat_host);
  * T enters the nonlinear term before the 2/3 truncation and the projection.
  * c_sp <= 0 (or all profiles NULL) switches the sponge off (the default).
  * Copied; FSI_EINVAL for a non-finite c_sp or a negative or non-finite
- * profile value.  While it is on, fsi_step_adjoint returns FSI_ESTATE (the
- * adjoint does not include the sponge). */
+ * profile value.  fsi_step_adjoint reverses the term with the sponge as set
+ * when it is called (the sponge of the taped steps must not have changed). */
 fsi_status fsi_set_sponge(fsi_ctx* ctx, double c_sp, const double* gx, const double* gy,
                           const double* gz);
 
@@ -252,7 +252,8 @@ fsi_status fsi_step_record(fsi_ctx* ctx, double dt, int32_t tape_slot);
  * objective with respect to the force F of that step. On return the cotangent
  * state is (dJ/du_hat^n, dJ/dN_hat^{n-1}) and, if non-NULL, dJdx[nv][3] and
  * dJdv[nv][3] hold dJ/d(vertex positions, velocities) of that step's mesh
- * through the mask and the solid velocity. Synchronizes. */
+ * through the mask and the solid velocity.  With the vorticity sponge on
+ * (fsi_set_sponge) its term is reversed too. Synchronizes. */
 fsi_status fsi_step_adjoint(fsi_ctx* ctx, int32_t tape_slot, double dt, double dt_prev, int32_t first,
                             const double dJdF[3], double* dJdx, double* dJdv);
 

@@ -934,14 +934,77 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // Sponge share of the reverse step: S = chi_sp omega, so lambda_omega gains
+  // chi_sp C2R(nu) (nu from COL_ADJ_MU), which reaches lambda_u through the
+  // transposed curl as the nonlinear term's lambda_omega does: z and y
+  // inverse of nu, x C2R, mask, x R2C, y forward, z forward accumulating
+  // m_k i k x (.) into lambda_u.  A9, B9 and phys are free at this point.
+  fsi_status sponge_adjoint() {
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = spadj_;
+      a.in_fs = clen;
+      a.out = A9;
+      a.out_fs = Alen;
+      a.nf = 3;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, 1, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = A9;
+      a.in_fs = Alen;
+      a.in_bs = C1;
+      a.out = B9;
+      a.out_fs = Blen;
+      a.out_bs = (long long)ny * kxp;
+      a.nf = 3;
+      FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
+    }
+    {
+      XArgs<T> a = x_base();
+      a.spec = B9;
+      a.sfs = Blen;
+      a.phys = phys;
+      a.pfs = npts;
+      FSI_HIP(launch_xplain<T>(X_C2R, 3, a, npart, s));
+      SpongeArgs<T> m;
+      m.phys = phys;
+      m.npts = npts;
+      m.nx = nx;
+      m.ny = ny;
+      m.nz = nz;
+      m.g = spg_;
+      FSI_HIP(launch_sponge_mask<T>(m, s));
+      FSI_HIP(launch_xplain<T>(X_R2C, 3, a, npart, s));
+    }
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = B9;
+      a.in_fs = Blen;
+      a.in_bs = (long long)ny * kxp;
+      a.out = A9;
+      a.out_fs = Alen;
+      a.out_bs = C1;
+      a.nf = 3;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = A9;
+      a.in_fs = Alen;
+      a.out = lu_;
+      a.cfs = clen;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_ACC_CURL, a, 1, s));
+    }
+    return FSI_OK;
+  }
+
   fsi_status step_adjoint(int slot, double dt, double dtp, int first, const double dJdF[3], double* dJdx,
                           double* dJdv) override {
     if (slot < 0 || slot >= (int)slots.size() || !slots[slot].used) {
       err = "tape slot is empty";
-      return FSI_ESTATE;
-    }
-    if (sponge_on) {
-      err = "the adjoint step does not include the sponge term";
       return FSI_ESTATE;
     }
     if (!(dt > 0) || (!first && !(dtp > 0))) {
@@ -1004,6 +1067,13 @@ class Engine : public EngineBase {
       m.first = first ? 1 : 0;
       m.invN3 = 1.0 / (double)npts;
       m.lpi = seed ? piadj_ : nullptr;
+      if (sponge_on) {
+        // every band row of a valid column is written (padding columns are
+        // zeroed by the inverse pass that reads nu)
+        if (!spadj_) FSI_TRY(alloc(&spadj_, 3 * clen));
+        m.spadj = spadj_;
+        m.csp_inv = (T)(1.0 / csp);
+      }
       m.out = A9 + 6 * Alen;
       m.out_fs = Alen;
       FSI_HIP(launch_col<T>(COL_ADJ_MU, m, 1, s));
@@ -1086,6 +1156,7 @@ class Engine : public EngineBase {
       a.in = A9 + 3 * Alen;
       FSI_HIP(launch_col<T>(COL_FWD_ACC_CURL, a, 1, s));
     }
+    if (sponge_on) FSI_TRY(sponge_adjoint());
     if (dJdx) memset(dJdx, 0, sizeof(double) * 3 * wing_nv);
     if (dJdv) memset(dJdv, 0, sizeof(double) * 3 * wing_nv);
     if (wing) {
@@ -1202,6 +1273,7 @@ class Engine : public EngineBase {
     free_dev(cwork);
     free_dev(spg_);
     free_dev(tsp_);
+    free_dev(spadj_);
     free_dev(dx_);
     free_dev(dv_);
     free_dev(dtri_);
@@ -1505,6 +1577,7 @@ class Engine : public EngineBase {
   double csp = 0.0;
   T* spg_ = nullptr;        // sponge profiles gx, gy, gz
   cpx<T>* tsp_ = nullptr;   // [3][clen] sponge term of the step
+  cpx<T>* spadj_ = nullptr; // [3][clen] sponge cotangent nu of the reverse step
   T* phys = nullptr;
   double* partials = nullptr;
   DevScalars* sc = nullptr;

@@ -31,7 +31,8 @@ enum ColMode {
   COL_FWD_UPDATE_Z = 9,  // COL_FWD_UPDATE, then COL_INV_CURL5 of the new velocity into zout
   COL_FWD_SPONGE = 10,   // sponge term -(1/C_sp) i k x forward(in[0..2]) / |k|^2 into out (compact)
   COL_ADJ_MU = 11        // adjoint: update/projection transpose on (uh = lambda_u, nh = lambda_N)
-                         // in place, then z inverse of mu = P(lambda_N)/(m_k N^3) into out (3 fields)
+                         // in place, then z inverse of mu = P(lambda_N)/(m_k N^3) into out (3 fields);
+                         // with spadj also the sponge cotangent nu of mu (compact)
 };
 enum XMode { X_FUSED = 0, X_C2R = 1, X_R2C = 2 };
 
@@ -80,6 +81,7 @@ struct ColArgs {
   double adt, adtp;      // dt of the reversed step and the one before
   double invN3;          // 1 / (nx ny nz)
   const cpx<T>* lpi;     // pressure seed (normalized R2C of the cotangent of Pi), NULL = none
+  cpx<T>* spadj;         // sponge on: nu = -(1/C_sp) i k x mu / |k|^2 (compact; csp_inv), NULL = none
 };
 
 // Sponge mask on the physical grid: phys[f] *= max(gx[x], gy[y], gz[z]), f < 3.

@@ -367,6 +367,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
           }
 #pragma unroll
           for (int q = 0; q < 3; ++q) M[q][k] = scl(ln[q], sc) + extra[q];
+          if (a.spadj) {
+            // the sponge term T_hat = A S_hat, A = -(1/C_sp) (i k x) / |k|^2, enters
+            // like N before the projection; A is Hermitian, so the cotangent
+            // of S_hat over m_k N^3 is A mu
+            const T f = k2 > (T)0 ? -a.csp_inv / k2 : (T)0;
+            const cpx<T> t0 = scl(M[2][k], ky) - scl(M[1][k], kz);
+            const cpx<T> t1 = scl(M[0][k], kz) - scl(M[2][k], kx);
+            const cpx<T> t2 = scl(M[1][k], kx) - scl(M[0][k], ky);
+            a.spadj[idx] = scl(mk<T>(-t0.im, t0.re), f);
+            a.spadj[a.cfs + idx] = scl(mk<T>(-t1.im, t1.re), f);
+            a.spadj[2 * a.cfs + idx] = scl(mk<T>(-t2.im, t2.re), f);
+          }
         }
       }
     }
@@ -1662,6 +1674,10 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   // the width that holds 512-point columns gets the compile-time 512 transform
   constexpr bool k512 = (W * 512 == NT * MAXE);
   const bool use512 = k512 && a.n == 512 && a.K == 170;
+  // the paired 512-point passes address a slice with 32-bit element offsets
+  if (use512 && sizeof(T) == 4 && W == 16 && (mode == COL_FWD_PLAIN || mode == COL_INV_WZ) &&
+      (long long)a.n * a.ld >= (1LL << 29))
+    return hipErrorInvalidValue;
 #define FSI_COL_CASE(M)                                                                \
   case M:                                                                              \
     if (use512) {                                                                      \

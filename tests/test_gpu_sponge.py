@@ -1,6 +1,6 @@
 """GPU parity of the vorticity sponge term (Sec. 4.1, sponge term of the
 penalized equations; sign and mask readings in oracle/sponge.py) against the
-FP64 oracle.
+FP64 oracle, and the adjoint of the step with the sponge on.
 
 The sponge layers are cosine tapers at the x faces and at the top z face, a
 tilted plate sits in the middle, and the field is the random k^-5/3 field.
@@ -15,6 +15,7 @@ import pytest
 from oracle import ns as ons
 from paper_2002_08642_amd import fsi
 from tests.helpers import rel_max
+from tests.test_gpu_adjoint import run_two_steps
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -120,19 +121,75 @@ def test_uniform_sponge_recurrence(prec):
     assert rel_max(s.velocity(), a * u0) < (1e-12 if prec == fsi.PREC_FP64 else 2e-6)
 
 
-def test_sponge_switches_off_and_guards_the_adjoint():
+def test_sponge_switches_off():
     n, L = CASES[0]
     a = fsi.Solver(n, L, 0.01, 0.05, precision=fsi.PREC_FP64)
     b = fsi.Solver(n, L, 0.01, 0.05, precision=fsi.PREC_FP64)
     for s in (a, b):
         s.set_velocity(synth.random_solenoidal(n, L, seed=3))
     a.set_sponge(0.1, gy=np.ones(n[1]))
-    a.save(0)
-    with pytest.raises(fsi.FsiError):
-        a.step_adjoint(0, 1e-3, 1e-3, 1, np.zeros(3))
     a.set_sponge(0.0)
     for s in (a, b):
         s.step(2e-3)
     assert np.array_equal(a.spectrum(), b.spectrum())
     with pytest.raises(fsi.FsiError):
         a.set_sponge(0.1, gx=-np.ones(n[0]))
+
+
+# Adjoint of the step with the sponge on: dot-product test (two steps, an
+# integrating-factor Euler step then an AB2 step) against central differences
+# of the GPU forward map, for perturbations of the initial spectrum, of the
+# mesh vertex positions and of their velocities, with force seeds and random
+# cotangents of the final state.  (32, 24, 20): the LDS x passes; (512, 16, 12):
+# the register-resident adjoint x pass next to the sponge's LDS x transforms.
+ADJ_CASES = [((32, 24, 20), (2.0, 1.5, 1.25), (0.05, 0.03, 0.3, 0.2)),
+             ((512, 16, 12), (8.0, 0.25, 0.1875), (0.03, 0.016, 0.3, 0.025))]
+
+
+def sponge_adjoint_case(n, L, geom, prec, c_sp=0.08, part="all"):
+    tw, h, pa, pb = geom
+    s = fsi.Solver(n, L, 0.02, 0.05, tw, h, fsi.PROFILE_COS, prec)
+    s.set_sponge(c_sp, gx=face_taper(n[0], n[0] // 5), gz=top_taper(n[2], max(3, n[2] // 6)))
+    rng = np.random.default_rng(23)
+    u0 = synth.random_solenoidal_compact(n, L, seed=8)
+    du = synth.random_solenoidal_compact(n, L, seed=9) if part in ("u", "all") else 0 * u0
+    centre = (0.5 * L[0] + 0.013, 0.5 * L[1] + 0.021, 0.5 * L[2] - 0.007)
+    ua = np.array([1.0, 0.05, 0.02]) / np.linalg.norm([1.0, 0.05, 0.02])
+    va = np.array([0.0, 0.3, 1.0]) / np.linalg.norm([0.0, 0.3, 1.0])
+    x0, tri = synth.flat_rectangle(centre, ua, va, pa, pb, 6, 4)
+    x0 = x0 + 0.002 * rng.standard_normal(x0.shape)
+    v0 = rng.standard_normal(x0.shape)
+    dx = 0.005 * rng.standard_normal(x0.shape) if part in ("x", "all") else 0 * x0
+    dv = rng.standard_normal(x0.shape) if part in ("v", "all") else 0 * x0
+    g = [rng.standard_normal(3), rng.standard_normal(3)]
+    lam_u = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    lam_n = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    return run_two_steps(s, u0, x0, v0, tri, (0.01, 0.013), g, lam_u, lam_n, du, dx, dv)
+
+
+@pytest.mark.parametrize("part", ["u", "all"])
+@pytest.mark.parametrize("n,L,geom", ADJ_CASES, ids=["32x24x20", "512x16x12"])
+def test_sponge_adjoint_dot_product(n, L, geom, part):
+    print("sponge adjoint", n, part, flush=True)
+    adj, fd, _ = sponge_adjoint_case(n, L, geom, fsi.PREC_FP64, part=part)
+    print("sponge adjoint %s %s: adjoint %.12e fd %.12e" % (n, part, adj, fd), flush=True)
+    assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
+
+
+def test_sponge_adjoint_changes_the_gradient():
+    """The dot-product test would pass with the sponge left out of both the
+    forward and the adjoint: the sponge must change the initial-state cotangent
+    by far more than the tolerance."""
+    n, L, geom = ADJ_CASES[0]
+    _, _, (lu_on, _, _, _) = sponge_adjoint_case(n, L, geom, fsi.PREC_FP64, part="u")
+    _, _, (lu_off, _, _, _) = sponge_adjoint_case(n, L, geom, fsi.PREC_FP64, c_sp=0.0, part="u")
+    assert rel_max(lu_on, lu_off) > 1e-3
+
+
+def test_sponge_adjoint_fp32_matches_fp64():
+    n, L, geom = ADJ_CASES[1]
+    _, _, (lu64, ln64, gx64, gv64) = sponge_adjoint_case(n, L, geom, fsi.PREC_FP64, part="u")
+    _, _, (lu32, ln32, gx32, gv32) = sponge_adjoint_case(n, L, geom, fsi.PREC_FP32, part="u")
+    e = [rel_max(lu32, lu64), rel_max(ln32, ln64), rel_max(gx32, gx64), rel_max(gv32, gv64)]
+    print("sponge adjoint FP32 vs FP64: %s" % e, flush=True)
+    assert max(e) < 1e-3
