@@ -267,6 +267,71 @@ __device__ __forceinline__ void col_fft(cpx<T>* buf, const FftPlan& p, const cpx
   }
 }
 
+// fft512_reg with one column per thread and slots at indices j and j + 32
+// (see there); the same stages and swizzled LDS rows.
+template <typename T, int W, bool INV>
+__device__ __forceinline__ void fft512_reg_onecol(cpx<T> (&v0)[8], cpx<T> (&v1)[8], cpx<T>* buf, const cpx<T>* tw) {
+  constexpr int SGN = INV ? 1 : -1;
+  auto twiddle = [&](cpx<T>(&x)[8], int step) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      cpx<T> w = tw[step * r];
+      if (INV) w.im = -w.im;
+      x[r] = cmul(x[r], w);
+    }
+  };
+  // rows 8 js + r at 8 js + (r ^ (js & 1)); rows js + 64 r at (js ^ bit 3 of js) + 64 r;
+  // rows d0 + 8 r (bit 3 of d0 clear) at d0 + 8 r ^ (r & 1)
+  auto put1 = [&](cpx<T>(&x)[8], int s) __attribute__((always_inline)) {
+    const int t = opaque((int)threadIdx.x);
+    const int cs = t % W, js = t / W + 32 * s, b = js & 1;
+    cpx<T>* pe = buf + (8 * js + b) * W + cs;
+    cpx<T>* po = buf + (8 * js + 1 - b) * W + cs;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) *((r & 1) ? po + (r - 1) * W : pe + r * W) = x[r];
+  };
+  auto get = [&](cpx<T>(&x)[8], int s) __attribute__((always_inline)) {
+    const int t = opaque((int)threadIdx.x);
+    const int cs = t % W, js = t / W + 32 * s;
+    const cpx<T>* p = buf + (js ^ ((js >> 3) & 1)) * W + cs;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = p[64 * r * W];
+  };
+  auto mid = [&](cpx<T>(&x)[8], int s) __attribute__((always_inline)) {
+    const int t = opaque((int)threadIdx.x);
+    const int cs = t % W, js = t / W + 32 * s, jm = js & 7;
+    twiddle(x, 8 * jm);
+    Bfly<T, 8, SGN>::run(x);
+    const int d0 = (js - jm) * 8 + jm;
+    cpx<T>* pe = buf + d0 * W + cs;
+    cpx<T>* po = buf + (d0 ^ 1) * W + cs;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) *(((r & 1) ? po : pe) + 8 * r * W) = x[r];
+  };
+  auto last = [&](cpx<T>(&x)[8], int s) __attribute__((always_inline)) {
+    get(x, s);
+    const int t = opaque((int)threadIdx.x);
+    twiddle(x, t / W + 32 * s);
+    Bfly<T, 8, SGN>::run(x);
+  };
+  Bfly<T, 8, SGN>::run(v0);
+  Bfly<T, 8, SGN>::run(v1);
+  __syncthreads();
+  put1(v0, 0);
+  put1(v1, 1);
+  __syncthreads();
+  get(v0, 0);
+  get(v1, 1);
+  __syncthreads();
+  mid(v0, 0);
+  mid(v1, 1);
+  __syncthreads();
+  last(v0, 0);
+  // one slot at a time: both at once would hold 14 twiddles and 16 values
+  __builtin_amdgcn_sched_barrier(0);
+  last(v1, 1);
+}
+
 // 512-point transforms of the W columns of a workgroup (the three radix-8
 // stages of col_fft, same arithmetic in the same order) with the first and the
 // last stage on registers.  Thread t carries columns cs = 2 (t % (W/2)) and
@@ -282,9 +347,17 @@ __device__ __forceinline__ void col_fft(cpx<T>* buf, const FftPlan& p, const cpx
 // LDS banks instead of one (every other access touches runs of consecutive
 // rows either way).  Begins with a barrier, so buf may still be being read by
 // a previous transform.
-template <typename T, int W, bool INV>
+//
+// ONECOL = true: the two slots of a thread are one column t % W at the
+// indices t / W and t / W + 32 (NT = 32 W threads), i.e. the thread's rows
+// t / W + 32 m with m = s + 2 r for slot s; LDS accesses one column at a time.
+template <typename T, int W, bool INV, bool ONECOL = false>
 __device__ __forceinline__ void fft512_reg(cpx<T> (&v0)[8], cpx<T> (&v1)[8], cpx<T>* buf, const cpx<T>* tw) {
   constexpr int SGN = INV ? 1 : -1;
+  if constexpr (ONECOL) {
+    fft512_reg_onecol<T, W, INV>(v0, v1, buf, tw);
+    return;
+  }
   // LDS addresses from an opaque thread id: computed per stage, not hoisted
   // and kept live across the kernel
   auto slot = [&](int& cs, int& js) __attribute__((always_inline)) {

@@ -73,6 +73,10 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// m of the e-th of the twelve rows r0 + 32 m (m = 0..5, 10..15) of a thread
+// that can lie in the 2/3 band of a 512-point column
+constexpr int band_slot512(int e) { return e < 6 ? e : e + 4; }
+
 // a s - b t with both products rounded (no fused multiply-add): the stand-alone
 // z-inverse pass and the one fused into the update pass then form the same bits
 template <typename T>
@@ -642,7 +646,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
   } else {
     // forward modes: all n rows in, band rows out
     const int nfield = (MODE == COL_FWD_PLAIN || MODE == COL_FWD_ACC) ? a.nf : 3;
-    cpx<T> st[2][MAXO];
+    // COL_FWD_UPDATE_Z at 512 points (FP32): the update and the next step's z
+    // inverse work on the thread's rows r0 + 32 m (fft512_reg's one-column
+    // slots, m = s + 2 r); the stash of the first two components follows that
+    // layout (band slot e = 0..11 for m = 0..5, 10..15).  The forward
+    // transforms stay in LDS: on registers as well, the three components and
+    // the prefetch would not fit in 128 VGPRs
+    constexpr bool REGZ = MODE == COL_FWD_UPDATE_Z && N == 512 && sizeof(T) == 4 && RSTEP == 32 && MAXE == 16;
+    constexpr int NST = REGZ ? 12 : MAXO;
+    cpx<T> st[2][NST];
     cpx<T> tmp[MAXE];
     // rows of field f into tmp: unconditional loads (clamped row and column);
     // columns outside the band are transformed but never stored
@@ -703,6 +715,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             const int i = r0 + k * RSTEP;
             if (i < nb) out[(long long)i * a.ld + c] = ov[k] + scl(buf[band_to_row(i, K, n) * W + col], m);
           }
+        }
+        __syncthreads();
+      } else if (REGZ && f < 2) {
+        if (f == 0) {
+#pragma unroll
+          for (int e = 0; e < NST; ++e) st[0][e] = scl(buf[(r0 + 32 * band_slot512(e)) * W + col], a.scale);
+        } else {
+#pragma unroll
+          for (int e = 0; e < NST; ++e) st[1][e] = scl(buf[(r0 + 32 * band_slot512(e)) * W + col], a.scale);
         }
         __syncthreads();
       } else if (f < 2) {
@@ -802,7 +823,122 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       }
     }
     constexpr bool UPD = (MODE == COL_FWD_UPDATE || MODE == COL_FWD_UPDATE_Z);
-    if constexpr (MODE == COL_FWD_PROJECT || UPD) {
+    if constexpr (REGZ) {
+      // band rows of the thread (K = 170): m <= 4 and m >= 11 always, m = 5 when
+      // r0 <= 10, m = 10 when r0 >= 22, never m = 6..9; band index r0 + 32 m
+      // (m <= 5) or r0 + 32 m - 171 (m >= 10), a valid compact row for every slot
+      cpx<T> U[3][NST];  // u^{n+1}, zero outside the band and in columns out of it
+      const int ix = c % a.kxp, iy = c / a.kxp;
+      const T kx = a.kfx * (T)ix;
+      const T ky = a.kfy * (T)band_mode(iy, a.Ky);
+      const double d_n = a.sc->dt[a.cur];
+      const double d_p = a.sc->dt[a.cur ^ 1];
+      const T dtn = (T)d_n, dtp = (T)d_p;
+      T c1, c2;
+      if (a.first) {
+        c1 = dtn;
+        c2 = 0;
+      } else {
+        const double xi = d_n / d_p;
+        c1 = (T)(d_n * (1.0 + 0.5 * xi));
+        c2 = (T)(d_n * 0.5 * xi);
+      }
+      const bool b5 = r0 <= 10, b10 = r0 >= 22;
+      const int cl = c < a.C ? c : 0;
+      // band slots in chunks of two: every load of a chunk before its first
+      // store (a load after a store that may alias it waits for that store)
+      constexpr int KCZ = 2;
+      static_for<0, 12 / KCZ>([&](auto cc) __attribute__((always_inline)) {
+        constexpr int e0 = KCZ * decltype(cc)::value;
+        cpx<T> uo[KCZ][3], po[KCZ][3];
+        const int r0l = opaque(r0);  // addresses per chunk, not for all chunks ahead
+#pragma unroll
+        for (int kk = 0; kk < KCZ; ++kk) {
+          const int m = band_slot512(e0 + kk);
+          const long long idx = (long long)(m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            uo[kk][q] = ld_state(a.uh + q * a.cfs + idx);
+            po[kk][q] = ld_state(a.nh + q * a.cfs + idx);  // unused on the first step
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KCZ; ++kk) {
+          const int e = e0 + kk, m = band_slot512(e);
+          const bool inb = (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) U[q][e] = mk<T>(0, 0);
+          if (cok && inb) {
+            const int i = m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171;
+            const T kz = a.kfz * (T)band_mode(i, K);
+            cpx<T> n0 = st[0][e], n1 = st[1][e];
+            cpx<T> n2 = scl(buf[(r0l + 32 * m) * W + col], a.scale);
+            const T k2 = kx * kx + ky * ky + kz * kz;
+            const long long idx = (long long)i * a.ld + c;
+            if (a.tsp) {  // vorticity sponge (solenoidal: the projection keeps it)
+              n0 = n0 + a.tsp[idx];
+              n1 = n1 + a.tsp[a.cfs + idx];
+              n2 = n2 + a.tsp[2 * a.cfs + idx];
+            }
+            if (k2 > (T)0) {
+              const T ik2 = (T)1 / k2;
+              cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
+              n0 = n0 - scl(sp, kx);
+              n1 = n1 - scl(sp, ky);
+              n2 = n2 - scl(sp, kz);
+              if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
+            } else if (a.pi) {
+              a.pi[idx] = mk<T>(0, 0);
+            }
+            const T en = dev_exp<T>(-a.nu * k2 * dtn);
+            const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
+            const cpx<T> nn[3] = {n0, n1, n2};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const cpx<T> u1 = scl(uo[kk][q] + scl(nn[q], c1), en);
+              // first step: Euler, the stored previous term is not read
+              const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
+              st_stream(a.uh + q * a.cfs + idx, u2);
+              st_stream(a.nh + q * a.cfs + idx, nn[q]);
+              U[q][e] = u2;
+            }
+          }
+        }
+      });
+      // the first pass of the next step on the same columns: z inverse of u^{n+1}
+      // and of omega_x, omega_y = (i k x u)_x,y in the order of COL_INV_CURL5
+      // (ux, wy, uz, wx, uy), from registers
+      static_for<0, 5>([&](auto oc) __attribute__((always_inline)) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int fo = (o == 1) ? 4 : (o == 4) ? 1 : o;
+        cpx<T> v0[8], v1[8];
+        const int r0l = opaque(r0);
+        static_for<0, 16>([&](auto mc) __attribute__((always_inline)) {
+          constexpr int m = decltype(mc)::value;
+          cpx<T> val = mk<T>(0, 0);
+          if constexpr (m <= 5 || m >= 10) {
+            constexpr int e = m <= 5 ? m : m - 4;
+            if constexpr (o == 0) val = U[0][e];
+            else if constexpr (o == 2) val = U[2][e];
+            else if constexpr (o == 4) val = U[1][e];
+            else {
+              const T kz = a.kfz * (T)band_mode(m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171, K);
+              // wy = i (kz ux - kx uz), wx = i (ky uz - kz uy)
+              const cpx<T> t = (o == 1) ? scaled_diff(U[0][e], kz, U[2][e], kx) : scaled_diff(U[2][e], ky, U[1][e], kz);
+              val = mk<T>(-t.im, t.re);
+            }
+          }
+          if constexpr (m & 1) v1[m >> 1] = val;
+          else v0[m >> 1] = val;
+        });
+        fft512_reg<T, W, true, true>(v0, v1, buf, tws);
+        cpx<T>* out = a.zout + fo * a.zout_fs;
+        if (cok) {
+#pragma unroll
+          for (int m = 0; m < 16; ++m) st_stream(out + (long long)(r0 + 32 * m) * a.ld + c, (m & 1) ? v1[m >> 1] : v0[m >> 1]);
+        }
+      });
+    } else if constexpr (MODE == COL_FWD_PROJECT || UPD) {
       // COL_FWD_UPDATE_Z keeps the new velocity of the thread's rows for the
       // z inverse of the next step
       cpx<T> U[3][MAXO];
