@@ -827,7 +827,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       // band rows of the thread (K = 170): m <= 4 and m >= 11 always, m = 5 when
       // r0 <= 10, m = 10 when r0 >= 22, never m = 6..9; band index r0 + 32 m
       // (m <= 5) or r0 + 32 m - 171 (m >= 10), a valid compact row for every slot
-      cpx<T> U[3][NST];  // u^{n+1}, zero outside the band and in columns out of it
+      // u_x, u_z of u^{n+1} (zero outside the band and in columns out of it);
+      // u_y is read back from u_hat when the inverse transforms need it (all
+      // three in registers next to a transform would not fit in 128 VGPRs)
+      cpx<T> U[3][NST];
       const int ix = c % a.kxp, iy = c / a.kxp;
       const T kx = a.kfx * (T)ix;
       const T ky = a.kfy * (T)band_mode(iy, a.Ky);
@@ -855,30 +858,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
         for (int kk = 0; kk < KCZ; ++kk) {
           const int m = band_slot512(e0 + kk);
-          const long long idx = (long long)(m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl;
+          // 32-bit element offsets from uniform field bases (one compact field
+          // at 512 points is far below 4 GB)
+          const int idx = (m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            uo[kk][q] = ld_state(a.uh + q * a.cfs + idx);
-            po[kk][q] = ld_state(a.nh + q * a.cfs + idx);  // unused on the first step
+            uo[kk][q] = ld_state(at_u32(a.uh + q * a.cfs, idx));
+            po[kk][q] = ld_state(at_u32(a.nh + q * a.cfs, idx));  // unused on the first step
           }
         }
 #pragma unroll
         for (int kk = 0; kk < KCZ; ++kk) {
           const int e = e0 + kk, m = band_slot512(e);
           const bool inb = (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
-#pragma unroll
-          for (int q = 0; q < 3; ++q) U[q][e] = mk<T>(0, 0);
+          U[0][e] = mk<T>(0, 0);
+          U[2][e] = mk<T>(0, 0);
           if (cok && inb) {
             const int i = m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171;
             const T kz = a.kfz * (T)band_mode(i, K);
             cpx<T> n0 = st[0][e], n1 = st[1][e];
             cpx<T> n2 = scl(buf[(r0l + 32 * m) * W + col], a.scale);
             const T k2 = kx * kx + ky * ky + kz * kz;
-            const long long idx = (long long)i * a.ld + c;
+            const int idx = i * a.ld + c;
             if (a.tsp) {  // vorticity sponge (solenoidal: the projection keeps it)
-              n0 = n0 + a.tsp[idx];
-              n1 = n1 + a.tsp[a.cfs + idx];
-              n2 = n2 + a.tsp[2 * a.cfs + idx];
+              n0 = n0 + *at_u32(a.tsp, idx);
+              n1 = n1 + *at_u32(a.tsp + a.cfs, idx);
+              n2 = n2 + *at_u32(a.tsp + 2 * a.cfs, idx);
             }
             if (k2 > (T)0) {
               const T ik2 = (T)1 / k2;
@@ -886,9 +891,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
               n0 = n0 - scl(sp, kx);
               n1 = n1 - scl(sp, ky);
               n2 = n2 - scl(sp, kz);
-              if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
+              if (a.pi) *at_u32(a.pi, idx) = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
             } else if (a.pi) {
-              a.pi[idx] = mk<T>(0, 0);
+              *at_u32(a.pi, idx) = mk<T>(0, 0);
             }
             const T en = dev_exp<T>(-a.nu * k2 * dtn);
             const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
@@ -898,9 +903,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
               const cpx<T> u1 = scl(uo[kk][q] + scl(nn[q], c1), en);
               // first step: Euler, the stored previous term is not read
               const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
-              st_stream(a.uh + q * a.cfs + idx, u2);
-              st_stream(a.nh + q * a.cfs + idx, nn[q]);
-              U[q][e] = u2;
+              st_stream(at_u32(a.uh + q * a.cfs, idx), u2);
+              st_stream(at_u32(a.nh + q * a.cfs, idx), nn[q]);
+              if (q != 1) U[q][e] = u2;
             }
           }
         }
@@ -913,18 +918,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         constexpr int fo = (o == 1) ? 4 : (o == 4) ? 1 : o;
         cpx<T> v0[8], v1[8];
         const int r0l = opaque(r0);
+        if constexpr (o == 2) {
+          // u_y back from u_hat (this thread's own stores above: a load after a
+          // store to the same address from the same thread returns the stored
+          // value), in flight during this transform; u_x is no longer needed
+#pragma unroll
+          for (int e = 0; e < NST; ++e) {
+            const int m = band_slot512(e);
+            U[1][e] = ld_state(at_u32(a.uh + a.cfs, (m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl));
+          }
+        }
         static_for<0, 16>([&](auto mc) __attribute__((always_inline)) {
           constexpr int m = decltype(mc)::value;
           cpx<T> val = mk<T>(0, 0);
           if constexpr (m <= 5 || m >= 10) {
             constexpr int e = m <= 5 ? m : m - 4;
+            // u_y as read back (outputs 3, 4): zero outside the band and in
+            // columns out of it
+            auto uy = [&]() __attribute__((always_inline)) {
+              const bool yok = cok && ((m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10);
+              return mk<T>(yok ? U[1][e].re : (T)0, yok ? U[1][e].im : (T)0);
+            };
             if constexpr (o == 0) val = U[0][e];
             else if constexpr (o == 2) val = U[2][e];
-            else if constexpr (o == 4) val = U[1][e];
+            else if constexpr (o == 4) val = uy();
             else {
               const T kz = a.kfz * (T)band_mode(m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171, K);
               // wy = i (kz ux - kx uz), wx = i (ky uz - kz uy)
-              const cpx<T> t = (o == 1) ? scaled_diff(U[0][e], kz, U[2][e], kx) : scaled_diff(U[2][e], ky, U[1][e], kz);
+              cpx<T> t;
+              if constexpr (o == 1) t = scaled_diff(U[0][e], kz, U[2][e], kx);
+              else t = scaled_diff(U[2][e], ky, uy(), kz);
               val = mk<T>(-t.im, t.re);
             }
           }
@@ -935,7 +958,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         cpx<T>* out = a.zout + fo * a.zout_fs;
         if (cok) {
 #pragma unroll
-          for (int m = 0; m < 16; ++m) st_stream(out + (long long)(r0 + 32 * m) * a.ld + c, (m & 1) ? v1[m >> 1] : v0[m >> 1]);
+          for (int m = 0; m < 16; ++m) st_stream(at_u32(out, (r0 + 32 * m) * a.ld + c), (m & 1) ? v1[m >> 1] : v0[m >> 1]);
         }
       });
     } else if constexpr (MODE == COL_FWD_PROJECT || UPD) {
