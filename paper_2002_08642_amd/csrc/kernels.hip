@@ -316,17 +316,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       bn = (T)(a.adt * 0.5 * xi);
     }
     const T sc = (T)(a.invN3 / (ix == 0 ? 1.0 : 2.0));
-    cpx<T> M[3][MAXO];
-    constexpr int KC = sizeof(T) == 4 ? 3 : 1;
+    // FP32 512-point columns: the thread's rows r0 + 32 m (fft512_reg's
+    // one-column slots; band slot e for m = band_slot512(e): m <= 4 and m >= 11
+    // always in the band, m = 5 when r0 <= 10, m = 10 when r0 >= 22), so that mu
+    // is in registers where the register-staged inverse transforms need it;
+    // other lengths: band index r0 + k RSTEP
+    constexpr bool REGM = N == 512 && sizeof(T) == 4 && RSTEP == 32 && MAXE == 16;
+    constexpr int NS = REGM ? 12 : MAXO;
+    const bool b5 = r0 <= 10, b10 = r0 >= 22;
+    auto band_i = [&](int k, int rr) __attribute__((always_inline)) {
+      if constexpr (REGM) {
+        const int m = band_slot512(k);
+        return m <= 5 ? rr + 32 * m : rr + 32 * m - 171;
+      } else {
+        return rr + k * RSTEP;
+      }
+    };
+    auto band_ok = [&](int k) __attribute__((always_inline)) {
+      if constexpr (REGM) {
+        const int m = band_slot512(k);
+        return (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
+      } else {
+        return r0 + k * RSTEP < nb;
+      }
+    };
+    cpx<T> M[3][NS];
+    constexpr int KC = REGM ? 2 : sizeof(T) == 4 ? 3 : 1;
     const int cl = c < a.C ? c : 0;
 #pragma unroll
-    for (int k0 = 0; k0 < MAXO; k0 += KC) {
+    for (int k0 = 0; k0 < NS; k0 += KC) {
       cpx<T> uo[KC][3], po[KC][3];
+      const int r0l = opaque(r0);  // addresses per chunk, not for all chunks ahead
 #pragma unroll
       for (int kk = 0; kk < KC; ++kk) {  // loads of the chunk before its stores
         const int k = k0 + kk;
-        if (k < MAXO) {
-          const int i = r0 + k * RSTEP;
+        if (k < NS) {
+          const int i = band_i(k, r0l);
           const long long idx = (long long)(i < nb ? i : 0) * a.ld + cl;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
@@ -338,11 +363,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 #pragma unroll
       for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
-        if (k >= MAXO) break;
-        const int i = r0 + k * RSTEP;
+        if (k >= NS) break;
+        const int i = band_i(k, r0l);
 #pragma unroll
         for (int q = 0; q < 3; ++q) M[q][k] = mk<T>(0, 0);
-        if (cok && i < nb) {
+        if (cok && band_ok(k)) {
           const T kz = a.kfz * (T)band_mode(i, K);
           const T k2 = kx * kx + ky * ky + kz * kz;
           const T en = dev_exp<T>(-a.nu * k2 * (T)a.adt);
@@ -386,41 +411,63 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
       }
     }
-    __syncthreads();
-    auto mstep = [&](auto oc) {
-      constexpr int o = decltype(oc)::value;
-      const int tid = opaque((int)threadIdx.x);
-      const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
-      const bool cok = c < a.C && (c % a.kxp) < a.kx1;
+    if constexpr (REGM) {
+      // z inverse of mu (three outputs) with the first and last stage on registers
+      static_for<0, 3>([&](auto oc) __attribute__((always_inline)) {
+        constexpr int o = decltype(oc)::value;
+        cpx<T> v0[8], v1[8];
+        static_for<0, 16>([&](auto mc) __attribute__((always_inline)) {
+          constexpr int m = decltype(mc)::value;
+          cpx<T> val = mk<T>(0, 0);
+          if constexpr (m <= 5 || m >= 10) val = M[o][m <= 5 ? m : m - 4];
+          if constexpr (m & 1) v1[m >> 1] = val;
+          else v0[m >> 1] = val;
+        });
+        fft512_reg<T, W, true, true>(v0, v1, buf, tws);
+        cpx<T>* out = a.out + o * a.out_fs + ob;
+        if (cok) {
 #pragma unroll
-      for (int k = 0; k < MAXE; ++k) {
-        const int r = r0 + k * RSTEP;
-        if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
-      }
-#pragma unroll
-      for (int k = 0; k < MAXO; ++k) {
-        const int i = r0 + k * RSTEP;
-        if (i < nb) buf[band_to_row(i, K, n) * W + col] = cok ? M[o][k] : mk<T>(0, 0);
-      }
+          for (int m = 0; m < 16; ++m)
+            st_stream(out + (long long)(r0 + 32 * m) * a.ld + c, (m & 1) ? v1[m >> 1] : v0[m >> 1]);
+        }
+      });
+    } else {
       __syncthreads();
-      col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
-      cpx<T>* out = a.out + o * a.out_fs + ob;
-      cpx<T> ov[MAXE];  // LDS reads first, then the stores
-#pragma unroll
-      for (int k = 0; k < MAXE; ++k) {
-        const int r = r0 + k * RSTEP;
-        ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
-      }
-      if (cok) {
+      auto mstep = [&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        const int tid = opaque((int)threadIdx.x);
+        const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+        const bool cok = c < a.C && (c % a.kxp) < a.kx1;
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
-          if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
+          if (r > K && r < n - K) buf[r * W + col] = mk<T>(0, 0);
         }
-      }
-      __syncthreads();
-    };
-    static_for<0, 3>([&](auto oc) { mstep(oc); });
+#pragma unroll
+        for (int k = 0; k < MAXO; ++k) {
+          const int i = r0 + k * RSTEP;
+          if (i < nb) buf[band_to_row(i, K, n) * W + col] = cok ? M[o][k] : mk<T>(0, 0);
+        }
+        __syncthreads();
+        col_fft<T, W, NT, MAXE, true, N>(buf, a.plan, tws);
+        cpx<T>* out = a.out + o * a.out_fs + ob;
+        cpx<T> ov[MAXE];  // LDS reads first, then the stores
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
+        }
+        if (cok) {
+#pragma unroll
+          for (int k = 0; k < MAXE; ++k) {
+            const int r = r0 + k * RSTEP;
+            if (FULL || r < n) st_stream(out + (long long)r * a.ld + c, ov[k]);
+          }
+        }
+        __syncthreads();
+      };
+      static_for<0, 3>([&](auto oc) { mstep(oc); });
+    }
   } else if constexpr (MODE == COL_INV_WZ && PAIR) {
     // COL_INV_WZ below with two columns per lane (same outputs, order and loads)
     // on the lane's own rows rp + 64 m (m = 0..7) of fft512_reg:
