@@ -1879,11 +1879,12 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   hipError_t e = hipSuccess;
   // the width that holds 512-point columns gets the compile-time 512 transform
   constexpr bool k512 = (W * 512 == NT * MAXE);
-  const bool use512 = k512 && a.n == 512 && a.K == 170;
-  // the paired 512-point passes address a slice with 32-bit element offsets
-  if (use512 && sizeof(T) == 4 && W == 16 && (mode == COL_FWD_PLAIN || mode == COL_INV_WZ) &&
-      (long long)a.n * a.ld >= (1LL << 29))
-    return hipErrorInvalidValue;
+  // the FP32 512-point y passes and update pass address a slice or a field with
+  // 32-bit byte offsets: beyond 4 GB they run the run-time-length kernels
+  const bool off32 = sizeof(T) == 4 && W == 16 &&
+                     (mode == COL_FWD_PLAIN || mode == COL_INV_WZ || mode == COL_FWD_UPDATE_Z);
+  const bool use512 = k512 && a.n == 512 && a.K == 170 &&
+                      (!off32 || (long long)a.n * a.ld * (long long)sizeof(cpx<T>) < (1LL << 32));
 #define FSI_COL_CASE(M)                                                                \
   case M:                                                                              \
     if (use512) {                                                                      \
