@@ -225,6 +225,40 @@ def test_x_pass_512_parity(prec):
     assert ef < FTOL[prec]
 
 
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_y_pass_512_parity(prec):
+    # ny = 512 selects the paired 512-point y passes (register-staged first and
+    # last radix-8 stage in FP32); thin x, z keep the oracle fast
+    n = (16, 512, 12)
+    L = (1.0, 32.0, 0.75)
+    nu, eta, tw, h = 0.01, 0.05, 0.05, 0.03
+    print("y pass 512", prec, flush=True)
+    o = ons.OracleNS(n, L, nu, eta, tw, h, 0)
+    s = fsi.Solver(n, L, nu, eta, tw, h, 0, prec)
+    u0 = synth.random_solenoidal(n, L, seed=22)
+    o.set_velocity(u0)
+    s.set_velocity(u0)
+    x, tri = synth.flat_rectangle((0.5, 16.0, 0.4), (0, 1, 0), (1, 0, 0), 0.2, 0.15, 5, 4)
+    v = np.tile(np.array([0.1, 0.3, 0.05]), (len(x), 1))
+    o.set_wing(x, v, tri)
+    s.set_wing(x, v, tri)
+    fo, fg = [], []
+    for _ in range(5):
+        d = o.step(dt=0.02)
+        s.step(0.02)
+        i = s.info()
+        fo.append(d["F"])
+        fg.append(i["F"])
+        assert i["umax"] == pytest.approx(d["umax"], rel=VTOL[prec] * 10)
+        assert i["E"] == pytest.approx(d["E"], rel=VTOL[prec] * 10)
+    ev = rel_max(s.velocity(), o.velocity())
+    ef = rel_max(np.array(fg), np.array(fo))
+    print("y pass 512 velocity %.3e force %.3e" % (ev, ef), flush=True)
+    assert np.max(np.abs(np.array(fo))) > 1e-3
+    assert ev < VTOL[prec]
+    assert ef < FTOL[prec]
+
+
 def test_step_record_and_adjoint_reset():
     """fsi_step_record = save the state in the tape slot, then step; the reverse
     step from that slot equals the one from an explicit save; fsi_adjoint_reset
