@@ -128,10 +128,12 @@ def long_x_case(prec, n=(512, 16, 12), L=(8.0, 2.0, 1.5), tw=0.3, h=0.2):
 
 
 # (512, 192, 192): each wavefront of the 512-point pass reverses several line
-# pairs; (384, 128, 96): the LDS pass, several line groups per workgroup.
+# pairs; (384, 128, 96): the LDS pass, several line groups per workgroup;
+# (48, 512, 12): the paired 512-point y passes (9-field inverse, 6-field forward).
 LARGE = [((512, 16, 12), (8.0, 2.0, 1.5), 0.3, 0.2),
          ((512, 192, 192), (8.0, 3.0, 3.0), 0.05, 0.03),
-         ((384, 128, 96), (6.0, 2.0, 1.5), 0.05, 0.03)]
+         ((384, 128, 96), (6.0, 2.0, 1.5), 0.05, 0.03),
+         ((48, 512, 12), (3.0, 32.0, 0.75), 0.05, 0.03)]
 
 
 @pytest.mark.parametrize("case", LARGE, ids=lambda c: "x".join(map(str, c[0])))
