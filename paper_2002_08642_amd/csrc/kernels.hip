@@ -720,14 +720,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
       const int tid = opaque((int)threadIdx.x);
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
+      if constexpr (REGZ) {
+        // the loaded rows r0 + 32 m are the inputs of the span-1 butterflies
+        // j = r0 and j = r0 + 32 (m = s + 2 r): that stage on registers, its
+        // outputs (rows 8 j + r) to LDS, the two other stages there
+        cpx<T> v0[8], v1[8];
 #pragma unroll
-      for (int k = 0; k < MAXE; ++k) {
-        const int r = r0 + k * RSTEP;
-        if (FULL || r < n) buf[r * W + col] = tmp[k];
+        for (int r = 0; r < 8; ++r) {
+          v0[r] = tmp[2 * r];
+          v1[r] = tmp[2 * r + 1];
+        }
+        Bfly<T, 8, -1>::run(v0);
+        Bfly<T, 8, -1>::run(v1);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          buf[(8 * r0 + r) * W + col] = v0[r];
+          buf[(8 * (r0 + 32) + r) * W + col] = v1[r];
+        }
+        __syncthreads();
+        if (prefetch) load_field(f + 1);
+        fft_stage<T, 8, W, W, NT, MAXE, false>(buf, 512, 8, tws);
+        fft_stage<T, 8, W, W, NT, MAXE, false>(buf, 512, 64, tws);
+      } else {
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int r = r0 + k * RSTEP;
+          if (FULL || r < n) buf[r * W + col] = tmp[k];
+        }
+        __syncthreads();
+        if (prefetch) load_field(f + 1);
+        col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       }
-      __syncthreads();
-      if (prefetch) load_field(f + 1);
-      col_fft<T, W, NT, MAXE, false, N>(buf, a.plan, tws);
       if (MODE == COL_FWD_PLAIN) {
         cpx<T>* out = a.out + f * a.out_fs + ob;
         cpx<T> ov[MAXO];  // LDS reads first, then the stores
