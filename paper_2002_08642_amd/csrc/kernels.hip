@@ -697,8 +697,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     // inverse work on the thread's rows r0 + 32 m (fft512_reg's one-column
     // slots, m = s + 2 r); the stash of the first two components follows that
     // layout (band slot e = 0..11 for m = 0..5, 10..15).  The forward
-    // transforms stay in LDS: on registers as well, the three components and
-    // the prefetch would not fit in 128 VGPRs
+    // transforms run their first stage on the loaded registers and the other
+    // two in LDS: all on registers, the three components and the prefetch
+    // would not fit in 128 VGPRs
     constexpr bool REGZ = MODE == COL_FWD_UPDATE_Z && N == 512 && sizeof(T) == 4 && RSTEP == 32 && MAXE == 16;
     constexpr int NST = REGZ ? 12 : MAXO;
     cpx<T> st[2][NST];
