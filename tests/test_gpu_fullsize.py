@@ -19,7 +19,10 @@ discrete method that hold at any size:
   - the nonlinear term is solenoidal and does exactly the penalization work
     Re sum w conj(u_hat).N_hat = -(1/(eta N^3)) sum chi u.(u - u_s) (u x omega
     does none);
-  - the update is the first (Euler) integrating-factor step of that term.
+  - the update is the first (Euler) integrating-factor step of that term;
+* the adjoint of two steps of the bench workload (the kernels the adjoint leg of
+  bench.py times): FP64 against central differences of the FP64 forward map
+  (dot-product test), FP32 cotangents against the FP64 ones.
 """
 
 import numpy as np
@@ -28,6 +31,7 @@ import pytest
 from oracle import mask as omask
 from paper_2002_08642_amd import fsi
 from tests.helpers import rel_max
+from tests.test_gpu_adjoint import run_two_steps
 import bench
 import synth
 
@@ -154,3 +158,41 @@ def test_fullsize_bench_first_step():
     eup = rel_max(uh1, expect)
     print("update %.3e" % eup, flush=True)
     assert eup < 1e-6
+
+
+def test_fullsize_adjoint_two_steps():
+    cfg = bench.workload(N)
+    n, L = cfg["n"], cfg["L"]
+    x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], 0.0, cfg["alpha"], cfg["omega"], 0.0,
+                             cfg["axis_point"])
+    tri = np.asarray(cfg["tri"])
+    rng = np.random.default_rng(29)
+    # jittered off the flat plate, so that no grid point is equidistant from two
+    # triangles (where the distance to the mesh has a kink)
+    x = x + 2e-3 * rng.standard_normal(x.shape)
+    u0 = synth.random_solenoidal_compact(n, L, seed=0)
+    du = synth.random_solenoidal_compact(n, L, seed=1)
+    dx = 1e-3 * rng.standard_normal(x.shape)
+    dv = rng.standard_normal(x.shape)
+    g = [rng.standard_normal(3), rng.standard_normal(3)]
+    lam_u = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    lam_n = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
+    dts = (1.0e-4, 1.2e-4)
+    out = {}
+    for prec in (fsi.PREC_FP64, fsi.PREC_FP32):
+        print("512^3 adjoint, precision", prec, flush=True)
+        s = fsi.Solver(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
+        out[prec] = run_two_steps(s, u0, x, v, tri, dts, g, lam_u, lam_n, du, dx, dv)
+        del s
+    adj, fd, r64 = out[fsi.PREC_FP64]
+    print("512^3 dot product FP64: adjoint %.12e fd %.12e" % (adj, fd), flush=True)
+    assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-8)
+    r32 = out[fsi.PREC_FP32][2]
+    for name, a32, a64 in zip(("lambda_u", "lambda_N", "dJ/dx", "dJ/dv"), r32, r64):
+        ref = np.max(np.abs(a64))
+        if name == "lambda_N":  # reversing the first (Euler) step leaves no N^{-1} cotangent
+            assert ref == 0.0 and np.max(np.abs(a32)) == 0.0
+            continue
+        err = np.max(np.abs(a32 - a64)) / ref
+        print("512^3 FP32 vs FP64 adjoint %s: %.3e" % (name, err), flush=True)
+        assert err < 1e-4
