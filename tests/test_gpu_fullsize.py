@@ -21,8 +21,10 @@ discrete method that hold at any size:
     does none);
   - the update is the first (Euler) integrating-factor step of that term;
 * the adjoint of two steps of the bench workload (the kernels the adjoint leg of
-  bench.py times): FP64 against central differences of the FP64 forward map
-  (dot-product test), FP32 cotangents against the FP64 ones.
+  bench.py times), without and with the sponge layers of the sponge leg: FP64
+  against central differences of the FP64 forward map (dot-product test), FP32
+  cotangents against the FP64 ones;
+* the uniform sponge on 2-D Taylor-Green: the closed-form damped recurrence.
 """
 
 import numpy as np
@@ -160,7 +162,34 @@ def test_fullsize_bench_first_step():
     assert eup < 1e-6
 
 
-def test_fullsize_adjoint_two_steps():
+@pytest.mark.parametrize("prec", [fsi.PREC_FP32, fsi.PREC_FP64])
+def test_fullsize_uniform_sponge_recurrence(prec):
+    """chi_sp = 1 on the 2-D Taylor-Green field at 512^3: the scalar IF-AB2
+    recurrence of a linear damping 1/C_sp (closed form; the sponge kernels of the
+    bench's sponge leg at full size)."""
+    n, L, nu, c_sp = (N, N, N), (2 * np.pi,) * 3, 0.02, 0.3
+    s = fsi.Solver(n, L, nu, 1.0, precision=prec)
+    u0 = synth.taylor_green_2d(n, L)
+    s.set_velocity(u0)
+    s.set_sponge(c_sp, gx=np.ones(N))
+    a_prev, a, dt_prev = None, 1.0, None
+    for dt in np.random.default_rng(4).uniform(0.005, 0.03, 4):
+        s.step(dt)
+        en = np.exp(-2 * nu * dt)
+        if a_prev is None:
+            a_new = en * (1 - dt / c_sp) * a
+        else:
+            xi = dt / dt_prev
+            ep = np.exp(-2 * nu * dt_prev)
+            a_new = en * (1 - dt * (1 + xi / 2) / c_sp) * a + dt * (xi / 2) / c_sp * en * ep * a_prev
+        a_prev, a, dt_prev = a, a_new, dt
+    err = rel_max(s.velocity(), a * u0)
+    print("512^3 uniform sponge prec %d: %.3e" % (prec, err), flush=True)
+    assert err < (1e-12 if prec == fsi.PREC_FP64 else 2e-6)
+
+
+@pytest.mark.parametrize("sponge", [False, True], ids=["plain", "sponge"])
+def test_fullsize_adjoint_two_steps(sponge):
     cfg = bench.workload(N)
     n, L = cfg["n"], cfg["L"]
     x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], 0.0, cfg["alpha"], cfg["omega"], 0.0,
@@ -182,6 +211,9 @@ def test_fullsize_adjoint_two_steps():
     for prec in (fsi.PREC_FP64, fsi.PREC_FP32):
         print("512^3 adjoint, precision", prec, flush=True)
         s = fsi.Solver(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
+        if sponge:  # the layers of the bench's sponge leg
+            gx, gz = bench.sponge_layers(N)
+            s.set_sponge(bench.SPONGE_C, gx=gx, gz=gz)
         out[prec] = run_two_steps(s, u0, x, v, tri, dts, g, lam_u, lam_n, du, dx, dv)
         del s
     adj, fd, r64 = out[fsi.PREC_FP64]
