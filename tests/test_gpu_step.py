@@ -259,6 +259,42 @@ def test_y_pass_512_parity(prec):
     assert ef < FTOL[prec]
 
 
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_revolving_plate_128_parity(prec):
+    """The revolving-plate workload at its own size (128^3, box 12, the plate
+    re-posed and the mask rebuilt every step, mid-ramp so that the plate moves):
+    five steps against the oracle."""
+    cfg = synth.revolving_plate(n=128)
+    n, L = cfg["n"], cfg["L"]
+    print("revolving plate 128", prec, flush=True)
+    o = ons.OracleNS(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"])
+    s = fsi.Solver(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
+    u0 = synth.random_solenoidal(n, L, seed=41)
+    o.set_velocity(u0)
+    s.set_velocity(u0)
+    tri = np.asarray(cfg["tri"])
+    t, dt = 0.15, 1e-3
+    fo, fg = [], []
+    for _ in range(5):
+        x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], t, cfg["alpha"], cfg["omega"],
+                                 cfg["t_ramp"], cfg["axis_point"])
+        o.set_wing(x, v, tri)
+        s.set_wing(x, v, tri)
+        d = o.step(dt=dt)
+        s.step(dt)
+        i = s.info()
+        fo.append(d["F"])
+        fg.append(i["F"])
+        assert i["umax"] == pytest.approx(d["umax"], rel=VTOL[prec] * 10)
+        t += dt
+    ev = rel_max(s.velocity(), o.velocity())
+    ef = rel_max(np.array(fg), np.array(fo))
+    print("revolving plate 128 velocity %.3e force %.3e" % (ev, ef), flush=True)
+    assert np.max(np.abs(np.array(fo))) > 1e-3
+    assert ev < VTOL[prec]
+    assert ef < FTOL[prec]
+
+
 def test_step_record_and_adjoint_reset():
     """fsi_step_record = save the state in the tape slot, then step; the reverse
     step from that slot equals the one from an explicit save; fsi_adjoint_reset
