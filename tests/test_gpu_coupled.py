@@ -60,10 +60,13 @@ def test_coupled_flexible_wing_matches_oracle(prec):
     assert max(g.iters) <= 8
 
 
-def test_full_flexible_wing_fp32_follows_fp64():
-    """The config-2 wing (31 x 16 membrane, 8 veins of 25 nodes) at 96^3: the
-    FP32 fluid with the FP64 structure follows the FP64 run."""
-    cfg = synth.revolving_plate(n=96, t_ramp=0.05)
+# 96^3, and the flexible-wing workload's own 256^3 (eta scales as dx^2 there:
+# dt / eta = 0.64)
+@pytest.mark.parametrize("n,dt,nsteps", [(96, 1e-3, 12), (256, 4e-4, 20)], ids=["96", "256"])
+def test_full_flexible_wing_fp32_follows_fp64(n, dt, nsteps):
+    """The config-2 wing (31 x 16 membrane, 8 veins of 25 nodes): the FP32 fluid
+    with the FP64 structure follows the FP64 run."""
+    cfg = synth.revolving_plate(n=n, t_ramp=0.05)
     w = synth.flexible_wing(density=1.0)
     ijk, owner = synth.vein_bending(w)
     kb = np.array([fsi.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
@@ -74,12 +77,12 @@ def test_full_flexible_wing_fp32_follows_fp64():
                        pressure=True)
         s.set_velocity(np.zeros((3,) + cfg["n"]))
         g = FlexibleWingFSI(s, w, ijk, kb, np.zeros(len(ijk), np.int32), kin, tol=1e-10)
-        F = [g.step(1e-3) for _ in range(12)]
+        F = [g.step(dt) for _ in range(nsteps)]
         runs[prec] = (g.state()[0], np.array(F), g)
     x64, F64, g64 = runs[fsi.PREC_FP64]
     x32, F32, _ = runs[fsi.PREC_FP32]
     xr, _ = g64._root_pose(g64.t, None)
     ed, ef = rel(x32 - xr, x64 - xr), rel(F32, F64)
-    print("config-2 wing 96^3: FP32 vs FP64 deflection %.3e force %.3e (max deflection %.3e)"
-          % (ed, ef, np.max(np.abs(x64 - xr))), flush=True)
+    print("config-2 wing %d^3: FP32 vs FP64 deflection %.3e force %.3e (max deflection %.3e)"
+          % (n, ed, ef, np.max(np.abs(x64 - xr))), flush=True)
     assert ed < 1e-4 and ef < 1e-4
