@@ -425,11 +425,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         });
         fft512_reg<T, W, true, true>(v0, v1, buf, tws);
         cpx<T>* out = a.out + o * a.out_fs + ob;
-        if (cok) {
+        // unconditional stores (columns out of the band carry zeros; the launcher
+        // runs this kernel only for whole workgroups of columns): a store under
+        // a branch makes the next wait for a prefetched load wait for the
+        // stores as well
 #pragma unroll
-          for (int m = 0; m < 16; ++m)
-            st_stream(out + (long long)(r0 + 32 * m) * a.ld + c, (m & 1) ? v1[m >> 1] : v0[m >> 1]);
-        }
+        for (int m = 0; m < 16; ++m)
+          st_stream(out + (long long)(r0 + 32 * m) * a.ld + c, (m & 1) ? v1[m >> 1] : v0[m >> 1]);
       });
     } else {
       __syncthreads();
@@ -535,10 +537,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       }
       fft512_reg<float, W, true>(v0, v1, reinterpret_cast<cpx<float>*>(buf), reinterpret_cast<const cpx<float>*>(tws));
       cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs + ob;
-      if (c < a.C) {  // columns out of the band hold zeros
+      // unconditional stores (columns out of the band, padding included, carry
+      // zeros; the launcher keeps the workgroup's columns within the row pitch):
+      // a store under a branch makes the next wait for the prefetched field
+      // wait for these stores as well
 #pragma unroll
-        for (int m = 0; m < 8; ++m) st_stream2(at_u32(out, (rp + 64 * m) * a.ld + c), cpx2f{v0[m], v1[m]});
-      }
+      for (int m = 0; m < 8; ++m) st_stream2(at_u32(out, (rp + 64 * m) * a.ld + c), cpx2f{v0[m], v1[m]});
     };
     load_into(0, RA);
     static_for<0, 6>([&](auto oc) { step(oc); });
@@ -663,13 +667,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
       cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + f * a.out_fs + ob;
       const float sc = (float)a.scale;
-      if (c < a.C) {
+      // unconditional stores (padding columns included, the launcher keeps the
+      // workgroup's columns within the row pitch; a store under a branch makes
+      // the next wait for the prefetched field wait for the stores as well): a
+      // row out of the band (m = 2 with rp > 42, m = 5 with rp < 22) stores the
+      // lane's row m = 0 again, same value, same address
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          if (m == 3 || m == 4 || (m == 2 && rp > 42) || (m == 5 && rp < 22)) continue;
-          const int i = m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
-          st_stream2(at_u32(out, i * a.ld + c), cpx2f{scl(v0[m], sc), scl(v1[m], sc)});
-        }
+      for (int m = 0; m < 8; ++m) {
+        if (m == 3 || m == 4) continue;
+        const bool inb = (m == 2) ? rp <= 42 : (m == 5) ? rp >= 22 : true;
+        const int i = !inb ? rp : m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
+        const cpx<float> w0 = inb ? v0[m] : v0[0], w1 = inb ? v1[m] : v1[0];
+        st_stream2(at_u32(out, i * a.ld + c), cpx2f{scl(w0, sc), scl(w1, sc)});
       }
     };
     load_field(0);
@@ -1027,10 +1036,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         });
         fft512_reg<T, W, true, true>(v0, v1, buf, tws);
         cpx<T>* out = a.zout + fo * a.zout_fs;
-        if (cok) {
+        // unconditional stores (columns out of the band carry zeros; whole
+        // workgroups of columns only): a store under a branch makes the next
+        // wait for a prefetched load wait for the stores as well
 #pragma unroll
-          for (int m = 0; m < 16; ++m) st_stream(at_u32(out, (r0 + 32 * m) * a.ld + c), (m & 1) ? v1[m >> 1] : v0[m >> 1]);
-        }
+        for (int m = 0; m < 16; ++m) st_stream(at_u32(out, (r0 + 32 * m) * a.ld + c), (m & 1) ? v1[m >> 1] : v0[m >> 1]);
       });
     } else if constexpr (MODE == COL_FWD_PROJECT || UPD) {
       // COL_FWD_UPDATE_Z keeps the new velocity of the thread's rows for the
@@ -1907,7 +1917,10 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   // 32-bit byte offsets: beyond 4 GB they run the run-time-length kernels
   const bool off32 = sizeof(T) == 4 && W == 16 &&
                      (mode == COL_FWD_PLAIN || mode == COL_INV_WZ || mode == COL_FWD_UPDATE_Z);
-  const bool use512 = k512 && a.n == 512 && a.K == 170 &&
+  // the FP32 512-point kernels store every column of their workgroup without a
+  // column test: the last workgroup's columns must lie within the row pitch
+  const bool whole = !(sizeof(T) == 4 && W == 16) || (long long)((a.C + W - 1) / W) * W <= a.ld;
+  const bool use512 = k512 && a.n == 512 && a.K == 170 && whole &&
                       (!off32 || (long long)a.n * a.ld * (long long)sizeof(cpx<T>) < (1LL << 32));
 #define FSI_COL_CASE(M)                                                                \
   case M:                                                                              \
