@@ -208,7 +208,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         const int r = r0 + k * RSTEP;
         ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
       }
-      if (cok) {
+      // 512 points: unconditional stores (columns out of the band carry zeros;
+      // the launcher keeps the workgroup's columns within the row pitch), so
+      // the next wait for a prefetched load does not wait for them as well
+      if (N == 512 || cok) {
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         const int r = r0 + k * RSTEP;
         ov[k] = buf[((FULL || r < n) ? r : 0) * W + col];
       }
-      if (cok) {
+      if (N == 512 || cok) {  // 512 points: unconditional stores, as in COL_INV_PLAIN
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int r = r0 + k * RSTEP;
@@ -1917,9 +1920,9 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   // 32-bit byte offsets: beyond 4 GB they run the run-time-length kernels
   const bool off32 = sizeof(T) == 4 && W == 16 &&
                      (mode == COL_FWD_PLAIN || mode == COL_INV_WZ || mode == COL_FWD_UPDATE_Z);
-  // the FP32 512-point kernels store every column of their workgroup without a
+  // the 512-point kernels store every column of their workgroup without a
   // column test: the last workgroup's columns must lie within the row pitch
-  const bool whole = !(sizeof(T) == 4 && W == 16) || (long long)((a.C + W - 1) / W) * W <= a.ld;
+  const bool whole = (long long)((a.C + W - 1) / W) * W <= a.ld;
   const bool use512 = k512 && a.n == 512 && a.K == 170 && whole &&
                       (!off32 || (long long)a.n * a.ld * (long long)sizeof(cpx<T>) < (1LL << 32));
 #define FSI_COL_CASE(M)                                                                \
