@@ -154,6 +154,61 @@ def random_solenoidal_compact(n, L, seed=0, energy=1.0, slope=-11.0 / 6.0):
     return uh * np.sqrt(energy / e)
 
 
+def beltrami_modes(n, L, m2, seed=0):
+    """A Beltrami (ABC-type) field: a sum of helical Fourier modes that all have
+    the same |k|, so that curl u = |k| u, u x omega = 0 and the field decays as
+    exp(-nu |k|^2 t) under the Navier-Stokes equations with no mask.
+
+    The modes are every integer vector m with |k(m)|^2 = (2 pi)^2 m2 / L_x^2
+    (k_j = 2 pi m_j / L_j) on the half space m_x > 0, or m_x = 0 and (m_y, m_z)
+    positive lexicographically; each carries a seeded complex amplitude times
+    the positive-helicity vector h = (e1 + i e2)/sqrt(2) (e1, e2, k/|k| a
+    right-handed orthonormal frame; i k x h = |k| h).  Returns a list of
+    (m, u_hat) pairs; the partner at -m is the conjugate (real field).  Every
+    m must lie in the 2/3 band of n.
+    """
+    nx, ny, nz = n
+    lx, ly, lz = L
+    target = (2 * np.pi) ** 2 * m2 / lx ** 2
+    rng = np.random.default_rng(seed)
+    r = int(math.isqrt(int(m2))) + 1
+    scale = [lx / lx, lx / ly, lx / lz]
+    out = []
+    for mx_ in range(0, int(r / scale[0]) + 2):
+        for my_ in range(-int(r / scale[1]) - 2, int(r / scale[1]) + 3):
+            for mz_ in range(-int(r / scale[2]) - 2, int(r / scale[2]) + 3):
+                if mx_ == 0 and (my_ < 0 or (my_ == 0 and mz_ <= 0)):
+                    continue
+                k = np.array([2 * np.pi * mx_ / lx, 2 * np.pi * my_ / ly, 2 * np.pi * mz_ / lz])
+                if abs(float(k @ k) - target) > 1e-12 * target:
+                    continue
+                if not (3 * abs(mx_) < nx and 3 * abs(my_) < ny and 3 * abs(mz_) < nz):
+                    raise ValueError("Beltrami mode outside the 2/3 band")
+                kh = k / np.linalg.norm(k)
+                a = np.array([0.0, 0.0, 1.0]) if abs(kh[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+                e1 = np.cross(kh, a)
+                e1 /= np.linalg.norm(e1)
+                e2 = np.cross(kh, e1)
+                c = rng.standard_normal() + 1j * rng.standard_normal()
+                out.append(((mx_, my_, mz_), c * (e1 + 1j * e2) / math.sqrt(2.0)))
+    if not out:
+        raise ValueError("no integer mode with that |k|")
+    return out
+
+
+def modes_to_compact(n, modes):
+    """Compact-band spectrum (3, 2Kz+1, 2Ky+1, Kx+1) holding the given half-space
+    modes (and, on the kx = 0 plane, their conjugate partners)."""
+    nx, ny, nz = n
+    Kx, Ky, Kz = (nx - 1) // 3, (ny - 1) // 3, (nz - 1) // 3
+    uh = np.zeros((3, 2 * Kz + 1, 2 * Ky + 1, Kx + 1), dtype=np.complex128)
+    for (mx_, my_, mz_), c in modes:
+        uh[:, mz_ % (2 * Kz + 1), my_ % (2 * Ky + 1), mx_] = c
+        if mx_ == 0:
+            uh[:, (-mz_) % (2 * Kz + 1), (-my_) % (2 * Ky + 1), 0] = np.conj(c)
+    return uh
+
+
 # ---------------------------------------------------------------------------
 # wing triangulations (wing frame; no pose)
 # ---------------------------------------------------------------------------

@@ -179,3 +179,42 @@ def test_save_load_roundtrip():
     o.step(dt=0.02)
     assert np.array_equal(a, o.velocity())
     assert np.max(np.abs(dft.forward(a).imag)) < 1.0
+
+
+def _compact_to_full(uh_c, n):
+    """Hermitian extension of the compact half-band layout (test helper)."""
+    nx, ny, nz = n
+    Kx, Ky, Kz = (nx - 1) // 3, (ny - 1) // 3, (nz - 1) // 3
+    full = np.zeros((3, nz, ny, nx), dtype=np.complex128)
+    mz = np.concatenate([np.arange(Kz + 1), np.arange(-Kz, 0)])
+    my = np.concatenate([np.arange(Ky + 1), np.arange(-Ky, 0)])
+    for a, zz in enumerate(mz):
+        for b, yy in enumerate(my):
+            full[:, zz % nz, yy % ny, :Kx + 1] = uh_c[:, a, b, :]
+            full[:, (-zz) % nz, (-yy) % ny, (nx - np.arange(1, Kx + 1)) % nx] = np.conj(uh_c[:, a, b, 1:])
+    return full
+
+
+@pytest.mark.parametrize("L", [(2 * np.pi,) * 3, (3.0, 3.0, 3.0)])
+def test_beltrami_exact_decay_any_dt_sequence(L, rng):
+    """Helical modes of one |k| (on every axis, z included): curl u = |k| u, so
+    u x omega = 0 pointwise and the step leaves only exp(-nu |k|^2 t)."""
+    from oracle import spectral
+    n = (24, 24, 24)
+    nu = 0.03
+    modes = synth.beltrami_modes(n, L, 6, seed=1)  # |m|^2 = 6: (1,1,2) and permutations
+    assert {abs(m[0][2]) for m in modes} == {1, 2}
+    full = _compact_to_full(synth.modes_to_compact(n, modes), n)
+    kmag = 2 * np.pi / L[0] * np.sqrt(6.0)
+    # the generator's field is real and a curl eigenfunction
+    u0 = dft.inverse_real(full)
+    assert np.max(np.abs(dft.forward(u0) - full)) < 1e-14 * np.max(np.abs(full))
+    w0 = dft.inverse_real(spectral.curl(full, n, L))
+    assert np.max(np.abs(w0 - kmag * u0)) < 1e-12 * kmag * np.max(np.abs(u0))
+    o = ns.OracleNS(n, L, nu, eta=1.0)
+    o.set_velocity(u0)
+    t = 0.0
+    for dt in rng.uniform(1e-3, 2e-2, 6):
+        o.step(dt=dt)
+        t += dt
+    assert np.max(np.abs(o.velocity() - np.exp(-nu * kmag ** 2 * t) * u0)) < 1e-13 * np.max(np.abs(u0))
