@@ -149,6 +149,25 @@ fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double*
  * current wing (zero everywhere without a wing). Synchronizes. */
 fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the mask of
+ * fsi_get_mask written into caller-owned device arrays, with no allocation of
+ * any kind.  chi: device array [nz][ny][nx], us: device array [3][nz][ny][nx],
+ * both of the context's precision (float for FSI_PREC_FP32, double for
+ * FSI_PREC_FP64), overwritten everywhere (zero outside the wing's support).
+ * The argmin keys of the mask kernels live in a fixed scratch array compiled
+ * into the library, one per device, of FSI_NOALLOC_MASK_CELLS sub-box cells
+ * (the grid points within the mask support of the wing's bounding box):
+ * FSI_EINVAL (state unchanged) if the current wing needs more.  Queued on the
+ * context's stream, no host synchronization; the outputs are ready after
+ * fsi_synchronize or any synchronizing call.  Every call on a device uses that
+ * device's one scratch array: calls that overlap on one device (several
+ * contexts or streams of one process) race and must be serialized by the
+ * caller.  No memset is queued (fills are kernels), so the call can be
+ * captured in a HIP graph. */
+#define FSI_NOALLOC_MASK_CELLS (1 << 20)
+fsi_status fsi_get_mask_noalloc(fsi_ctx* ctx, void* chi, void* us);
+
 /* One step with a given dt > 0 (queued on the stream, no host sync).
  * FSI_ESTABILITY if a wing is set and dt > eta. */
 fsi_status fsi_step(fsi_ctx* ctx, double dt);

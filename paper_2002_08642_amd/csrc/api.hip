@@ -11,14 +11,44 @@
 #include "../../include/fsi.h"
 #include "engine.h"
 
+#include <mutex>
+
 struct fsi_ctx {
   fsi::EngineBase* eng = nullptr;
+  int device = 0;  // the device current at fsi_create
 };
 
 namespace {
 thread_local std::string g_create_error;
 
 fsi_status guard(fsi_ctx* c) { return (c && c->eng) ? FSI_OK : FSI_EINVAL; }
+
+// Fixed key scratch of fsi_get_mask_noalloc: two u64 keys per mask sub-box cell,
+// FSI_NOALLOC_MASK_CELLS cells (16 MiB per device, held until the process ends).
+// Every call on a device shares that device's copy.
+static __device__ __align__(256) unsigned long long scratch[2 * FSI_NOALLOC_MASK_CELLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the host-side name is only a stand-in);
+// resolved once per device at fsi_create, with that device current.
+fsi_status resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return FSI_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return FSI_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FSI_EDEVICE;
+  g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+  return FSI_OK;
+}
+
+unsigned long long* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 }  // namespace
 
 extern "C" {
@@ -44,8 +74,14 @@ fsi_status fsi_create(const fsi_desc* desc, fsi_ctx** out) {
     g_create_error = "no HIP device available";
     return FSI_EDEVICE;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || resolve_scratch(dev) != FSI_OK) {
+    g_create_error = "cannot resolve the device address of the fixed mask scratch";
+    return FSI_EDEVICE;
+  }
   fsi_ctx* c = new (std::nothrow) fsi_ctx();
   if (!c) return FSI_ENOMEM;
+  c->device = dev;
   c->eng = desc->precision == FSI_PREC_FP64 ? fsi::make_engine_f64() : fsi::make_engine_f32();
   const fsi_status st = c->eng->init(*desc);
   if (st != FSI_OK) {
@@ -127,6 +163,16 @@ fsi_status fsi_set_sponge(fsi_ctx* ctx, double c_sp, const double* gx, const dou
 fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us) {
   if (guard(ctx) != FSI_OK || !chi || !us) return FSI_EINVAL;
   return ctx->eng->get_mask(chi, us);
+}
+
+fsi_status fsi_get_mask_noalloc(fsi_ctx* ctx, void* chi, void* us) {
+  if (guard(ctx) != FSI_OK || !chi || !us) return FSI_EINVAL;
+  unsigned long long* p = scratch_of(ctx->device);
+  if (!p) {
+    ctx->eng->err = "fixed mask scratch not resolved for this device";
+    return FSI_EDEVICE;
+  }
+  return ctx->eng->get_mask_grid(chi, us, p, FSI_NOALLOC_MASK_CELLS);
 }
 
 fsi_status fsi_step(fsi_ctx* ctx, double dt) {

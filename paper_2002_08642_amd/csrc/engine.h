@@ -24,6 +24,9 @@ class EngineBase {
   virtual fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) = 0;
   virtual fsi_status set_sponge(double c_sp, const double* gx, const double* gy, const double* gz) = 0;
   virtual fsi_status get_mask(double* chi, double* us) = 0;
+  // get_mask into device grids with caller-provided key scratch (2 * max_cells
+  // u64); queued on the stream, allocates nothing
+  virtual fsi_status get_mask_grid(void* chi, void* us, unsigned long long* scratch, long long max_cells) = 0;
   virtual fsi_status step(bool adaptive, double dt, double cfl, double c_eta, double dt_max) = 0;
   virtual fsi_status step_info(double F[3], double* dt, double* E, double* umax, double* t, long long* nstep) = 0;
   virtual fsi_status fft_r2c(const double* f, double* fh) = 0;

@@ -586,6 +586,48 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  fsi_status get_mask_grid(void* chi_out, void* us_out, unsigned long long* scratch, long long max_cells) override {
+    if (!chi_out || !us_out) {
+      err = "chi and us must be device pointers";
+      return FSI_EINVAL;
+    }
+    const bool wing = wing_nt > 0 && bcells > 0;
+    if (wing && bcells > max_cells) {
+      err = "mask sub-box of " + std::to_string(bcells) + " cells exceeds the " + std::to_string(max_cells) +
+            " cells of the fixed scratch";
+      return FSI_EINVAL;
+    }
+    MaskArgs<T> m;
+    memset(&m, 0, sizeof(m));
+    m.x = dx_;
+    m.v = dv_;
+    m.tri = dtri_;
+    m.nt = wing ? wing_nt : 0;
+    m.key1 = scratch;
+    m.key2 = scratch + max_cells;
+    m.chi = (T*)chi_out;
+    m.us = (T*)us_out;
+    m.bx0 = bx0;
+    m.by0 = by0;
+    m.bz0 = bz0;
+    m.bnx = bnx;
+    m.bny = bny;
+    m.bnz = bnz;
+    m.bcells = wing ? bcells : 0;
+    m.dx = dxs[0];
+    m.dy = dxs[1];
+    m.dz = dxs[2];
+    m.rsup = rsup;
+    m.tw = d.tw;
+    m.h = d.h;
+    m.profile = d.mask_profile;
+    m.gnx = nx;
+    m.gny = ny;
+    m.gcells = npts;
+    FSI_HIP(launch_mask_grid<T>(m, s));
+    return FSI_OK;
+  }
+
   // -- one step ------------------------------------------------------------------
   // vorticity sponge: chi_sp = max(gx[x], gy[y], gz[z]) (NULL profile = 0), c_sp <= 0: off
   fsi_status set_sponge(double c_sp, const double* gx, const double* gy, const double* gz) override {

@@ -167,6 +167,10 @@ struct MaskArgs {
   double rsup;         // support radius
   double tw, h;
   int profile;
+  // grid output (launch_mask_grid only): chi and u_s written to full grids
+  // [nz][ny][nx] (u_s component stride gcells) instead of the sub-box arrays
+  int gnx, gny;
+  long long gcells;
 };
 
 // ---------------------------------------------------------------------------

@@ -1752,16 +1752,18 @@ __global__ __launch_bounds__(kNT) void mask_dist(MaskArgs<T> a) {
   }
 }
 
-template <typename T>
+// GRID = false: chi, u_s into the sub-box arrays; GRID = true: into full grids
+// (the caller has zeroed them outside the sub-box)
+template <typename T, bool GRID>
 __global__ __launch_bounds__(kNT) void mask_eval(MaskArgs<T> a) {
   for (long long cell = (long long)blockIdx.x * kNT + threadIdx.x; cell < a.bcells; cell += (long long)gridDim.x * kNT) {
     const unsigned long long key = a.key2[cell];
     double ch = 0, u0 = 0, u1 = 0, u2 = 0;
+    const int bx = (int)(cell % a.bnx);
+    const int by = (int)((cell / a.bnx) % a.bny);
+    const int bz = (int)(cell / ((long long)a.bnx * a.bny));
     if (key != ~0ull) {
       const int t = (int)(key & 0xffffffffull);
-      const int bx = (int)(cell % a.bnx);
-      const int by = (int)((cell / a.bnx) % a.bny);
-      const int bz = (int)(cell / ((long long)a.bnx * a.bny));
       const int ia = a.tri[3 * t], ib = a.tri[3 * t + 1], ic = a.tri[3 * t + 2];
       const double ax = a.x[3 * ia], ay = a.x[3 * ia + 1], az = a.x[3 * ia + 2];
       const double px = (double)(bx + a.bx0) * a.dx - ax, py = (double)(by + a.by0) * a.dy - ay,
@@ -1779,11 +1781,24 @@ __global__ __launch_bounds__(kNT) void mask_eval(MaskArgs<T> a) {
         }
       }
     }
-    a.chi[cell] = (T)ch;
-    a.us[cell] = (T)u0;
-    a.us[a.bcells + cell] = (T)u1;
-    a.us[2 * a.bcells + cell] = (T)u2;
+    if constexpr (GRID) {
+      const long long o = ((long long)(bz + a.bz0) * a.gny + (by + a.by0)) * a.gnx + (bx + a.bx0);
+      a.chi[o] = (T)ch;
+      a.us[o] = (T)u0;
+      a.us[a.gcells + o] = (T)u1;
+      a.us[2 * a.gcells + o] = (T)u2;
+    } else {
+      a.chi[cell] = (T)ch;
+      a.us[cell] = (T)u0;
+      a.us[a.bcells + cell] = (T)u1;
+      a.us[2 * a.bcells + cell] = (T)u2;
+    }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void fill_zero(T* p, long long n) {
+  for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long long)gridDim.x * kNT) p[i] = (T)0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2064,7 +2079,31 @@ hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(mask_eval<T>, dim3((unsigned)blocks), dim3(kNT), 0, s, a);
+  hipLaunchKernelGGL((mask_eval<T, false>), dim3((unsigned)blocks), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mask_grid(const MaskArgs<T>& a, hipStream_t s) {
+  // zero both grids (a fill kernel: no memset node if the caller captures the stream)
+  hipLaunchKernelGGL(fill_zero<T>, dim3(8192), dim3(kNT), 0, s, a.chi, a.gcells);
+  hipLaunchKernelGGL(fill_zero<T>, dim3(8192), dim3(kNT), 0, s, a.us, 3 * a.gcells);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.bcells == 0) return e;
+  long long blocks = (a.bcells + kNT - 1) / kNT;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_keys, dim3((unsigned)blocks), dim3(kNT), 0, s, a.key1, a.key2, a.bcells);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.nt > 0) {
+    hipLaunchKernelGGL((mask_dist<T, 1>), dim3(a.nt), dim3(kNT), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mask_dist<T, 2>), dim3(a.nt), dim3(kNT), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((mask_eval<T, true>), dim3((unsigned)blocks), dim3(kNT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2088,5 +2127,7 @@ template hipError_t launch_sponge_mask<double>(const SpongeArgs<double>&, hipStr
 template hipError_t launch_psample<double>(const PressArgs<double>&, hipStream_t);
 template hipError_t launch_mask<float>(const MaskArgs<float>&, hipStream_t);
 template hipError_t launch_mask<double>(const MaskArgs<double>&, hipStream_t);
+template hipError_t launch_mask_grid<float>(const MaskArgs<float>&, hipStream_t);
+template hipError_t launch_mask_grid<double>(const MaskArgs<double>&, hipStream_t);
 
 }  // namespace fsi

@@ -57,6 +57,10 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 int xfused_grid(int n, long long nlines, int lines_per_group);
 template <typename T>
 hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
+// The same kernels writing chi and u_s into full grids [nz][ny][nx] (gnx, gny,
+// gcells of MaskArgs), zeroed first; key1 / key2 may be any scratch of bcells each.
+template <typename T>
+hipError_t launch_mask_grid(const MaskArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
 template <typename T>

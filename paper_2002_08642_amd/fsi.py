@@ -41,7 +41,9 @@ EXPORTS = [
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
     "fsi_sample_pressure", "fsi_get_pressure_loads", "fsi_get_pressure_box", "fsi_adjoint_set_pressure_seed",
+    "fsi_get_mask_noalloc",
 ]
+NOALLOC_MASK_CELLS = 1 << 20  # FSI_NOALLOC_MASK_CELLS
 
 
 class FsiError(RuntimeError):
@@ -92,6 +94,7 @@ def load_library():
     lib.fsi_step_record.argtypes = [P, ctypes.c_double, I32]
     lib.fsi_adjoint_reset.argtypes = [P]
     lib.fsi_get_mask.argtypes = [P, D, D]
+    lib.fsi_get_mask_noalloc.argtypes = [P, P, P]
     lib.fsi_step.argtypes = [P, ctypes.c_double]
     lib.fsi_step_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.fsi_get_step_info.argtypes = [P, D, D, D, D, D, ctypes.POINTER(ctypes.c_int64)]
@@ -365,6 +368,11 @@ class Solver:
         us = np.zeros((3,) + self.shape3)
         self._check(self.lib.fsi_get_mask(self.ctx, _dptr(chi), _dptr(us)))
         return chi, us
+
+    def mask_noalloc(self, chi_ptr, us_ptr):
+        """fsi_get_mask_noalloc into caller-owned device arrays (addresses as ints,
+        the context's precision, [nz][ny][nx] and [3][nz][ny][nx]); no sync."""
+        self._check(self.lib.fsi_get_mask_noalloc(self.ctx, ctypes.c_void_p(chi_ptr), ctypes.c_void_p(us_ptr)))
 
     def step(self, dt):
         self._check(self.lib.fsi_step(self.ctx, float(dt)))
