@@ -570,7 +570,7 @@ class Engine : public EngineBase {
     memset(chi_h, 0, sizeof(double) * npts);
     memset(us_h, 0, sizeof(double) * 3 * npts);
     if (wing_nt == 0 || bcells == 0) return FSI_OK;
-    FSI_TRY(run_mask());
+    FSI_TRY(run_mask(s));
     std::vector<T> c(bcells), u(3 * bcells);
     FSI_HIP(hipMemcpyAsync(c.data(), chi, sizeof(T) * bcells, hipMemcpyDeviceToHost, s));
     FSI_HIP(hipMemcpyAsync(u.data(), us, sizeof(T) * 3 * bcells, hipMemcpyDeviceToHost, s));
@@ -686,9 +686,24 @@ class Engine : public EngineBase {
     }
     const int cur = (int)(nstep & 1);
     hipEvent_t* ev = timing ? next_events() : nullptr;
-    if (ev) FSI_HIP(hipEventRecord(ev[0], s));
-    if (wing_nt > 0 && bcells > 0) FSI_TRY(run_mask());
-    if (ev) FSI_HIP(hipEventRecord(ev[1], s));
+    // The mask depends only on the wing: it runs on the side stream while P1/P2
+    // transform the velocity, and P3 waits for it.  It starts after everything
+    // queued so far on the context stream (the mesh upload, and the previous
+    // step's P3, which read the mask buffers).
+    const bool wing = wing_nt > 0 && bcells > 0;
+    FSI_TRY(ensure_side());
+    if (wing) {
+      FSI_HIP(hipEventRecord(e_ready, s));
+      FSI_HIP(hipStreamWaitEvent(s2, e_ready, 0));
+      if (ev) FSI_HIP(hipEventRecord(ev[EV_MASK0], s2));
+      FSI_TRY(run_mask(s2));
+      if (ev) FSI_HIP(hipEventRecord(ev[EV_MASK1], s2));
+      FSI_HIP(hipEventRecord(e_mask, s2));
+    } else if (ev) {
+      FSI_HIP(hipEventRecord(ev[EV_MASK0], s));
+      FSI_HIP(hipEventRecord(ev[EV_MASK1], s));
+    }
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P1_0], s));
     // P1: z inverse of u and of omega_x, omega_y (omega = i k x u); the
     // previous step's last pass has already produced it unless u_hat has been
     // replaced or A used since
@@ -701,7 +716,7 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_INV_CURL5, a, 1, s));  // u, omega_x, omega_y
     }
     zs_valid = false;
-    if (ev) FSI_HIP(hipEventRecord(ev[2], s));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P2_0], s));
     // P2: y inverse of the five fields, omega_z = i (kx uy - ky ux) formed on the way
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
@@ -713,7 +728,9 @@ class Engine : public EngineBase {
       a.out_bs = (long long)ny * kxp;
       FSI_HIP(launch_col<T>(COL_INV_WZ, a, nz, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[3], s));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P2_1], s));
+    if (wing) FSI_HIP(hipStreamWaitEvent(s, e_mask, 0));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P3_0], s));
     // P3: x C2R, nonlinear + penalization term, diagnostics, x R2C
     {
       XArgs<T> a = x_base();
@@ -744,6 +761,10 @@ class Engine : public EngineBase {
       a.inv_eta = (T)(1.0 / d.eta);
       FSI_HIP(launch_xfused<T>(a, nfused, s));
     }
+    // the reductions need only P3's partials: they run on the side stream
+    // alongside the rest of the step, and P5 (which reads dt_n) waits for them
+    FSI_HIP(hipEventRecord(e_x, s));
+    FSI_HIP(hipStreamWaitEvent(s2, e_x, 0));
     // sponge: S = chi_sp omega from the x-spectral omega left in fields 3-5 of B
     // (x inverse, mask, x forward, back into the same fields)
     if (sponge_on && nx == 512) {  // register transforms, in place
@@ -768,9 +789,10 @@ class Engine : public EngineBase {
       FSI_HIP(launch_sponge_mask<T>(m, s));
       FSI_HIP(launch_xplain<T>(X_R2C, 3, a, npart, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[4], s));
-    // diagnostics and dt_n
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P3_1], s));
+    // diagnostics and dt_n (side stream)
     {
+      if (ev) FSI_HIP(hipEventRecord(ev[EV_RED0], s2));
       FinalArgs f;
       f.partials = partials;
       f.np = nfused;
@@ -782,15 +804,16 @@ class Engine : public EngineBase {
       f.cap = adaptive ? std::min(c_eta * d.eta, dt_max) : 0.0;
       f.dV = dV;
       f.inv_eta = 1.0 / d.eta;
-      FSI_HIP(launch_finalize(f, s));
+      FSI_HIP(launch_finalize(f, s2));
+      // the diagnostics and dt_n are final here: the read-back does not wait for
+      // the last two passes, so the caller can prepare the next step meanwhile
+      FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s2));
+      if (!info_ev) FSI_HIP(hipEventCreateWithFlags(&info_ev, hipEventDisableTiming));
+      FSI_HIP(hipEventRecord(info_ev, s2));
+      info_pending = true;
+      if (ev) FSI_HIP(hipEventRecord(ev[EV_RED1], s2));
+      FSI_HIP(hipEventRecord(e_fin, s2));
     }
-    // the diagnostics and dt_n are final here: the read-back does not wait for
-    // the last two passes, so the caller can prepare the next step meanwhile
-    FSI_HIP(hipMemcpyAsync(sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-    if (!info_ev) FSI_HIP(hipEventCreateWithFlags(&info_ev, hipEventDisableTiming));
-    FSI_HIP(hipEventRecord(info_ev, s));
-    info_pending = true;
-    if (ev) FSI_HIP(hipEventRecord(ev[5], s));
     // P4: y forward of G, truncated to the y band
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
@@ -814,7 +837,9 @@ class Engine : public EngineBase {
       a.csp_inv = (T)(1.0 / csp);
       FSI_HIP(launch_col<T>(COL_FWD_SPONGE, a, 1, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[6], s));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P4_1], s));
+    FSI_HIP(hipStreamWaitEvent(s, e_fin, 0));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P5_0], s));
     // P5: z forward, dealias, Leray projection, integrating-factor AB2
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
@@ -837,7 +862,7 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_FWD_UPDATE_Z, a, 1, s));
       zs_valid = true;
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[7], s));
+    if (ev) FSI_HIP(hipEventRecord(ev[EV_P5_1], s));
     ++nstep;
     have_prev = true;
     p_ready = d.fsi_pressure && wing_nt > 0 && bcells > 0;
@@ -1074,7 +1099,7 @@ class Engine : public EngineBase {
         tgrad_cap = wing_nt;
         FSI_TRY(alloc(&tgrad_, 18LL * tgrad_cap));
       }
-      FSI_TRY(run_mask());
+      FSI_TRY(run_mask(s));
     }
     // pressure seed: lambda_Pi on the grid (zero outside the box), its normalized R2C
     const bool seed = seed_pending && d.fsi_pressure && wing && pcells > 0;
@@ -1259,11 +1284,17 @@ class Engine : public EngineBase {
 
   fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) override {
     FSI_HIP(hipStreamSynchronize(s));
+    if (s2) FSI_HIP(hipStreamSynchronize(s2));
+    // (start, end) event of each pass: mask (side stream), P1, P2, P3 (+ sponge
+    // x pass), reductions and dt (side stream), P4 (+ sponge z pass), P5
+    static const int span[FSI_NPASS][2] = {{EV_MASK0, EV_MASK1}, {EV_P1_0, EV_P2_0}, {EV_P2_0, EV_P2_1},
+                                           {EV_P3_0, EV_P3_1},   {EV_RED0, EV_RED1}, {EV_P3_1, EV_P4_1},
+                                           {EV_P5_0, EV_P5_1}};
     for (int p = 0; p < FSI_NPASS; ++p) ms[p] = 0.0;
     for (int k = 0; k < ev_used; ++k) {
       for (int p = 0; p < FSI_NPASS; ++p) {
         float e = 0.f;
-        FSI_HIP(hipEventElapsedTime(&e, events[k][p], events[k][p + 1]));
+        FSI_HIP(hipEventElapsedTime(&e, events[k][span[p][0]], events[k][span[p][1]]));
         ms[p] += e;
       }
     }
@@ -1302,6 +1333,15 @@ class Engine : public EngineBase {
 
   void release() {
     if (s || uh) (void)hipStreamSynchronize(s);
+    if (s2) {
+      (void)hipStreamSynchronize(s2);
+      (void)hipStreamDestroy(s2);
+      s2 = nullptr;
+    }
+    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin}) {
+      if (*e) (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
     free_dev(uh);
     free_dev(nh);
     free_dev(A);
@@ -1557,7 +1597,7 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
-  fsi_status run_mask() {
+  fsi_status run_mask(hipStream_t st) {
     MaskArgs<T> m;
     memset(&m, 0, sizeof(m));
     m.x = dx_;
@@ -1582,7 +1622,16 @@ class Engine : public EngineBase {
     m.tw = d.tw;
     m.h = d.h;
     m.profile = d.mask_profile;
-    FSI_HIP(launch_mask<T>(m, s));
+    FSI_HIP(launch_mask<T>(m, st));
+    return FSI_OK;
+  }
+
+  // Side stream of the step (non-blocking, default priority) and the events
+  // that order it against the context stream.
+  fsi_status ensure_side() {
+    if (s2) return FSI_OK;
+    FSI_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin}) FSI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return FSI_OK;
   }
 
@@ -1597,7 +1646,7 @@ class Engine : public EngineBase {
   hipEvent_t* next_events() {
     if (ev_used >= 4096) return nullptr;
     if (ev_used == (int)events.size()) {
-      std::array<hipEvent_t, FSI_NPASS + 1> e;
+      std::array<hipEvent_t, EV_COUNT> e;
       for (auto& h : e)
         if (hipEventCreate(&h) != hipSuccess) return nullptr;
       events.push_back(e);
@@ -1632,6 +1681,11 @@ class Engine : public EngineBase {
   size_t stage_cap = 0;
   hipEvent_t stage_ev = nullptr;
   hipEvent_t info_ev = nullptr;  // recorded after the step's read-back of the device scalars
+  hipStream_t s2 = nullptr;      // side stream of the step (mask, reductions)
+  hipEvent_t e_ready = nullptr, e_mask = nullptr, e_x = nullptr, e_fin = nullptr;
+  // timing events of one step
+  enum { EV_MASK0, EV_MASK1, EV_P1_0, EV_P2_0, EV_P2_1, EV_P3_0, EV_P3_1, EV_RED0, EV_RED1, EV_P4_1, EV_P5_0,
+         EV_P5_1, EV_COUNT };
   bool info_pending = false;
   bool stage_pending = false;
   int bx0 = 0, by0 = 0, bz0 = 0, bnx = 0, bny = 0, bnz = 0;
@@ -1665,7 +1719,7 @@ class Engine : public EngineBase {
   // timing
   bool timing = false;
   int ev_used = 0;
-  std::vector<std::array<hipEvent_t, FSI_NPASS + 1>> events;
+  std::vector<std::array<hipEvent_t, EV_COUNT>> events;
 };
 
 EngineBase* make_engine_f32() { return new Engine<float>(); }

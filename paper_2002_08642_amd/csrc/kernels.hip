@@ -1314,7 +1314,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
             a.up[2 * a.pcells + cell] = uz;
           }
         }
-        const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        const double u2 = (double)(ux * ux + uy * uy + uz * uz);
         aE += u2;
         aM = fmax(aM, u2);
         g0[k] = gx;
@@ -1418,7 +1418,8 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
     const T wx = P[1][j].im, wy = P[2][j].re, wz = P[2][j].im;
     g[j] = mk<T>(uy * wz - uz * wy, uz * wx - ux * wz);
     gz[j] = ux * wy - uy * wx;
-    const double u2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+    // |u|^2 as a product in the bulk precision, summed per lane in FP64
+    const double u2 = (double)(ux * ux + uy * uy + uz * uz);
     aE += u2;
     aM = fmax(aM, u2);
   }

@@ -27,11 +27,39 @@ __device__ __forceinline__ int xslot1(int x1, int l) { return x1 * 72 + l; }
 __device__ __forceinline__ int xslot2(int x1, int y1, int l1) { return x1 * 72 + y1 * 9 + l1; }
 constexpr int kXBuf = 576;
 
-// inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1
+// The inverse radix-8 butterfly over r of a band-limited spectrum: inputs
+// v[3] = Z[lane + 192] and v[4] = Z[lane + 256] lie outside the 2/3 band of
+// every lane (170 < lane + 192 < 342) and are zero.  Written out without them:
+// IEEE rules keep the compiler from folding x + 0 and 0 - x itself.  Same
+// values as Bfly<T, 8, +1> on such input (up to the sign of zero results).
+template <typename T>
+__device__ __forceinline__ void bfly8_inv_zero34(cpx<T> (&v)[8]) {
+  // even half {v0, v2, 0, v6}
+  const cpx<T> s26 = v[2] + v[6], d26 = mul_i<T, 1>(v[2] - v[6]);
+  const cpx<T> e0 = v[0] + s26, e2 = v[0] - s26, e1 = v[0] + d26, e3 = v[0] - d26;
+  // odd half {v1, 0, v5, v7}
+  const cpx<T> s15 = v[1] + v[5], d15 = v[1] - v[5], i7 = mul_i<T, 1>(v[7]);
+  const cpx<T> o0 = s15 + v[7], o2 = s15 - v[7], o1 = d15 - i7, o3 = d15 + i7;
+  const T h = (T)0.70710678118654752440084436210484903928;
+  const cpx<T> w1 = mk(h * (o1.re - o1.im), h * (o1.im + o1.re));
+  const cpx<T> w2 = mul_i<T, 1>(o2);
+  const cpx<T> w3 = mk(h * (-o3.re - o3.im), h * (-o3.im + o3.re));
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + w1;
+  v[5] = e1 - w1;
+  v[2] = e2 + w2;
+  v[6] = e2 - w2;
+  v[3] = e3 + w3;
+  v[7] = e3 - w3;
+}
+
+// inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1;
+// v[3], v[4] must be zero on entry (pack512 leaves them so)
 template <typename T>
 __device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tIB, const cpx<T>* tC) {
   const int hi = lane >> 3, lo = lane & 7;
-  Bfly<T, 8, 1>::run(v);
+  bfly8_inv_zero34<T>(v);
 #pragma unroll
   for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tIB[64 * j + lane]);
 #pragma unroll
