@@ -217,6 +217,17 @@ fsi_status fsi_sample_pressure(fsi_ctx* ctx, int32_t n, const double* pts, doubl
  * fsi_sample_pressure.  Synchronizes. */
 fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp);
 
+/* Sec. 4.1, staggered-scheme paragraph, in the paper's order: after the fluid
+ * step u^n -> u^{n+1}, the pressure p^{n+1} of the new velocity (with the mask
+ * of the current wing, i.e. still the wing of t^n) replaces the step's p^n, so
+ * that fsi_sample_pressure, fsi_get_pressure_loads and fsi_get_pressure_box
+ * return it.  One more evaluation of the nonlinear term (mask, inverse
+ * transforms, fused x pass, forward transforms, Pi_hat = -i k.N'/|k|^2 with
+ * N' = u x omega - (chi/eta)(u - u_s)); u_hat, the Adams-Bashforth history,
+ * dt and the step diagnostics are unchanged.  Queued on the stream.
+ * FSI_ESTATE if FSI mode is off or no wing is set. */
+fsi_status fsi_eval_pressure(fsi_ctx* ctx);
+
 /* The pressure box of the current mesh (box0[3]: grid index of its first
  * cell, boxn[3]: cells per axis) and, if p is not NULL, p = Pi - |u|^2/2 of
  * the last step at its cells, p[boxn[2]][boxn[1]][boxn[0]] (the data the host
@@ -259,13 +270,16 @@ fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev);
 /* Zero the cotangent state (the start of a reverse sweep). Synchronizes. */
 fsi_status fsi_adjoint_reset(fsi_ctx* ctx);
 
-/* Forward step with its tape: saves the state at the start of the step in
- * tape_slot (as fsi_save_state) and takes the step (as fsi_step), so that
- * fsi_step_adjoint(tape_slot, ...) can reverse it later.  Errors as the two. */
+/* Forward step with its tape: saves the velocity spectrum u_hat^n at the start
+ * of the step in tape_slot (all that fsi_step_adjoint needs: it re-derives u and
+ * omega from it) and takes the step (as fsi_step), so that
+ * fsi_step_adjoint(tape_slot, ...) can reverse it later.  A tape slot is not a
+ * full state: fsi_load_state refuses it (FSI_ESTATE) until fsi_save_state
+ * overwrites it.  Errors as fsi_save_state and fsi_step. */
 fsi_status fsi_step_record(fsi_ctx* ctx, double dt, int32_t tape_slot);
 
-/* Reverse one step. tape_slot holds the state saved (fsi_save_state) at the
- * start of the step; the wing of that step must be set (fsi_set_wing); dt is
+/* Reverse one step. tape_slot holds the state saved (fsi_step_record or
+ * fsi_save_state) at the start of the step; the wing of that step must be set (fsi_set_wing); dt is
  * the step's dt, dt_prev the one before (ignored when first = 1, i.e. the step
  * was an integrating-factor Euler step). dJdF[3] is the derivative of the
  * objective with respect to the force F of that step. On return the cotangent

@@ -4,9 +4,11 @@ vertical axis (Sec. 4.1, staggered scheme paragraph; wing model of Sec. 2).
 One coupled step n (state: fluid at t^n, wing q^n = [x^n, v^n]):
  1. the fluid step uses the mask and solid velocity of the wing at t^n
     (fsi_set_wing, fsi_step) and yields the force F^n;
- 2. the pressure of that step gives the vertex loads (fsi_get_pressure_loads;
-    reading: the structure is advanced with p^n, so no second nonlinear
-    evaluation is needed per step);
+ 2. the pressure gives the vertex loads (fsi_get_pressure_loads): order
+    "lagged" (default reading) uses p^n of that step, so no second nonlinear
+    evaluation is needed per step; order "paper" first replaces it by
+    p^{n+1} of the new velocity (fsi_eval_pressure, the wing still at t^n),
+    as the staggered-scheme paragraph orders it;
  3. the wing advances to t^{n+1} by the BDF2/Newton step of the native
     mass-spring solver (fsi_ms_step) with those loads, its root vertices
     clamped to the rigid kinematics at t^{n+1} and the bending angles measured
@@ -28,7 +30,10 @@ class FlexibleWingFSI:
     driven at its root by the revolving-plate kinematics ``kin`` (alpha, omega,
     t_ramp, axis_point, law)."""
 
-    def __init__(self, solver, wing, bend_ijk, bend_kb, bend_axis, kin, tol=1e-10, max_iter=30):
+    def __init__(self, solver, wing, bend_ijk, bend_kb, bend_axis, kin, tol=1e-10, max_iter=30, order="lagged"):
+        if order not in ("lagged", "paper"):
+            raise ValueError("order must be 'lagged' or 'paper'")
+        self.order = order
         self.s = solver
         self.w = wing
         self.kin = kin
@@ -68,6 +73,8 @@ class FlexibleWingFSI:
         self.s.set_wing(x, v, self.tri)
         self.s.step(dt)
         F = self.s.info()["F"]
+        if self.order == "paper":
+            self.s.eval_pressure()
         loads, _ = self.s.pressure_loads()
         t1 = self.t + dt
         xc, vc = self._root_pose(t1, self.clamped)
@@ -153,10 +160,13 @@ class HingeRollout:
         self.ms.set_rest(self._frame(0.0, alpha))
         self.ms.set_history(None)
 
-    def _step(self, n, alpha, record):
+    def _step(self, n, alpha, record, tape=None):
         x, v = self.ms.state()
         self.s.set_wing(x, v, self.tri)
-        self.s.step(self.dts[n])
+        if tape is None:
+            self.s.step(self.dts[n])
+        else:  # keep u_hat^n in tape slot `tape` for the reverse step
+            self.s.step_record(self.dts[n], tape)
         F = self.s.info()["F"]
         loads, _ = self.s.pressure_loads()
         rec = None
@@ -208,8 +218,7 @@ class HingeRollout:
                 self.ms.set_history(*prev)
             recs = []
             for n in range(n0, n1):
-                self.s.save(tape0 + n - n0)
-                recs.append(self._step(n, alpha, True)[1])
+                recs.append(self._step(n, alpha, True, tape=tape0 + n - n0)[1])
             for n in reversed(range(n0, n1)):
                 rec = recs[n - n0]
                 t1 = self.times[n] + self.dts[n]

@@ -36,6 +36,12 @@ __device__ __forceinline__ int adj_sig(int l, int q) { return l == 0 ? q : 9 + (
 __device__ __forceinline__ int adj_sig_line(int r) { return r < 9 ? 0 : 1; }
 __device__ __forceinline__ int adj_sig_field(int r) { return r < 9 ? r : (r == 9 ? 8 : r - 10); }
 
+// Input field f: u, omega (f < 6) from the step's tape when there is one
+template <typename T>
+__device__ __forceinline__ const cpx<T>* adj_in(const XAdjArgs<T>& a, int f) {
+  return (f < 6 && a.utape) ? a.utape + (long long)f * a.sfs : a.spec + (long long)f * a.sfs;
+}
+
 template <typename T, int NT, int MAXE>
 __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -60,10 +66,8 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
       const int x = it % n, j = it / n;
       const int ra = 2 * j, rb = 2 * j + 1;
       if (x <= K) {
-        const cpx<T> A =
-            a.spec[adj_sig_field(ra) * a.sfs + (long long)(line0 + adj_sig_line(ra)) * a.ld + x];
-        const cpx<T> B =
-            a.spec[adj_sig_field(rb) * a.sfs + (long long)(line0 + adj_sig_line(rb)) * a.ld + x];
+        const cpx<T> A = adj_in(a, adj_sig_field(ra))[(long long)(line0 + adj_sig_line(ra)) * a.ld + x];
+        const cpx<T> B = adj_in(a, adj_sig_field(rb))[(long long)(line0 + adj_sig_line(rb)) * a.ld + x];
         if (x == 0) buf[j] = mk<T>(A.re, B.re);
         else {
           buf[x * RI + j] = mk<T>(A.re - B.im, A.im + B.re);
@@ -177,8 +181,7 @@ __global__ __launch_bounds__(NT) void xpass_adj(XAdjArgs<T> a) {
 
 template <typename T>
 __device__ __forceinline__ void xadj_load(const XAdjArgs<T>& a, int line, int f, int lane, Raw512<T>& w) {
-  load512<T>(a.spec + (long long)f * a.sfs + (long long)line * a.ld,
-             a.spec + (long long)(f + 1) * a.sfs + (long long)line * a.ld, lane, w);
+  load512<T>(adj_in(a, f) + (long long)line * a.ld, adj_in(a, f + 1) + (long long)line * a.ld, lane, w);
 }
 
 // One line: inverse transforms of the 8 paired inputs (lambda_Gz given in the

@@ -204,6 +204,11 @@ fsi_status fsi_get_pressure_loads(fsi_ctx* ctx, double* loads, double* dp) {
   return ctx->eng->pressure_loads(loads, dp);
 }
 
+fsi_status fsi_eval_pressure(fsi_ctx* ctx) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->eval_pressure();
+}
+
 fsi_status fsi_get_pressure_box(fsi_ctx* ctx, int32_t* box0, int32_t* boxn, double* p) {
   if (guard(ctx) != FSI_OK || !box0 || !boxn) return FSI_EINVAL;
   int b0[3], bn[3];
@@ -253,9 +258,7 @@ fsi_status fsi_adjoint_reset(fsi_ctx* ctx) {
 
 fsi_status fsi_step_record(fsi_ctx* ctx, double dt, int32_t tape_slot) {
   if (guard(ctx) != FSI_OK) return FSI_EINVAL;
-  const fsi_status st = ctx->eng->save_state(tape_slot);
-  if (st != FSI_OK) return st;
-  return ctx->eng->step(false, dt, 0.0, 0.0, 0.0);
+  return ctx->eng->step_record(dt, tape_slot);
 }
 
 fsi_status fsi_adjoint_get(fsi_ctx* ctx, double* lam_uhat, double* lam_nprev) {

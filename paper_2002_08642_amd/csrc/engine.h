@@ -32,6 +32,8 @@ class EngineBase {
   virtual fsi_status fft_r2c(const double* f, double* fh) = 0;
   virtual fsi_status fft_c2r(const double* fh, double* f) = 0;
   virtual fsi_status save_state(int slot) = 0;
+  virtual fsi_status save_tape(int slot) = 0;
+  virtual fsi_status step_record(double dt, int slot) = 0;
   virtual fsi_status load_state(int slot) = 0;
   virtual fsi_status synchronize() = 0;
   virtual fsi_status adjoint_set(const double* lu, const double* lnp) = 0;
@@ -40,6 +42,7 @@ class EngineBase {
                                   double* dJdv) = 0;
   virtual fsi_status sample_pressure(int n, const double* pts, double* p) = 0;
   virtual fsi_status pressure_loads(double* loads, double* dp) = 0;
+  virtual fsi_status eval_pressure() = 0;
   virtual fsi_status pressure_box(int box0[3], int boxn[3], double* p) = 0;
   virtual fsi_status set_pressure_seed(const int box0[3], const int boxn[3], const double* lam) = 0;
   virtual fsi_status set_timing(bool on) = 0;

@@ -313,10 +313,13 @@ class Engine : public EngineBase {
         }
       }
     }
-    // stage the mesh through pinned memory
+    // stage the mesh through pinned memory; it is uploaded in one copy on the
+    // side stream (the mask that needs it runs there; work on the context
+    // stream that reads it waits for the upload's event)
+    FSI_TRY(ensure_side());
     const size_t need = sizeof(double) * 6 * (size_t)nv + sizeof(int) * 3 * (size_t)nt;
     if (need > stage_cap) {
-      FSI_HIP(hipStreamSynchronize(s));
+      FSI_TRY(sync_both());
       if (stage) FSI_HIP(hipHostFree(stage));
       stage = nullptr;
       FSI_HIP(hipHostMalloc(&stage, need * 2, hipHostMallocDefault));
@@ -330,16 +333,11 @@ class Engine : public EngineBase {
     memcpy(sv, v, sizeof(double) * 3 * (size_t)nv);
     memcpy(st, tri, sizeof(int) * 3 * (size_t)nt);
     tri_host.assign(tri, tri + 3 * (size_t)nt);
-    if (nv > mesh_vcap || nt > mesh_tcap) {
-      FSI_HIP(hipStreamSynchronize(s));
-      free_dev(dx_);
-      free_dev(dv_);
-      free_dev(dtri_);
-      mesh_vcap = std::max(nv, mesh_vcap) * 2;
-      mesh_tcap = std::max(nt, mesh_tcap) * 2;
-      FSI_TRY(alloc(&dx_, 3LL * mesh_vcap));
-      FSI_TRY(alloc(&dv_, 3LL * mesh_vcap));
-      FSI_TRY(alloc(&dtri_, 3LL * mesh_tcap));
+    if ((long long)need > mesh_cap) {
+      FSI_TRY(sync_both());
+      free_dev(dmesh_);
+      mesh_cap = 2 * (long long)need;
+      FSI_TRY(alloc(&dmesh_, mesh_cap));
     }
     if (d.fsi_pressure) {
       const long long pc = (long long)qn[0] * qn[1] * qn[2];
@@ -359,7 +357,7 @@ class Engine : public EngineBase {
       }
     }
     if (cells > box_cap) {
-      FSI_HIP(hipStreamSynchronize(s));
+      FSI_TRY(sync_both());
       free_dev(key1);
       free_dev(key2);
       free_dev(chi);
@@ -370,12 +368,16 @@ class Engine : public EngineBase {
       FSI_TRY(alloc(&chi, box_cap));
       FSI_TRY(alloc(&us, 3 * box_cap));
     }
-    FSI_HIP(hipMemcpyAsync(dx_, sx, sizeof(double) * 3 * (size_t)nv, hipMemcpyHostToDevice, s));
-    FSI_HIP(hipMemcpyAsync(dv_, sv, sizeof(double) * 3 * (size_t)nv, hipMemcpyHostToDevice, s));
-    FSI_HIP(hipMemcpyAsync(dtri_, st, sizeof(int) * 3 * (size_t)nt, hipMemcpyHostToDevice, s));
+    // device views with the staging layout: x [nv][3], v [nv][3], tri [nt][3]
+    dx_ = reinterpret_cast<double*>(dmesh_);
+    dv_ = dx_ + 3 * (size_t)nv;
+    dtri_ = reinterpret_cast<int*>(dv_ + 3 * (size_t)nv);
+    FSI_HIP(hipMemcpyAsync(dmesh_, stage, need, hipMemcpyHostToDevice, s2));
     if (!stage_ev) FSI_HIP(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
-    FSI_HIP(hipEventRecord(stage_ev, s));
+    FSI_HIP(hipEventRecord(stage_ev, s2));
     stage_pending = true;
+    FSI_HIP(hipEventRecord(e_up, s2));
+    mesh_pending = true;
     wing_nt = nt;
     wing_nv = nv;
     bx0 = i0[0];
@@ -597,6 +599,7 @@ class Engine : public EngineBase {
             " cells of the fixed scratch";
       return FSI_EINVAL;
     }
+    FSI_TRY(mesh_wait(s));
     MaskArgs<T> m;
     memset(&m, 0, sizeof(m));
     m.x = dx_;
@@ -718,12 +721,13 @@ class Engine : public EngineBase {
     zs_valid = false;
     if (ev) FSI_HIP(hipEventRecord(ev[EV_P2_0], s));
     // P2: y inverse of the five fields, omega_z = i (kx uy - ky ux) formed on the way
+    // (into the step's tape when recording: the reverse step reads u, omega there)
     {
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
       a.in = A;
       a.in_fs = Alen;
       a.in_bs = C1;
-      a.out = B;
+      a.out = rec_bt ? rec_bt : B;
       a.out_fs = Blen;
       a.out_bs = (long long)ny * kxp;
       FSI_HIP(launch_col<T>(COL_INV_WZ, a, nz, s));
@@ -732,35 +736,7 @@ class Engine : public EngineBase {
     if (wing) FSI_HIP(hipStreamWaitEvent(s, e_mask, 0));
     if (ev) FSI_HIP(hipEventRecord(ev[EV_P3_0], s));
     // P3: x C2R, nonlinear + penalization term, diagnostics, x R2C
-    {
-      XArgs<T> a = x_base();
-      a.spec = B;
-      a.sfs = Blen;
-      a.partials = partials;
-      if (wing_nt > 0 && bcells > 0) {
-        a.chi = chi;
-        a.us = us;
-        a.bx0 = bx0;
-        a.by0 = by0;
-        a.bz0 = bz0;
-        a.bnx = bnx;
-        a.bny = bny;
-        a.bnz = bnz;
-        a.bcells = bcells;
-        if (d.fsi_pressure) {
-          a.up = up_;
-          a.px0 = px0;
-          a.py0 = py0;
-          a.pz0 = pz0;
-          a.pnx = pnx;
-          a.pny = pny;
-          a.pnz = pnz;
-          a.pcells = pcells;
-        }
-      }
-      a.inv_eta = (T)(1.0 / d.eta);
-      FSI_HIP(launch_xfused<T>(a, nfused, s));
-    }
+    FSI_HIP(launch_xfused<T>(p3_args(), nfused, s));
     // the reductions need only P3's partials: they run on the side stream
     // alongside the rest of the step, and P5 (which reads dt_n) waits for them
     FSI_HIP(hipEventRecord(e_x, s));
@@ -869,6 +845,99 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // Arguments of the fused x pass: mask sub-box, and the pressure box in FSI mode
+  XArgs<T> p3_args() {
+    XArgs<T> a = x_base();
+    a.spec = rec_bt ? rec_bt : B;  // u, omega (the step's tape when recording)
+    a.gout = B;                    // G
+    a.sfs = Blen;
+    a.partials = partials;
+    if (wing_nt > 0 && bcells > 0) {
+      a.chi = chi;
+      a.us = us;
+      a.bx0 = bx0;
+      a.by0 = by0;
+      a.bz0 = bz0;
+      a.bnx = bnx;
+      a.bny = bny;
+      a.bnz = bnz;
+      a.bcells = bcells;
+      if (d.fsi_pressure) {
+        a.up = up_;
+        a.px0 = px0;
+        a.py0 = py0;
+        a.pz0 = pz0;
+        a.pnx = pnx;
+        a.pny = pny;
+        a.pnz = pnz;
+        a.pcells = pcells;
+      }
+    }
+    a.inv_eta = (T)(1.0 / d.eta);
+    return a;
+  }
+
+  // Total pressure of the current velocity with the current wing's mask,
+  // without a step: the nonlinear term's passes (mask, z/y inverse, fused x
+  // pass, y forward) and a z forward that keeps only Pi_hat = -i k.N'/|k|^2.
+  // The state (u_hat, N_hat history, dt, diagnostics) is unchanged.
+  fsi_status eval_pressure() override {
+    if (!d.fsi_pressure) {
+      err = "FSI mode (fsi_pressure) is off";
+      return FSI_ESTATE;
+    }
+    if (wing_nt == 0 || bcells == 0) {
+      err = "no wing";
+      return FSI_ESTATE;
+    }
+    FSI_TRY(run_mask(s));
+    if (!zs_valid) {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = uh;
+      a.in_fs = clen;
+      a.out = A;
+      a.out_fs = Alen;
+      FSI_HIP(launch_col<T>(COL_INV_CURL5, a, 1, s));
+    }
+    zs_valid = false;  // P4 below overwrites fields 0-2 of A
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = A;
+      a.in_fs = Alen;
+      a.in_bs = C1;
+      a.out = B;
+      a.out_fs = Blen;
+      a.out_bs = (long long)ny * kxp;
+      FSI_HIP(launch_col<T>(COL_INV_WZ, a, nz, s));
+    }
+    FSI_HIP(launch_xfused<T>(p3_args(), nfused, s));  // partials written, not reduced
+    {
+      ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
+      a.in = B;
+      a.in_fs = Blen;
+      a.in_bs = (long long)ny * kxp;
+      a.out = A;
+      a.out_fs = Alen;
+      a.out_bs = C1;
+      a.nf = 3;
+      a.scale = (T)1;
+      FSI_HIP(launch_col<T>(COL_FWD_PLAIN, a, nz, s));
+    }
+    {
+      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+      a.in = A;
+      a.in_fs = Alen;
+      a.out = nullptr;  // projection computed, only Pi_hat stored
+      a.cfs = clen;
+      a.nf = 3;
+      a.scale = (T)(1.0 / (double)npts);
+      a.pi = pi_;
+      FSI_HIP(launch_col<T>(COL_FWD_PROJECT, a, 1, s));
+    }
+    p_ready = true;
+    return FSI_OK;
+  }
+
   fsi_status step_info(double F[3], double* dt, double* E, double* umax, double* t, long long* ns) override {
     if (info_pending) FSI_HIP(hipEventSynchronize(info_ev));
     else FSI_HIP(hipStreamSynchronize(s));
@@ -931,6 +1000,64 @@ class Engine : public EngineBase {
     sl.nstep = nstep;
     sl.have_prev = have_prev;
     sl.used = true;
+    sl.tape_only = false;
+    sl.bt_valid = false;
+    return FSI_OK;
+  }
+
+  // A tape entry for the reverse step: only u_hat (the reverse step re-derives
+  // u and omega from it; the Adams-Bashforth history is not needed there)
+  fsi_status save_tape(int slot) override {
+    if (slot < 0 || slot >= (int)slots.size()) {
+      err = "slot out of range";
+      return FSI_EINVAL;
+    }
+    Slot& sl = slots[slot];
+    if (!sl.uh) {
+      FSI_TRY(alloc(&sl.uh, 3 * clen));
+      FSI_TRY(alloc(&sl.nh, 3 * clen));
+      FSI_TRY(alloc(&sl.sc, 1));
+    }
+    FSI_HIP(hipMemcpyAsync(sl.uh, uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
+    sl.nstep = nstep;
+    sl.have_prev = have_prev;
+    sl.used = true;
+    sl.tape_only = true;
+    sl.bt_valid = false;
+    return FSI_OK;
+  }
+
+  // Forward step with its tape.  Without the sponge the step's y-inverse pass
+  // writes u and omega (x spectral, y and z physical: 6 fields of the B layout)
+  // straight into the slot and the fused x pass reads them there, so the tape
+  // costs no copy and the reverse step skips re-deriving u and omega (one
+  // z-inverse and six y-inverse transforms).  With the sponge (its x pass
+  // works in place on omega), or if the slot's 6 fields cannot be allocated,
+  // the tape is u_hat (save_tape).
+  fsi_status step_record(double dt, int slot) override {
+    if (slot < 0 || slot >= (int)slots.size()) {
+      err = "slot out of range";
+      return FSI_EINVAL;
+    }
+    Slot& sl = slots[slot];
+    if (!sponge_on && !sl.bt) {
+      void* q = nullptr;
+      if (hipMalloc(&q, sizeof(cpx<T>) * 6 * (size_t)Blen) == hipSuccess) sl.bt = (cpx<T>*)q;
+      else (void)hipGetLastError();
+    }
+    if (sponge_on || !sl.bt) {
+      FSI_TRY(save_tape(slot));
+      return step(false, dt, 0.0, 0.0, 0.0);
+    }
+    sl.used = false;  // until the step has written it
+    rec_bt = sl.bt;
+    const fsi_status st = step(false, dt, 0.0, 0.0, 0.0);
+    rec_bt = nullptr;
+    if (st != FSI_OK) return st;
+    sl.used = true;
+    sl.tape_only = true;
+    sl.bt_valid = true;
+    sl.nstep = nstep - 1;
     return FSI_OK;
   }
 
@@ -942,6 +1069,10 @@ class Engine : public EngineBase {
     Slot& sl = slots[slot];
     if (!sl.used) {
       err = "slot is empty";
+      return FSI_ESTATE;
+    }
+    if (sl.tape_only) {
+      err = "slot holds a tape entry of fsi_step_record (velocity only), not a full state";
       return FSI_ESTATE;
     }
     FSI_HIP(hipMemcpyAsync(uh, sl.uh, sizeof(cpx<T>) * 3 * clen, hipMemcpyDeviceToDevice, s));
@@ -1117,13 +1248,16 @@ class Engine : public EngineBase {
     // inverse transforms: u, omega of the taped state, and the update and
     // projection transposes with mu = P(lambda_N)/(m_k N^3) followed by
     // lambda_G = C2R(mu) in one pass (z inverse of mu from registers)
+    const bool taped = slots[slot].bt_valid;  // u, omega recorded by the forward step
     {
-      ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
-      a.in = slots[slot].uh;
-      a.in_fs = clen;
-      a.out = A9;
-      a.out_fs = Alen;
-      FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
+      if (!taped) {
+        ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
+        a.in = slots[slot].uh;
+        a.in_fs = clen;
+        a.out = A9;
+        a.out_fs = Alen;
+        FSI_HIP(launch_col<T>(COL_INV_CURL, a, 1, s));
+      }
       ColArgs<T> m = col_base(pz, twz, nz, Kz, C1, C1);
       m.uh = lu_;
       m.nh = lnp_;
@@ -1146,20 +1280,23 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_ADJ_MU, m, 1, s));
     }
     {
+      // y inverse of u, omega and lambda_G (9 fields), or of lambda_G alone
+      // when u, omega come from the tape
       ColArgs<T> a = col_base(py, twy, ny, Ky, kx1, kxp);
-      a.in = A9;
+      a.in = taped ? A9 + 6 * Alen : A9;
       a.in_fs = Alen;
       a.in_bs = C1;
-      a.out = B9;
+      a.out = taped ? B9 + 6 * Blen : B9;
       a.out_fs = Blen;
       a.out_bs = (long long)ny * kxp;
-      a.nf = 9;
+      a.nf = taped ? 3 : 9;
       FSI_HIP(launch_col<T>(COL_INV_PLAIN, a, nz, s));
     }
     {
       XAdjArgs<T> a;
       memset(&a, 0, sizeof(a));
       a.spec = B9;
+      a.utape = taped ? slots[slot].bt : nullptr;
       a.sfs = Blen;
       a.ld = kxp;
       a.nlines = ny * nz;
@@ -1276,9 +1413,16 @@ class Engine : public EngineBase {
   }
 
   fsi_status set_timing(bool on) override {
-    FSI_HIP(hipStreamSynchronize(s));
+    FSI_TRY(sync_both());
     timing = on;
     ev_used = 0;
+    // the events of the next kEvPool steps are created here, not inside the
+    // steps being timed
+    while (on && (int)events.size() < kEvPool) {
+      std::array<hipEvent_t, EV_COUNT> e;
+      for (auto& h : e) FSI_HIP(hipEventCreate(&h));
+      events.push_back(e);
+    }
     return FSI_OK;
   }
 
@@ -1311,6 +1455,9 @@ class Engine : public EngineBase {
     long long nstep = 0;
     bool have_prev = false;
     bool used = false;
+    bool tape_only = false;  // u_hat only (fsi_step_record)
+    cpx<T>* bt = nullptr;    // u, omega of a recorded step, 6 fields of the B layout
+    bool bt_valid = false;   // bt holds the tape (else uh does)
   };
 
   template <typename P>
@@ -1338,7 +1485,7 @@ class Engine : public EngineBase {
       (void)hipStreamDestroy(s2);
       s2 = nullptr;
     }
-    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin}) {
+    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin, &e_up}) {
       if (*e) (void)hipEventDestroy(*e);
       *e = nullptr;
     }
@@ -1356,9 +1503,9 @@ class Engine : public EngineBase {
     free_dev(spg_);
     free_dev(tsp_);
     free_dev(spadj_);
-    free_dev(dx_);
-    free_dev(dv_);
-    free_dev(dtri_);
+    free_dev(dmesh_);
+    dx_ = dv_ = nullptr;
+    dtri_ = nullptr;
     free_dev(key1);
     free_dev(key2);
     free_dev(lu_);
@@ -1381,6 +1528,7 @@ class Engine : public EngineBase {
       free_dev(sl.uh);
       free_dev(sl.nh);
       free_dev(sl.sc);
+      free_dev(sl.bt);
     }
     if (sc_host) (void)hipHostFree(sc_host);
     sc_host = nullptr;
@@ -1597,7 +1745,20 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // work on the context stream that reads the mesh waits for its upload
+  fsi_status mesh_wait(hipStream_t st) {
+    if (mesh_pending && st != s2) FSI_HIP(hipStreamWaitEvent(st, e_up, 0));
+    return FSI_OK;
+  }
+
+  fsi_status sync_both() {
+    FSI_HIP(hipStreamSynchronize(s));
+    if (s2) FSI_HIP(hipStreamSynchronize(s2));
+    return FSI_OK;
+  }
+
   fsi_status run_mask(hipStream_t st) {
+    FSI_TRY(mesh_wait(st));
     MaskArgs<T> m;
     memset(&m, 0, sizeof(m));
     m.x = dx_;
@@ -1631,7 +1792,8 @@ class Engine : public EngineBase {
   fsi_status ensure_side() {
     if (s2) return FSI_OK;
     FSI_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin}) FSI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    for (hipEvent_t* e : {&e_ready, &e_mask, &e_x, &e_fin, &e_up})
+      FSI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return FSI_OK;
   }
 
@@ -1643,6 +1805,7 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  static constexpr int kEvPool = 64;
   hipEvent_t* next_events() {
     if (ev_used >= 4096) return nullptr;
     if (ev_used == (int)events.size()) {
@@ -1674,7 +1837,9 @@ class Engine : public EngineBase {
   DevScalars* sc = nullptr;
   DevScalars* sc_host = nullptr;
   // wing and mask sub-box
-  int wing_nt = 0, wing_nv = 0, mesh_vcap = 0, mesh_tcap = 0;
+  int wing_nt = 0, wing_nv = 0;
+  long long mesh_cap = 0;           // bytes of dmesh_
+  unsigned char* dmesh_ = nullptr;  // x, v, tri of the current mesh (views below)
   double *dx_ = nullptr, *dv_ = nullptr;
   int* dtri_ = nullptr;
   void* stage = nullptr;
@@ -1683,6 +1848,9 @@ class Engine : public EngineBase {
   hipEvent_t info_ev = nullptr;  // recorded after the step's read-back of the device scalars
   hipStream_t s2 = nullptr;      // side stream of the step (mask, reductions)
   hipEvent_t e_ready = nullptr, e_mask = nullptr, e_x = nullptr, e_fin = nullptr;
+  hipEvent_t e_up = nullptr;  // mesh upload done (side stream)
+  cpx<T>* rec_bt = nullptr;   // tape of the step being recorded (u, omega after P2)
+  bool mesh_pending = false;
   // timing events of one step
   enum { EV_MASK0, EV_MASK1, EV_P1_0, EV_P2_0, EV_P2_1, EV_P3_0, EV_P3_1, EV_RED0, EV_RED1, EV_P4_1, EV_P5_0,
          EV_P5_1, EV_COUNT };

@@ -97,6 +97,7 @@ struct SpongeArgs {
 template <typename T>
 struct XArgs {
   cpx<T>* spec;       // [f][line][ld], kx1 valid entries per line
+  cpx<T>* gout;       // fused mode: G out [3][line][ld] (stride sfs; may be spec)
   long long sfs;      // field stride of spec
   int ld;             // line pitch of spec (>= kx1, whole 128-byte lines)
   T* phys;            // [f][line][n] (plain modes)
@@ -188,6 +189,9 @@ struct MaskArgs {
 template <typename T>
 struct XAdjArgs {
   cpx<T>* spec;  // [9][line][ld] in, [6][line][ld] out
+  // u, omega of the step from its tape (fields 0-5, stride sfs); NULL: fields
+  // 0-5 of spec
+  const cpx<T>* utape;
   long long sfs;
   int ld;
   int nlines, ny, n, kx1;

@@ -51,6 +51,29 @@ __device__ __forceinline__ void st_stream2(cpx<float>* p, cpx2f v) {
   if (FSI_NT & 1) __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
   else *reinterpret_cast<v4f*>(p) = w;
 }
+// The same accesses through a buffer resource (a wave-uniform base and byte
+// bound): a lane whose byte offset is at or beyond the bound loads zeros and
+// its store is dropped, with no memory traffic and no branch (a branch around
+// stores would make the next wait for prefetched loads wait for the stores).
+// kOOB marks such lanes; every bound used here is below 2^31 bytes.
+constexpr unsigned kOOB = 0x80000000u;
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           (int)(bytes < (long long)kOOB ? bytes : (long long)kOOB), 0x00020000);
+}
+__device__ __forceinline__ cpx2f ld_buf2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const v4f w = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, (FSI_NT & 2) ? 2 : 0));
+  return cpx2f{mk<float>(w.x, w.y), mk<float>(w.z, w.w)};
+}
+__device__ __forceinline__ void st_buf2(__amdgpu_buffer_rsrc_t r, unsigned off, cpx2f v) {
+  v4f w;
+  w.x = v.a.re;
+  w.y = v.a.im;
+  w.z = v.b.re;
+  w.w = v.b.im;
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, w), r, off, 0, (FSI_NT & 1) ? 2 : 0);
+}
 __device__ __forceinline__ cpx2f ld_lds2(const cpx<float>* p) {
   const v4f w = *reinterpret_cast<const v4f*>(p);
   return cpx2f{mk<float>(w.x, w.y), mk<float>(w.z, w.w)};
@@ -649,13 +672,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     constexpr int WP = W / 2;
     const int nfield = a.nf;
     cpx2f tmp[8];
+    // buffer accesses (a field of a y slab is below 2^31 bytes): column pairs
+    // wholly in the kx padding or past the last column load zeros and are not
+    // stored, nor are rows out of the y band
     auto load_field = [&](int f) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
-      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs + ib;  // as in COL_INV_WZ
-      const int cc = cq < a.C ? cq : 0;
+      const __amdgpu_buffer_rsrc_t rin = buf_rsrc(reinterpret_cast<const cpx<float>*>(a.in) + f * a.in_fs,
+                                                  (long long)a.in_fs * 8);
+      const bool cin = cq < a.C && (cq % a.kxp) < a.kx1;
+      const unsigned base = (unsigned)(ib + cq) * 8u;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) tmp[m] = ld_stream2(at_u32(in, (rq + 64 * m) * a.ld + cc));
+      for (int m = 0; m < 8; ++m) tmp[m] = ld_buf2(rin, cin ? base + (unsigned)((rq + 64 * m) * a.ld) * 8u : kOOB);
     };
     auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
       cpx<float> v0[8], v1[8];
@@ -668,20 +696,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
       fft512_reg<float, W, false>(v0, v1, reinterpret_cast<cpx<float>*>(buf), reinterpret_cast<const cpx<float>*>(tws));
       const int tid = opaque((int)threadIdx.x);
       const int cp = tid % WP, rp = tid / WP, c = blockIdx.x * W + 2 * cp;
-      cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + f * a.out_fs + ob;
+      const __amdgpu_buffer_rsrc_t rout =
+          buf_rsrc(reinterpret_cast<cpx<float>*>(a.out) + f * a.out_fs, (long long)a.out_fs * 8);
+      const bool cin = c < a.C && (c % a.kxp) < a.kx1;
+      const unsigned base = (unsigned)(ob + c) * 8u;
       const float sc = (float)a.scale;
-      // unconditional stores (padding columns included, the launcher keeps the
-      // workgroup's columns within the row pitch; a store under a branch makes
-      // the next wait for the prefetched field wait for the stores as well): a
-      // row out of the band (m = 2 with rp > 42, m = 5 with rp < 22) stores the
-      // lane's row m = 0 again, same value, same address
+      // stores without a branch: rows out of the band (m = 2 with rp > 42,
+      // m = 5 with rp < 22) and padding pairs take the dropped offset
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         if (m == 3 || m == 4) continue;
-        const bool inb = (m == 2) ? rp <= 42 : (m == 5) ? rp >= 22 : true;
-        const int i = !inb ? rp : m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
-        const cpx<float> w0 = inb ? v0[m] : v0[0], w1 = inb ? v1[m] : v1[0];
-        st_stream2(at_u32(out, i * a.ld + c), cpx2f{scl(w0, sc), scl(w1, sc)});
+        const bool inb = cin && ((m == 2) ? rp <= 42 : (m == 5) ? rp >= 22 : true);
+        const int i = m <= 2 ? rp + 64 * m : rp + 64 * m - 171;
+        st_buf2(rout, inb ? base + (unsigned)(i * a.ld) * 8u : kOOB, cpx2f{scl(v0[m], sc), scl(v1[m], sc)});
       }
     };
     load_field(0);
@@ -1114,16 +1141,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
               n0 = n0 - scl(sp, kx);
               n1 = n1 - scl(sp, ky);
               n2 = n2 - scl(sp, kz);
-              if constexpr (UPD) {
-                if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
-              }
-            } else if constexpr (UPD) {
-              if (a.pi) a.pi[idx] = mk<T>(0, 0);
+              if (a.pi) a.pi[idx] = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
+            } else if (a.pi) {
+              a.pi[idx] = mk<T>(0, 0);
             }
             if constexpr (MODE == COL_FWD_PROJECT) {
-              a.out[idx] = n0;
-              a.out[a.cfs + idx] = n1;
-              a.out[2 * a.cfs + idx] = n2;
+              if (a.out) {  // NULL: the total pressure only
+                a.out[idx] = n0;
+                a.out[a.cfs + idx] = n1;
+                a.out[2 * a.cfs + idx] = n2;
+              }
             } else {
               const T en = dev_exp<T>(-a.nu * k2 * dtn);
               const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
@@ -1354,7 +1381,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
           const cpx<T> d = z - zc;
           r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
         }
-        a.spec[f * a.sfs + (long long)(line0 + l) * a.ld + x] = r;
+        a.gout[f * a.sfs + (long long)(line0 + l) * a.ld + x] = r;
       }
     }
     __syncthreads();
@@ -1463,7 +1490,7 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
     }
   }
   fwd512<T>(g, X, lane, tC, tFB);
-  unpack_store512<T>(g, lane, K, a.spec + (long long)line * a.ld, a.spec + a.sfs + (long long)line * a.ld);
+  unpack_store512<T>(g, lane, K, a.gout + (long long)line * a.ld, a.gout + a.sfs + (long long)line * a.ld);
 }
 
 template <typename T>
@@ -1508,8 +1535,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
     for (int j = 0; j < 8; ++j) g[j] = mk<T>(gzs[wv][j][lane], gzb[j]);
     const int l3 = opaque(lane);
     fwd512<T>(g, X, l3, tC, tFB);
-    unpack_store512<T>(g, l3, K, a.spec + 2 * a.sfs + (long long)(2 * pr) * a.ld,
-                       a.spec + 2 * a.sfs + (long long)(2 * pr + 1) * a.ld);
+    unpack_store512<T>(g, l3, K, a.gout + 2 * a.sfs + (long long)(2 * pr) * a.ld,
+                       a.gout + 2 * a.sfs + (long long)(2 * pr + 1) * a.ld);
   }
   double v[4] = {aF0, aF1, aF2, aE};
   block_sum<4, 256>(v, red);

@@ -41,7 +41,7 @@ EXPORTS = [
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
     "fsi_sample_pressure", "fsi_get_pressure_loads", "fsi_get_pressure_box", "fsi_adjoint_set_pressure_seed",
-    "fsi_get_mask_noalloc",
+    "fsi_get_mask_noalloc", "fsi_eval_pressure",
 ]
 NOALLOC_MASK_CELLS = 1 << 20  # FSI_NOALLOC_MASK_CELLS
 
@@ -115,6 +115,7 @@ def load_library():
                                           ctypes.c_double, I32, D, D]
     lib.fsi_sample_pressure.argtypes = [P, I32, D, D]
     lib.fsi_get_pressure_loads.argtypes = [P, D, D]
+    lib.fsi_eval_pressure.argtypes = [P]
     lib.fsi_get_pressure_box.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
     lib.fsi_adjoint_set_pressure_seed.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
     lib.fsi_ms_create.argtypes = [I32, D, ctypes.POINTER(P)]
@@ -338,6 +339,10 @@ class Solver:
         dp = np.zeros(self._nv)
         self._check(self.lib.fsi_get_pressure_loads(self.ctx, _dptr(loads), _dptr(dp)))
         return loads, dp
+
+    def eval_pressure(self):
+        """fsi_eval_pressure: the pressure of the current velocity (paper's coupling order)."""
+        self._check(self.lib.fsi_eval_pressure(self.ctx))
 
     def pressure_box(self, values=True):
         """(box0, p) of the current pressure box; p (nz, ny, nx of the box) of the

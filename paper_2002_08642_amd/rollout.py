@@ -51,10 +51,13 @@ class PlateRollout:
         u0 = self.u0 if self.u0 is not None else np.zeros((3, nz, ny, nx))
         self.s.set_velocity(u0)
 
-    def _step(self, n, alpha):
+    def _step(self, n, alpha, tape=None):
         x, v = self._pose(self.times[n], alpha)
         self.s.set_wing(x, v, self.cfg["tri"])
-        self.s.step(self.dts[n])
+        if tape is None:
+            self.s.step(self.dts[n])
+        else:  # keep u_hat^n in tape slot `tape` for the reverse step
+            self.s.step_record(self.dts[n], tape)
         return self.s.info()["F"]
 
     def forward(self, alpha):
@@ -87,8 +90,7 @@ class PlateRollout:
         n0, n1 = seg * self.K, min(seg * self.K + self.K, N)
         self.s.load(seg)
         for n in range(n0, n1):
-            self.s.save(tape0 + n - n0)
-            self._step(n, alpha)
+            self._step(n, alpha, tape=tape0 + n - n0)
         for n in reversed(range(n0, n1)):
             x, v = self._pose(self.times[n], alpha)
             self.s.set_wing(x, v, cfg["tri"])

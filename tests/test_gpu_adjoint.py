@@ -76,15 +76,21 @@ def test_adjoint_dot_product_two_steps(part):
     assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
 
 
-def run_two_steps(s, u0, x0, v0, tri, dts, g, lam_u, lam_n, du, dx, dv):
+def run_two_steps(s, u0, x0, v0, tri, dts, g, lam_u, lam_n, du, dx, dv, record=False):
     """Central-difference directional derivative of the two-step functional
-    and the adjoint's inner product with the same direction."""
+    and the adjoint's inner product with the same direction.  record: the tape
+    of each step from fsi_step_record (u, omega kept by the step itself) instead
+    of fsi_save_state (u_hat, the reverse step re-derives u, omega)."""
 
     def run(eps, save=False):
         s.set_spectrum(u0 + eps * du)
         s.set_wing(x0 + eps * dx, v0 + eps * dv, tri)
         J = 0.0
         for k, dt in enumerate(dts):
+            if save and record:
+                s.step_record(dt, k)
+                J += float(np.dot(g[k], s.info()["F"]))
+                continue
             if save:
                 s.save(k)
             s.step(dt)
@@ -103,7 +109,7 @@ def run_two_steps(s, u0, x0, v0, tri, dts, g, lam_u, lam_n, du, dx, dv):
     return adj, fd, (lu0, ln0, gx0 + gx1, gv0 + gv1)
 
 
-def long_x_case(prec, n=(512, 16, 12), L=(8.0, 2.0, 1.5), tw=0.3, h=0.2):
+def long_x_case(prec, n=(512, 16, 12), L=(8.0, 2.0, 1.5), tw=0.3, h=0.2, record=False):
     """Long x lines (512 points: the register-resident adjoint x pass), a plate
     close to the x-y plane in the middle of the box."""
     s = fsi.Solver(n, L, 0.02, 0.05, tw, h, fsi.PROFILE_COS, prec)
@@ -124,7 +130,7 @@ def long_x_case(prec, n=(512, 16, 12), L=(8.0, 2.0, 1.5), tw=0.3, h=0.2):
     g = [rng.standard_normal(3), rng.standard_normal(3)]
     lam_u = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
     lam_n = rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape)
-    return run_two_steps(s, u0, x0, v0, tri, (0.01, 0.013), g, lam_u, lam_n, du, dx, dv)
+    return run_two_steps(s, u0, x0, v0, tri, (0.01, 0.013), g, lam_u, lam_n, du, dx, dv, record)
 
 
 # (512, 192, 192): each wavefront of the 512-point pass reverses several line
@@ -136,12 +142,33 @@ LARGE = [((512, 16, 12), (8.0, 2.0, 1.5), 0.3, 0.2),
          ((48, 512, 12), (3.0, 32.0, 0.75), 0.05, 0.03)]
 
 
+@pytest.mark.parametrize("record", [False, True], ids=["saved", "recorded"])
 @pytest.mark.parametrize("case", LARGE, ids=lambda c: "x".join(map(str, c[0])))
-def test_adjoint_dot_product_long_lines(case):
+def test_adjoint_dot_product_long_lines(case, record):
     n, L, tw, h = case
-    adj, fd, _ = long_x_case(fsi.PREC_FP64, n, L, tw, h)
-    print("dot product %s: adjoint %.12e fd %.12e" % (n, adj, fd), flush=True)
+    adj, fd, _ = long_x_case(fsi.PREC_FP64, n, L, tw, h, record)
+    print("dot product %s record %d: adjoint %.12e fd %.12e" % (n, record, adj, fd), flush=True)
     assert abs(adj - fd) <= 1e-7 * max(abs(fd), 1e-8)
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+@pytest.mark.parametrize("case", [((64, 24, 20), (4.0, 1.5, 1.25), 0.1, 0.06), LARGE[0], LARGE[3]],
+                         ids=lambda c: "x".join(map(str, c[0])))
+def test_recorded_tape_matches_saved_state(case, prec):
+    """The reverse step from the tape of fsi_step_record (u, omega written by the
+    step's own y-inverse pass) equals the reverse step from a saved u_hat (u,
+    omega re-derived) up to the rounding of the two transform orders."""
+    n, L, tw, h = case
+    _, _, ra = long_x_case(prec, n, L, tw, h, False)
+    _, _, rb = long_x_case(prec, n, L, tw, h, True)
+    for name, a, b in zip(("lambda_u", "lambda_N", "dJ/dx", "dJ/dv"), ra, rb):
+        ref = np.max(np.abs(a))
+        if ref == 0.0:
+            assert np.max(np.abs(b)) == 0.0
+            continue
+        err = np.max(np.abs(a - b)) / ref
+        print("recorded vs saved %s %s prec %d: %.3e" % (n, name, prec, err), flush=True)
+        assert err < (1e-12 if prec == fsi.PREC_FP64 else 2e-6)
 
 
 @pytest.mark.parametrize("case", LARGE, ids=lambda c: "x".join(map(str, c[0])))

@@ -35,18 +35,22 @@ def rel(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
 
 
+@pytest.mark.parametrize("order", ["lagged", "paper"])
 @pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
-def test_coupled_flexible_wing_matches_oracle(prec):
+def test_coupled_flexible_wing_matches_oracle(prec, order):
+    """Both pressure orders of the staggered step: p^n of the fluid step
+    (lagged), or p^{n+1} of the new velocity (the paper's order, one more
+    nonlinear evaluation per step: fsi_eval_pressure)."""
     cfg, w, ijk, owner, kin = small_case()
     kb_o = np.array([st.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
     kb_g = np.array([fsi.bending_stiffness(w["vein_EI"][v], w["vein_length"], len(w["veins"][v]) - 2) for v in owner])
     axis = np.zeros(len(ijk), dtype=np.int32)
     o = CoupledOracle(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], w, ijk, kb_o,
-                      axis, kin)
+                      axis, kin, order=order)
     s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec,
                    pressure=True)
     s.set_velocity(np.zeros((3,) + cfg["n"]))
-    g = FlexibleWingFSI(s, w, ijk, kb_g, axis, kin, tol=1e-12)
+    g = FlexibleWingFSI(s, w, ijk, kb_g, axis, kin, tol=1e-12, order=order)
     fo, fg = [], []
     for k in range(10):
         fo.append(o.step(2e-3))
@@ -54,8 +58,8 @@ def test_coupled_flexible_wing_matches_oracle(prec):
     x, v = g.state()
     xr, _ = o._root_pose(o.t, None)
     ex, ev, ef = rel(x - xr, o.q[0] - xr), rel(v, o.q[1]), rel(fg, fo)
-    print("coupled prec %d: deflection %.3e velocity %.3e force %.3e (max deflection %.3e, Newton its %s)"
-          % (prec, ex, ev, ef, np.max(np.abs(o.q[0] - xr)), g.iters), flush=True)
+    print("coupled %s prec %d: deflection %.3e velocity %.3e force %.3e (max deflection %.3e, Newton its %s)"
+          % (order, prec, ex, ev, ef, np.max(np.abs(o.q[0] - xr)), g.iters), flush=True)
     assert ex < TOL[prec] and ev < TOL[prec] and ef < TOL[prec]
     assert max(g.iters) <= 8
 

@@ -296,9 +296,10 @@ def test_revolving_plate_128_parity(prec):
 
 
 def test_step_record_and_adjoint_reset():
-    """fsi_step_record = save the state in the tape slot, then step; the reverse
-    step from that slot equals the one from an explicit save; fsi_adjoint_reset
-    zeroes the cotangent state."""
+    """fsi_step_record = keep the tape of the step (u_hat^n) in the slot, then
+    step; the reverse step from that slot equals the one from an explicit save;
+    a tape slot is not a full state (fsi_load_state refuses it);
+    fsi_adjoint_reset zeroes the cotangent state."""
     n, L = (32, 24, 20), (2.0, 1.5, 1.25)
     runs = []
     for record in (True, False):
@@ -310,6 +311,9 @@ def test_step_record_and_adjoint_reset():
         s.set_wing(x, v, tri)
         if record:
             s.step_record(2e-3, 3)
+            with pytest.raises(fsi.FsiError) as e:
+                s.load(3)
+            assert e.value.code == -5
         else:
             s.save(3)
             s.step(2e-3)
@@ -323,5 +327,8 @@ def test_step_record_and_adjoint_reset():
         s.adjoint_reset()
         z = s.adjoint_get()
         assert not np.any(z[0]) and not np.any(z[1])
-    for a, b in zip(runs[0], runs[1]):
-        assert np.array_equal(a, b)
+    # the forward step is the same computation either way; the reverse steps
+    # differ in how u, omega are obtained (taped by the step / re-derived)
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for a, b in zip(runs[0][1:], runs[1][1:]):
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-300)
