@@ -101,12 +101,12 @@ def sponge_layers(n):
 SPONGE_C = 1e-2  # C_sp of the sponge leg (dt / C_sp ~ 0.01 on this workload)
 
 
-def run_gpu(n, prec, steps, warmup, timing, sponge=False):
+def run_gpu(n, prec, steps, warmup, timing, sponge=False, uh0=None):
     from paper_2002_08642_amd import fsi
     import synth
     cfg = workload(n)
     s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec)
-    s.set_spectrum(synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0))
+    s.set_spectrum(synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0) if uh0 is None else uh0)
     if sponge:
         gx, gz = sponge_layers(n)
         s.set_sponge(SPONGE_C, gx=gx, gz=gz)
@@ -122,19 +122,57 @@ def run_gpu(n, prec, steps, warmup, timing, sponge=False):
 
     for _ in range(warmup):
         t, info = one_step(t)
+    per_pass, dominant = {}, None
+    if timing:
+        # every pass timed on a few steps before the timed region; inside it only
+        # the pass with the largest time (each recorded event orders its stream)
+        s.synchronize()
+        s.set_timing(True)
+        for _ in range(SAMPLE_STEPS):
+            t, info = one_step(t)
+        passes, nrec = s.pass_times()
+        per_pass = {k: v / max(nrec, 1) for k, v in passes.items()}
+        dominant = max(per_pass, key=per_pass.get)
+        s.set_timing(True, passes=[dominant])
     s.synchronize()
     sync_torch()
-    s.set_timing(timing)
     t0 = time.perf_counter()
     for _ in range(steps):
         t, info = one_step(t)
     s.synchronize()
     sync_torch()
     el = time.perf_counter() - t0
-    passes, nrec = s.pass_times() if timing else ({}, 0)
-    s.set_timing(False)
-    per_pass = {k: v / max(nrec, 1) for k, v in passes.items()}
-    return el / steps, per_pass, info
+    if timing:
+        passes, nrec = s.pass_times()
+        per_pass[dominant] = passes[dominant] / max(nrec, 1)
+        s.set_timing(False)
+    s.close()
+    return el / steps, per_pass, info, dominant
+
+
+SAMPLE_STEPS = 5  # steps with every pass timed, before the timed region
+
+
+def large_grid_leg(n, steps, warmup):
+    """The same workload at n^3 (800^3: 2^5 5^2, run-time mixed-radix plans)
+    in FP32 and FP64: time per step, the pass-model roofline fraction of the
+    step and the algorithmic-byte rate of every pass."""
+    from paper_2002_08642_amd import fsi
+    import synth
+    cfg = workload(n)
+    uh0 = synth.random_solenoidal_compact(cfg["n"], cfg["L"], seed=0)
+    out = {"grid": [n, n, n], "steps": steps, "warmup": warmup}
+    for name, prec, wsize in (("fp32", fsi.PREC_FP32, 4), ("fp64", fsi.PREC_FP64, 8)):
+        ms, passes, _, _ = run_gpu(n, prec, steps, warmup, True, uh0=uh0)
+        algo = algorithmic_bytes(n, wsize, 0)
+        out[name] = {
+            "value": round(n ** 3 / ms / 1e6, 1), "unit": "Mpts/s", "ms_per_step": round(ms * 1e3, 4),
+            "step_roofline_frac": round(step_model_bytes(n, wsize) / ms / 1e9 / HBM_PEAK_GBS, 4),
+            "pass_ms": {k: round(v, 4) for k, v in passes.items()},
+            "pass_frac": {k: round(algo[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                          for k, v in passes.items() if k in algo and v > 0.01},
+        }
+    return out
 
 
 def run_adjoint(n, prec, K):
@@ -268,6 +306,10 @@ def main():
                     help="steps in the timed adjoint segment (0 skips the adjoint/forward leg)")
     ap.add_argument("--sponge-steps", type=int, default=10,
                     help="timed steps of the leg with the vorticity sponge on (0 skips it)")
+    ap.add_argument("--large-n", type=int, default=800,
+                    help="grid of the large-grid FP32/FP64 leg (800: the largest workload grid)")
+    ap.add_argument("--large-steps", type=int, default=10,
+                    help="timed steps of the large-grid leg (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--no-torch", action="store_true",
@@ -285,21 +327,22 @@ def main():
         calibrate_copy()
 
     n = args.n
-    ms32, pass32, info32 = run_gpu(n, fsi.PREC_FP32, args.steps, args.warmup, True)
-    ms64, pass64, _ = (None, {}, None)
+    ms32, pass32, info32, dominant = run_gpu(n, fsi.PREC_FP32, args.steps, args.warmup, True)
+    ms64, pass64 = None, {}
     if args.fp64_steps > 0:
-        ms64, pass64, _ = run_gpu(n, fsi.PREC_FP64, args.fp64_steps, 2, True)
+        ms64, pass64, _, _ = run_gpu(n, fsi.PREC_FP64, args.fp64_steps, 2, True)
 
     adj = run_adjoint(n, fsi.PREC_FP32, args.adjoint_k) if args.adjoint_k > 0 else None
     spg = None
     if args.sponge_steps > 0:
-        mss, passs, _ = run_gpu(n, fsi.PREC_FP32, args.sponge_steps, 2, True, sponge=True)
+        mss, passs, _, _ = run_gpu(n, fsi.PREC_FP32, args.sponge_steps, 2, True, sponge=True)
         spg = {"value": round(n ** 3 / mss / 1e6, 1), "unit": "Mpts/s", "ms_per_step": round(mss * 1e3, 4),
                "steps": args.sponge_steps, "c_sp": SPONGE_C,
                "layers": "cosine layers n/8 deep at both x faces and the top z face",
                "pass_ms": {k: round(v, 4) for k, v in passs.items()}}
 
-    dominant = max(pass32, key=pass32.get)
+    large = large_grid_leg(args.large_n, args.large_steps, 2) if args.large_steps > 0 else None
+
     cfg = workload(n)
     # sub-box cells of the mask (chi + 3 u_s read by the fused x pass)
     dx = cfg["L"][0] / n
@@ -354,6 +397,8 @@ def main():
             "design_bytes": design_step_bytes(n, 4),
             "design_frac": round(design_step_bytes(n, 4) / ms32 / 1e9 / HBM_PEAK_GBS, 4),
             "pass_ms": {k: round(v, 4) for k, v in pass32.items()},
+            "pass_ms_note": "HIP-event times per pass on %d steps before the timed region, except the "
+                            "dominant pass, timed in the timed region" % SAMPLE_STEPS,
         },
         "fp64": None if ms64 is None else {
             "value": round(n ** 3 / ms64 / 1e6, 1), "unit": "Mpts/s", "ms_per_step": round(ms64 * 1e3, 4),
@@ -363,6 +408,7 @@ def main():
         },
         "adjoint": adj,
         "sponge": spg,
+        "large_grid": large,
         "last_step": {"dt": info32["dt"], "umax": info32["umax"], "E": info32["E"],
                       "F": [float(f) for f in info32["F"]]},
         "cpu_baseline": None,

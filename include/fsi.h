@@ -320,12 +320,17 @@ fsi_status fsi_plate_frame_dalpha(double t, double alpha, double omega, double t
 /* Wait for all queued work of the context. */
 fsi_status fsi_synchronize(fsi_ctx* ctx);
 
-/* Per-pass timing with HIP events on the context stream (off by default).
- * fsi_get_pass_times synchronizes, writes the summed milliseconds of each of
- * the FSI_NPASS passes recorded since timing was enabled or last read, and
- * the number of steps they cover, then resets the sums. Pass order: mask,
- * z-inverse+curl, y-inverse, x-fused, reduce, y-forward, z-forward+update. */
+/* Per-pass timing with HIP events on the streams of the step (off by default).
+ * on = 0: off; on = 1 (any value without FSI_TIME_PASSES): every pass;
+ * on = FSI_TIME_PASSES | mask: only the passes whose bit (1 << pass index) is
+ * set (each recorded event orders its stream, so timing fewer passes
+ * disturbs the step less).  fsi_get_pass_times synchronizes, writes the summed
+ * milliseconds of each of the FSI_NPASS passes recorded since timing was
+ * enabled or last read (0 for passes not timed), and the number of steps they
+ * cover, then resets the sums. Pass order: mask, z-inverse+curl, y-inverse,
+ * x-fused, reduce, y-forward, z-forward+update.  FSI_EINVAL if on < 0. */
 enum { FSI_NPASS = 7 };
+#define FSI_TIME_PASSES 0x100
 fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on);
 fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps);
 

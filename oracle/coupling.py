@@ -74,7 +74,7 @@ class CoupledOracle:
         F = self.fluid.step(dt=dt)["F"]
         if self.order == "paper":
             # p^{n+1} from u^{n+1}; the wing (and so the mask) is still at t^n
-            self.fluid.nonlinear(*self.fluid.mask())
+            self.fluid.nonlinear(*self.fluid.combined_mask())
         loads, _ = pressure.wing_loads(self.fluid.p_last, self.L, x, self.tri, self.d)
         t1 = self.t + dt
         xc, vc = self._root_pose(t1, self.clamped)

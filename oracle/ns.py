@@ -26,6 +26,17 @@ Algorithm of one step n (state: u_hat^n, N_hat^{n-1}, dt_{n-1}, t^n):
     the coefficients come from integrating the linear interpolant of
     exp(nu |k|^2 t) N_hat(t) over [t_n, t_{n+1}].
 
+Static penalization (set_static_mask; off by default): a second solid given on
+the grid instead of a mesh, independent of z (channel walls, fixed obstacles,
+an inflow layer imposing a velocity profile: the channel workload of
+Sec. 4.2.1), chi_st(x, y), u_st(x, y).  Reading: the two masks form one mask
+function chi = max(chi_wing, chi_st), with the solid velocity of the solid
+whose chi is larger (the static one on ties).  The force F is the wing's
+(points where the wing's chi is the larger); F_st = (dV/eta) sum w chi
+(u - u_st) over the points where the static solid wins, with a caller's
+weight w(x, y) (1 on the obstacle whose force is wanted, 0 on walls and the
+inflow layer).
+
 Pins (tests/test_oracle_ns.py): 2-D Taylor-Green decays exactly as
 exp(-2 nu t) for any dt sequence; 3-D Taylor-Green energy follows
 exp(-6 nu t) within the nonlinear-transfer bound; with nu = 0 and chi = 0 the
@@ -61,6 +72,33 @@ class OracleNS:
         self.wing = None
         self.p_last = None  # p = Pi - |u|^2/2 of the last step (oracle.pressure)
         self.sponge = None  # (chi_sp, C_sp)
+        self.static = None  # (chi_st [ny][nx], u_st [3][ny][nx], w [ny][nx])
+
+    def set_static_mask(self, chi, us, weight=None):
+        """z-independent static penalization chi_st (ny, nx), u_st (3, ny, nx) and
+        the weight of its force (ny, nx; None = 0); chi = None removes it."""
+        if chi is None:
+            self.static = None
+            return
+        nx, ny, nz = self.n
+        chi = np.asarray(chi, dtype=np.float64).reshape(ny, nx)
+        us = np.asarray(us, dtype=np.float64).reshape(3, ny, nx)
+        w = np.zeros((ny, nx)) if weight is None else np.asarray(weight, dtype=np.float64).reshape(ny, nx)
+        self.static = (chi, us, w)
+
+    def combined_mask(self):
+        """(chi, u_s, wing force weight, static force weight) on the grid."""
+        chi_w, us_w = self.mask()
+        if self.static is None:
+            return chi_w, us_w, np.ones_like(chi_w), np.zeros_like(chi_w)
+        nz = self.n[2]
+        chi_s = np.broadcast_to(self.static[0][None], chi_w.shape)
+        us_s = np.broadcast_to(self.static[1][:, None], us_w.shape)
+        w_s = np.broadcast_to(self.static[2][None], chi_w.shape)
+        wing = chi_w > chi_s
+        chi = np.where(wing, chi_w, chi_s)
+        us = np.where(wing[None], us_w, us_s)
+        return chi, us, wing.astype(np.float64), np.where(wing, 0.0, w_s)
 
     def set_sponge(self, c_sp, gx=None, gy=None, gz=None):
         """Vorticity sponge with chi_sp = max(gx[x], gy[y], gz[z]); c_sp <= 0 removes it."""
@@ -102,16 +140,22 @@ class OracleNS:
         self.dt_prev, self.t, self.nstep = s[2], s[3], s[4]
 
     # -- one step ------------------------------------------------------------
-    def nonlinear(self, chi, us):
-        """Return (N_hat (projected, dealiased), diagnostics dict) at the current state."""
+    def nonlinear(self, chi, us, fw=None, sw=None):
+        """Return (N_hat (projected, dealiased), diagnostics dict) at the current
+        state; fw, sw: weights of the wing force and of the static-mask force
+        (None: every point for the wing, none for the static mask)."""
         u = dft.inverse_real(self.uh)
         w = dft.inverse_real(spectral.curl(self.uh, self.n, self.L))
         slip = u - us
         g = spectral.cross(u, w) - (chi / self.eta)[None] * slip
-        force = (self.dV / self.eta) * np.array([np.sum(chi * slip[c]) for c in range(3)])
+        cw = chi if fw is None else chi * fw
+        force = (self.dV / self.eta) * np.array([np.sum(cw * slip[c]) for c in range(3)])
+        cs = np.zeros_like(chi) if sw is None else chi * sw
+        force_st = (self.dV / self.eta) * np.array([np.sum(cs * slip[c]) for c in range(3)])
         speed2 = np.sum(u * u, axis=0)
         diag = {
             "F": force,
+            "F_static": force_st,
             "E": 0.5 * self.dV * float(np.sum(speed2)),
             "umax": float(np.sqrt(np.max(speed2))),
         }
@@ -132,9 +176,10 @@ class OracleNS:
         """Advance one step; returns the diagnostics at t^n plus the dt used."""
         if mask_override is not None:
             chi, us = mask_override
+            fw = sw = None
         else:
-            chi, us = self.mask()
-        nh, diag = self.nonlinear(chi, us)
+            chi, us, fw, sw = self.combined_mask()
+        nh, diag = self.nonlinear(chi, us, fw, sw)
         if dt is None:
             dt = self.adaptive_dt(diag["umax"], cfl, c_eta, dt_max)
         dt = float(dt)

@@ -279,7 +279,10 @@ fsi_status fsi_synchronize(fsi_ctx* ctx) {
 
 fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on) {
   if (guard(ctx) != FSI_OK) return FSI_EINVAL;
-  return ctx->eng->set_timing(on != 0);
+  if (on < 0) return FSI_EINVAL;
+  const unsigned all = (1u << FSI_NPASS) - 1;
+  const unsigned u = (unsigned)on;
+  return ctx->eng->set_timing(u == 0 ? 0u : (u & FSI_TIME_PASSES) ? (u & all) : all);
 }
 
 fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps) {

@@ -698,15 +698,15 @@ class Engine : public EngineBase {
     if (wing) {
       FSI_HIP(hipEventRecord(e_ready, s));
       FSI_HIP(hipStreamWaitEvent(s2, e_ready, 0));
-      if (ev) FSI_HIP(hipEventRecord(ev[EV_MASK0], s2));
+      if (ev && ev_need[EV_MASK0]) FSI_HIP(hipEventRecord(ev[EV_MASK0], s2));
       FSI_TRY(run_mask(s2));
-      if (ev) FSI_HIP(hipEventRecord(ev[EV_MASK1], s2));
+      if (ev && ev_need[EV_MASK1]) FSI_HIP(hipEventRecord(ev[EV_MASK1], s2));
       FSI_HIP(hipEventRecord(e_mask, s2));
-    } else if (ev) {
+    } else if (ev && ev_need[EV_MASK0]) {
       FSI_HIP(hipEventRecord(ev[EV_MASK0], s));
       FSI_HIP(hipEventRecord(ev[EV_MASK1], s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P1_0], s));
+    if (ev && ev_need[EV_P1_0]) FSI_HIP(hipEventRecord(ev[EV_P1_0], s));
     // P1: z inverse of u and of omega_x, omega_y (omega = i k x u); the
     // previous step's last pass has already produced it unless u_hat has been
     // replaced or A used since
@@ -719,7 +719,7 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_INV_CURL5, a, 1, s));  // u, omega_x, omega_y
     }
     zs_valid = false;
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P2_0], s));
+    if (ev && ev_need[EV_P2_0]) FSI_HIP(hipEventRecord(ev[EV_P2_0], s));
     // P2: y inverse of the five fields, omega_z = i (kx uy - ky ux) formed on the way
     // (into the step's tape when recording: the reverse step reads u, omega there)
     {
@@ -732,9 +732,9 @@ class Engine : public EngineBase {
       a.out_bs = (long long)ny * kxp;
       FSI_HIP(launch_col<T>(COL_INV_WZ, a, nz, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P2_1], s));
+    if (ev && ev_need[EV_P2_1]) FSI_HIP(hipEventRecord(ev[EV_P2_1], s));
     if (wing) FSI_HIP(hipStreamWaitEvent(s, e_mask, 0));
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P3_0], s));
+    if (ev && ev_need[EV_P3_0]) FSI_HIP(hipEventRecord(ev[EV_P3_0], s));
     // P3: x C2R, nonlinear + penalization term, diagnostics, x R2C
     FSI_HIP(launch_xfused<T>(p3_args(), nfused, s));
     // the reductions need only P3's partials: they run on the side stream
@@ -765,10 +765,10 @@ class Engine : public EngineBase {
       FSI_HIP(launch_sponge_mask<T>(m, s));
       FSI_HIP(launch_xplain<T>(X_R2C, 3, a, npart, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P3_1], s));
+    if (ev && ev_need[EV_P3_1]) FSI_HIP(hipEventRecord(ev[EV_P3_1], s));
     // diagnostics and dt_n (side stream)
     {
-      if (ev) FSI_HIP(hipEventRecord(ev[EV_RED0], s2));
+      if (ev && ev_need[EV_RED0]) FSI_HIP(hipEventRecord(ev[EV_RED0], s2));
       FinalArgs f;
       f.partials = partials;
       f.np = nfused;
@@ -787,7 +787,7 @@ class Engine : public EngineBase {
       if (!info_ev) FSI_HIP(hipEventCreateWithFlags(&info_ev, hipEventDisableTiming));
       FSI_HIP(hipEventRecord(info_ev, s2));
       info_pending = true;
-      if (ev) FSI_HIP(hipEventRecord(ev[EV_RED1], s2));
+      if (ev && ev_need[EV_RED1]) FSI_HIP(hipEventRecord(ev[EV_RED1], s2));
       FSI_HIP(hipEventRecord(e_fin, s2));
     }
     // P4: y forward of G, truncated to the y band
@@ -813,9 +813,9 @@ class Engine : public EngineBase {
       a.csp_inv = (T)(1.0 / csp);
       FSI_HIP(launch_col<T>(COL_FWD_SPONGE, a, 1, s));
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P4_1], s));
+    if (ev && ev_need[EV_P4_1]) FSI_HIP(hipEventRecord(ev[EV_P4_1], s));
     FSI_HIP(hipStreamWaitEvent(s, e_fin, 0));
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P5_0], s));
+    if (ev && ev_need[EV_P5_0]) FSI_HIP(hipEventRecord(ev[EV_P5_0], s));
     // P5: z forward, dealias, Leray projection, integrating-factor AB2
     {
       ColArgs<T> a = col_base(pz, twz, nz, Kz, C1, C1);
@@ -838,7 +838,7 @@ class Engine : public EngineBase {
       FSI_HIP(launch_col<T>(COL_FWD_UPDATE_Z, a, 1, s));
       zs_valid = true;
     }
-    if (ev) FSI_HIP(hipEventRecord(ev[EV_P5_1], s));
+    if (ev && ev_need[EV_P5_1]) FSI_HIP(hipEventRecord(ev[EV_P5_1], s));
     ++nstep;
     have_prev = true;
     p_ready = d.fsi_pressure && wing_nt > 0 && bcells > 0;
@@ -1412,10 +1412,15 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
-  fsi_status set_timing(bool on) override {
+  fsi_status set_timing(unsigned mask) override {
     FSI_TRY(sync_both());
-    timing = on;
+    tmask = mask & ((1u << FSI_NPASS) - 1);
+    timing = tmask != 0;
+    for (int e = 0; e < EV_COUNT; ++e) ev_need[e] = false;
+    for (int p = 0; p < FSI_NPASS; ++p)
+      if (tmask & (1u << p)) ev_need[kSpan[p][0]] = ev_need[kSpan[p][1]] = true;
     ev_used = 0;
+    const bool on = timing;
     // the events of the next kEvPool steps are created here, not inside the
     // steps being timed
     while (on && (int)events.size() < kEvPool) {
@@ -1429,16 +1434,12 @@ class Engine : public EngineBase {
   fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) override {
     FSI_HIP(hipStreamSynchronize(s));
     if (s2) FSI_HIP(hipStreamSynchronize(s2));
-    // (start, end) event of each pass: mask (side stream), P1, P2, P3 (+ sponge
-    // x pass), reductions and dt (side stream), P4 (+ sponge z pass), P5
-    static const int span[FSI_NPASS][2] = {{EV_MASK0, EV_MASK1}, {EV_P1_0, EV_P2_0}, {EV_P2_0, EV_P2_1},
-                                           {EV_P3_0, EV_P3_1},   {EV_RED0, EV_RED1}, {EV_P3_1, EV_P4_1},
-                                           {EV_P5_0, EV_P5_1}};
     for (int p = 0; p < FSI_NPASS; ++p) ms[p] = 0.0;
     for (int k = 0; k < ev_used; ++k) {
       for (int p = 0; p < FSI_NPASS; ++p) {
+        if (!(tmask & (1u << p))) continue;
         float e = 0.f;
-        FSI_HIP(hipEventElapsedTime(&e, events[k][span[p][0]], events[k][span[p][1]]));
+        FSI_HIP(hipEventElapsedTime(&e, events[k][kSpan[p][0]], events[k][kSpan[p][1]]));
         ms[p] += e;
       }
     }
@@ -1854,6 +1855,13 @@ class Engine : public EngineBase {
   // timing events of one step
   enum { EV_MASK0, EV_MASK1, EV_P1_0, EV_P2_0, EV_P2_1, EV_P3_0, EV_P3_1, EV_RED0, EV_RED1, EV_P4_1, EV_P5_0,
          EV_P5_1, EV_COUNT };
+  // (start, end) event of each pass: mask (side stream), P1, P2, P3 (+ sponge
+  // x pass), reductions and dt (side stream), P4 (+ sponge z pass), P5
+  static constexpr int kSpan[FSI_NPASS][2] = {{EV_MASK0, EV_MASK1}, {EV_P1_0, EV_P2_0}, {EV_P2_0, EV_P2_1},
+                                              {EV_P3_0, EV_P3_1},   {EV_RED0, EV_RED1}, {EV_P3_1, EV_P4_1},
+                                              {EV_P5_0, EV_P5_1}};
+  unsigned tmask = 0;          // passes being timed
+  bool ev_need[EV_COUNT] = {};  // events those passes need (each recorded event orders its stream)
   bool info_pending = false;
   bool stage_pending = false;
   int bx0 = 0, by0 = 0, bz0 = 0, bnx = 0, bny = 0, bnz = 0;

@@ -23,6 +23,7 @@ PROFILE_TANH = 1
 PREC_FP32 = 0
 PREC_FP64 = 1
 NPASS = 7
+TIME_PASSES = 0x100  # FSI_TIME_PASSES
 PASS_NAMES = ["mask", "z_inverse_curl", "y_inverse", "x_fused", "reduce_dt", "y_forward", "z_forward_update"]
 
 # every symbol declared in include/*.h
@@ -417,8 +418,16 @@ class Solver:
     def synchronize(self):
         self._check(self.lib.fsi_synchronize(self.ctx))
 
-    def set_timing(self, on):
-        self._check(self.lib.fsi_set_timing(self.ctx, 1 if on else 0))
+    def set_timing(self, on, passes=None):
+        """Per-pass HIP-event timing: on/off for every pass, or only the passes
+        named in ``passes`` (names of PASS_NAMES)."""
+        if on and passes is not None:
+            mask = 0
+            for p in passes:
+                mask |= 1 << PASS_NAMES.index(p)
+            self._check(self.lib.fsi_set_timing(self.ctx, TIME_PASSES | mask))
+        else:
+            self._check(self.lib.fsi_set_timing(self.ctx, 1 if on else 0))
 
     def pass_times(self):
         ms = np.zeros(NPASS)

@@ -332,3 +332,30 @@ def test_step_record_and_adjoint_reset():
     assert np.array_equal(runs[0][0], runs[1][0])
     for a, b in zip(runs[0][1:], runs[1][1:]):
         assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-300)
+
+
+def test_pass_timing_masks():
+    """fsi_set_timing: every pass, or only the passes of a mask (the others
+    report 0); a negative value is rejected."""
+    cfg = synth.config0(True)
+    s = solver_for(cfg, fsi.PREC_FP32)
+    s.set_velocity(synth.taylor_green_3d(cfg["n"], cfg["L"]))
+    x, v, tri = cfg["wing"]
+    s.set_wing(x, v, tri)
+    s.step(cfg["dt"])
+    s.set_timing(True)
+    for _ in range(2):
+        s.step(cfg["dt"])
+    ms, nrec = s.pass_times()
+    assert nrec == 2
+    for k in ("mask", "y_inverse", "x_fused", "reduce_dt", "y_forward", "z_forward_update"):
+        assert ms[k] > 0.0, k
+    s.set_timing(True, passes=["x_fused", "y_forward"])
+    for _ in range(3):
+        s.step(cfg["dt"])
+    ms, nrec = s.pass_times()
+    assert nrec == 3
+    assert ms["x_fused"] > 0.0 and ms["y_forward"] > 0.0
+    assert all(ms[k] == 0.0 for k in ms if k not in ("x_fused", "y_forward"))
+    s.set_timing(False)
+    assert s.lib.fsi_set_timing(s.ctx, -1) == -1

@@ -62,10 +62,10 @@ class StubFluid:
         self.t += dt
         return {"F": np.zeros(3)}
 
-    def mask(self):
-        return None, None
+    def combined_mask(self):
+        return None, None, None, None
 
-    def nonlinear(self, chi, us):
+    def nonlinear(self, chi, us, fw=None, sw=None):
         self.p_last = self._p(self.t)
 
 
