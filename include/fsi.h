@@ -145,8 +145,25 @@ fsi_status fsi_get_spectrum(fsi_ctx* ctx, double* uhat_host);
 fsi_status fsi_set_wing(fsi_ctx* ctx, int32_t nv, const double* x, const double* v,
                         int32_t nt, const int32_t* tri);
 
+/* Static penalization (Sec. 4.1 penalized equations; the channel walls,
+ * cylinder and inflow layer of the Sec. 4.2.1 workload): a second solid given
+ * on the grid, independent of z: chi[ny][nx] in [0, 1], u_s us[3][ny][nx]
+ * (component stride ny*nx), weight[ny][nx] of its force (NULL = 0, e.g. 1 on
+ * an obstacle, 0 on walls and inflow layers).  It combines with the wing's mask
+ * into one mask function chi = max(chi_wing, chi_static), with the solid
+ * velocity of the solid whose chi is larger (the static one on ties).  The
+ * step's force F (fsi_get_step_info) is the wing's (points where the wing's chi
+ * is larger); fsi_get_static_force returns (dV/eta) sum weight chi (u - u_s)
+ * over the points where the static solid wins, at t^n of the last step.
+ * chi = NULL removes it.  Arrays are copied; FSI_EINVAL on values out of
+ * range.  The reverse step (fsi_step_adjoint) does not include it and returns
+ * FSI_ESTATE while it is set. */
+fsi_status fsi_set_static_mask(fsi_ctx* ctx, const double* chi, const double* us, const double* weight);
+fsi_status fsi_get_static_force(fsi_ctx* ctx, double F[3]);
+
 /* Mask chi[nz][ny][nx] and solid velocity us[3][nz][ny][nx] built from the
- * current wing (zero everywhere without a wing). Synchronizes. */
+ * current wing (zero everywhere without a wing; the static penalization is
+ * not included). Synchronizes. */
 fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us);
 
 /* For callers that cannot allocate device memory (code under HIP graph

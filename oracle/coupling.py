@@ -71,7 +71,8 @@ class CoupledOracle:
     def step(self, dt):
         x, v = self.q
         self.fluid.set_wing(x, v, self.tri)
-        F = self.fluid.step(dt=dt)["F"]
+        self.last = self.fluid.step(dt=dt)  # diagnostics of the fluid step
+        F = self.last["F"]
         if self.order == "paper":
             # p^{n+1} from u^{n+1}; the wing (and so the mask) is still at t^n
             self.fluid.nonlinear(*self.fluid.combined_mask())

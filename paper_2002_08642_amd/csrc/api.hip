@@ -160,6 +160,16 @@ fsi_status fsi_set_sponge(fsi_ctx* ctx, double c_sp, const double* gx, const dou
   return ctx->eng->set_sponge(c_sp, gx, gy, gz);
 }
 
+fsi_status fsi_set_static_mask(fsi_ctx* ctx, const double* chi, const double* us, const double* weight) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->set_static_mask(chi, us, weight);
+}
+
+fsi_status fsi_get_static_force(fsi_ctx* ctx, double F[3]) {
+  if (guard(ctx) != FSI_OK || !F) return FSI_EINVAL;
+  return ctx->eng->static_force(F);
+}
+
 fsi_status fsi_get_mask(fsi_ctx* ctx, double* chi, double* us) {
   if (guard(ctx) != FSI_OK || !chi || !us) return FSI_EINVAL;
   return ctx->eng->get_mask(chi, us);

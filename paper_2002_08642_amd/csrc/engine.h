@@ -23,6 +23,8 @@ class EngineBase {
   virtual fsi_status get_nonlinear(double* nh) = 0;
   virtual fsi_status set_wing(int nv, const double* x, const double* v, int nt, const int* tri) = 0;
   virtual fsi_status set_sponge(double c_sp, const double* gx, const double* gy, const double* gz) = 0;
+  virtual fsi_status set_static_mask(const double* chi, const double* us, const double* w) = 0;
+  virtual fsi_status static_force(double F[3]) = 0;
   virtual fsi_status get_mask(double* chi, double* us) = 0;
   // get_mask into device grids with caller-provided key scratch (2 * max_cells
   // u64); queued on the stream, allocates nothing

@@ -631,6 +631,58 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // static z-independent penalization (walls, fixed obstacles, inflow layers)
+  fsi_status set_static_mask(const double* chi_h, const double* us_h, const double* w_h) override {
+    if (!chi_h) {
+      static_on = false;
+      return FSI_OK;
+    }
+    if (!us_h) {
+      err = "u_s of the static mask is NULL";
+      return FSI_EINVAL;
+    }
+    const long long np2 = (long long)nx * ny;
+    for (long long i = 0; i < np2; ++i) {
+      if (!(chi_h[i] >= 0.0 && chi_h[i] <= 1.0)) {
+        err = "static chi must lie in [0, 1]";
+        return FSI_EINVAL;
+      }
+      if (w_h && !std::isfinite(w_h[i])) {
+        err = "non-finite static force weight";
+        return FSI_EINVAL;
+      }
+    }
+    for (long long i = 0; i < 3 * np2; ++i)
+      if (!std::isfinite(us_h[i])) {
+        err = "non-finite static u_s";
+        return FSI_EINVAL;
+      }
+    if (!st_chi_) {
+      FSI_TRY(alloc(&st_chi_, np2));
+      FSI_TRY(alloc(&st_us_, 3 * np2));
+      FSI_TRY(alloc(&st_w_, np2));
+    }
+    std::vector<T> h(5 * (size_t)np2);
+    for (long long i = 0; i < np2; ++i) {
+      h[i] = (T)chi_h[i];
+      h[4 * np2 + i] = w_h ? (T)w_h[i] : (T)0;
+    }
+    for (long long i = 0; i < 3 * np2; ++i) h[np2 + i] = (T)us_h[i];
+    FSI_TRY(sync_both());
+    FSI_HIP(hipMemcpy(st_chi_, h.data(), sizeof(T) * np2, hipMemcpyHostToDevice));
+    FSI_HIP(hipMemcpy(st_us_, h.data() + np2, sizeof(T) * 3 * np2, hipMemcpyHostToDevice));
+    FSI_HIP(hipMemcpy(st_w_, h.data() + 4 * np2, sizeof(T) * np2, hipMemcpyHostToDevice));
+    static_on = true;
+    return FSI_OK;
+  }
+
+  fsi_status static_force(double F[3]) override {
+    if (info_pending) FSI_HIP(hipEventSynchronize(info_ev));
+    else FSI_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < 3; ++q) F[q] = sc_host->fst[q];
+    return nan_status();
+  }
+
   // -- one step ------------------------------------------------------------------
   // vorticity sponge: chi_sp = max(gx[x], gy[y], gz[z]) (NULL profile = 0), c_sp <= 0: off
   fsi_status set_sponge(double c_sp, const double* gx, const double* gy, const double* gz) override {
@@ -682,7 +734,7 @@ class Engine : public EngineBase {
         err = "dt must be positive and finite";
         return FSI_EINVAL;
       }
-      if (wing_nt > 0 && dt / d.eta > 1.0) {
+      if ((wing_nt > 0 || static_on) && dt / d.eta > 1.0) {
         err = "dt * max(chi) / eta > 1: explicit penalization unstable";
         return FSI_ESTABILITY;
       }
@@ -872,6 +924,11 @@ class Engine : public EngineBase {
         a.pnz = pnz;
         a.pcells = pcells;
       }
+    }
+    if (static_on) {
+      a.st_chi = st_chi_;
+      a.st_us = st_us_;
+      a.st_w = st_w_;
     }
     a.inv_eta = (T)(1.0 / d.eta);
     return a;
@@ -1213,6 +1270,10 @@ class Engine : public EngineBase {
       err = "nx too long for the adjoint x pass in this precision";
       return FSI_EINVAL;
     }
+    if (static_on) {
+      err = "the reverse step does not include the static penalization (fsi_set_static_mask)";
+      return FSI_ESTATE;
+    }
     FSI_TRY(ensure_adjoint());
     const bool wing = wing_nt > 0 && bcells > 0;
     if (wing) {
@@ -1505,6 +1566,9 @@ class Engine : public EngineBase {
     free_dev(tsp_);
     free_dev(spadj_);
     free_dev(dmesh_);
+    free_dev(st_chi_);
+    free_dev(st_us_);
+    free_dev(st_w_);
     dx_ = dv_ = nullptr;
     dtri_ = nullptr;
     free_dev(key1);
@@ -1851,6 +1915,8 @@ class Engine : public EngineBase {
   hipEvent_t e_ready = nullptr, e_mask = nullptr, e_x = nullptr, e_fin = nullptr;
   hipEvent_t e_up = nullptr;  // mesh upload done (side stream)
   cpx<T>* rec_bt = nullptr;   // tape of the step being recorded (u, omega after P2)
+  bool static_on = false;     // static penalization plane set
+  T *st_chi_ = nullptr, *st_us_ = nullptr, *st_w_ = nullptr;
   bool mesh_pending = false;
   // timing events of one step
   enum { EV_MASK0, EV_MASK1, EV_P1_0, EV_P2_0, EV_P2_1, EV_P3_0, EV_P3_1, EV_RED0, EV_RED1, EV_P4_1, EV_P5_0,

@@ -41,6 +41,7 @@ struct DevScalars {
   double dt[2];     // dt_n and dt_{n-1}, indexed by step parity
   double t;         // time after the last completed step
   double info[8];   // F[3], E, umax, dt, nonfinite flag, spare
+  double fst[3];    // force of the static penalization (weighted)
 };
 
 template <typename T>
@@ -119,6 +120,11 @@ struct XArgs {
   T* up;
   int px0, py0, pz0, pnx, pny, pnz;
   long long pcells;
+  // static z-independent penalization (fused mode; NULL: off): chi [y][x],
+  // u_s [3][y][x] (component stride ny * nx), force weight [y][x]
+  const T* st_chi;
+  const T* st_us;
+  const T* st_w;
 };
 
 // p = Pi - |u|^2/2 at the cells of the pressure box (out, FP64), and the

@@ -1236,13 +1236,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 // LDS holds n rows of packed signals with a padded row stride (odd number of
 // complex values against bank conflicts), then the twiddle table.
 
+// Penalization at one grid point with the static plane on (max rule): the
+// static solid's chi, u_s at plane index sidx, replaced by the wing's at
+// sub-box cell `cell` (-1: outside the sub-box) where the wing's chi is larger.
+// Subtracts (chi/eta)(u - u_s) from G and adds chi (u - u_s) to the force sums
+// of the solid that wins (weighted by the static force weight).
+template <typename T>
+__device__ __forceinline__ void penalize_static(const XArgs<T>& a, long long cell, long long sidx, T ux, T uy, T uz,
+                                                T& gx, T& gy, T& gz, double& f0, double& f1, double& f2, double& s0,
+                                                double& s1, double& s2) {
+  const long long plane = (long long)a.ny * a.n;
+  T ch = a.st_chi[sidx], u0 = a.st_us[sidx], u1 = a.st_us[plane + sidx], u2 = a.st_us[2 * plane + sidx];
+  bool wing = false;
+  if (cell >= 0) {
+    const T cw = a.chi[cell];
+    if (cw > ch) {
+      ch = cw;
+      u0 = a.us[cell];
+      u1 = a.us[a.bcells + cell];
+      u2 = a.us[2 * a.bcells + cell];
+      wing = true;
+    }
+  }
+  if (ch != (T)0) {
+    const T sx = ux - u0, sy = uy - u1, sz = uz - u2;
+    const T ce = ch * a.inv_eta;
+    gx -= ce * sx;
+    gy -= ce * sy;
+    gz -= ce * sz;
+    if (wing) {
+      f0 += (double)(ch * sx);
+      f1 += (double)(ch * sy);
+      f2 += (double)(ch * sz);
+    } else {
+      const T cwt = ch * a.st_w[sidx];
+      s0 += (double)(cwt * sx);
+      s1 += (double)(cwt * sy);
+      s2 += (double)(cwt * sz);
+    }
+  }
+}
+
 // Fused pass: C2R of (u, omega) for L lines, G = u x omega - (chi/eta)(u - u_s),
 // partial sums of the diagnostics, R2C of G truncated to the x band.
-template <typename T, int L, int NT, int MAXE>
+template <typename T, int L, int NT, int MAXE, bool ST>
 __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  __shared__ double red[5 * (NT / 64)];
+  __shared__ double red[8 * (NT / 64)];
   constexpr int WI = 3 * L;      // inverse: pairs (ux,uy) (uz,wx) (wy,wz) per line
   constexpr int WF = 3 * L / 2;  // forward: (Gx,Gy) per line, (Gz,Gz') per line pair
   constexpr int RI = PadStride<WI>::value;
@@ -1256,7 +1297,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
   const int nitems = 3 * L * a.kx1;
   cpx<T>* tws = buf + n * RI;
   for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
-  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
+  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
 
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int tid = opaque((int)threadIdx.x);
@@ -1311,7 +1352,14 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
         T gx = uy * wz - uz * wy;
         T gy = uz * wx - ux * wz;
         T gz = ux * wy - uy * wx;
-        if (a.bnx > 0) {
+        if constexpr (ST) {
+          const int line = line0 + l;
+          const int z = line / a.ny, y = line - z * a.ny;
+          const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
+          const bool in = a.bnx > 0 && bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz;
+          const long long cell = in ? ((long long)bz * a.bny + by) * a.bnx + bx : -1;
+          penalize_static<T>(a, cell, (long long)y * n + x, ux, uy, uz, gx, gy, gz, aF0, aF1, aF2, aS0, aS1, aS2);
+        } else if (a.bnx > 0) {
           const int line = line0 + l;
           const int z = line / a.ny, y = line - z * a.ny;
           const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
@@ -1387,8 +1435,8 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
     __syncthreads();
   }
 
-  double v[4] = {aF0, aF1, aF2, aE};
-  block_sum<4, NT>(v, red);
+  double v[7] = {aF0, aF1, aF2, aE, aS0, aS1, aS2};
+  block_sum<ST ? 7 : 4, NT>(reinterpret_cast<double(&)[ST ? 7 : 4]>(v), red);
   __syncthreads();
   const double m = block_max<NT>(aM, red);
   if (tid == 0) {
@@ -1398,9 +1446,9 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
     p[2] = v[2];
     p[3] = v[3];
     p[4] = m;
-    p[5] = 0;
-    p[6] = 0;
-    p[7] = 0;
+    p[5] = ST ? v[4] : 0.0;
+    p[6] = ST ? v[5] : 0.0;
+    p[7] = ST ? v[6] : 0.0;
   }
 }
 
@@ -1419,11 +1467,11 @@ __device__ __forceinline__ void load512_sig(const XArgs<T>& a, int line, int p, 
 // diagnostics, R2C of (Gx, Gy) stored; returns Gz in the physical layout.
 // On entry pf holds the line's first packed signal; on exit it holds the first
 // signal of line `next` (if next >= 0), loaded while this line is transformed.
-template <typename T>
+template <typename T, bool ST>
 __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int next, int lane, cpx<T>* X,
                                              const cpx<T>* tIB, const cpx<T>* tC, const cpx<T>* tFB, Raw512<T>& pf,
                                              T (&gz)[8], double& aF0, double& aF1, double& aF2, double& aE,
-                                             double& aM) {
+                                             double& aM, double& aS0, double& aS1, double& aS2) {
   constexpr int K = 170;  // the 2/3 band of 512 points: 3 * 170 < 512
   cpx<T> P[3][8];
 #pragma unroll
@@ -1465,7 +1513,19 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
     }
   }
   const int by = y - a.by0, bz = z - a.bz0;
-  if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
+  if constexpr (ST) {  // static plane on every line, the wing's sub-box where it has one
+    const bool inbox = a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz;  // uniform per wave
+    const long long rowcell = inbox ? ((long long)bz * a.bny + by) * a.bnx : 0;
+    const long long srow = (long long)y * a.n;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int x = (lane >> 3) + 8 * (lane & 7) + 64 * j;
+      const int bx = x - a.bx0;
+      const long long cell = (inbox && bx >= 0 && bx < a.bnx) ? rowcell + bx : -1;
+      penalize_static<T>(a, cell, srow + x, P[0][j].re, P[0][j].im, P[1][j].re, g[j].re, g[j].im, gz[j], aF0, aF1,
+                         aF2, aS0, aS1, aS2);
+    }
+  } else if (a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {  // uniform per wave
     const long long rowcell = ((long long)bz * a.bny + by) * a.bnx;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -1493,13 +1553,13 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
   unpack_store512<T>(g, lane, K, a.gout + (long long)line * a.ld, a.gout + a.sfs + (long long)line * a.ld);
 }
 
-template <typename T>
+template <typename T, bool ST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void xpass_wave512(XArgs<T> a) {
   __shared__ cpx<T> xbuf[4][kXBuf];
   // per-lane twiddle sets, [j][lane]: exp(+2 pi i lane j / 512), exp(-2 pi i lo j / 64),
   // exp(-2 pi i (lo + 8 j) hi / 512) with lo = lane & 7, hi = lane >> 3
   __shared__ cpx<T> tws[3][512];
-  __shared__ double red[5 * 4];
+  __shared__ double red[8 * 4];
   // Gz of the first line of a pair waits here (lane-private slots) while the
   // second line is transformed: registers are what limits the waves per SIMD
   __shared__ T gzs[4][8][64];
@@ -1513,7 +1573,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
   const cpx<T>* tIB = tws[0];
   const cpx<T>* tC = tws[1];
   const cpx<T>* tFB = tws[2];
-  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0;
+  double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
   const int npairs = a.nlines / 2;
   Raw512<T> pf;
   const int pr0 = blockIdx.x * 4 + wv;
@@ -1524,12 +1584,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
     const int ln = opaque(lane);
     {
       T gza[8];
-      wave512_line<T>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM);
+      wave512_line<T, ST>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM, aS0, aS1, aS2);
 #pragma unroll
       for (int j = 0; j < 8; ++j) gzs[wv][j][lane] = gza[j];
     }
     T gzb[8];
-    wave512_line<T>(a, 2 * pr + 1, nxt, opaque(lane), X, tIB, tC, tFB, pf, gzb, aF0, aF1, aF2, aE, aM);
+    wave512_line<T, ST>(a, 2 * pr + 1, nxt, opaque(lane), X, tIB, tC, tFB, pf, gzb, aF0, aF1, aF2, aE, aM, aS0, aS1,
+                        aS2);
     cpx<T> g[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = mk<T>(gzs[wv][j][lane], gzb[j]);
@@ -1538,8 +1599,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
     unpack_store512<T>(g, l3, K, a.gout + 2 * a.sfs + (long long)(2 * pr) * a.ld,
                        a.gout + 2 * a.sfs + (long long)(2 * pr + 1) * a.ld);
   }
-  double v[4] = {aF0, aF1, aF2, aE};
-  block_sum<4, 256>(v, red);
+  double v[7] = {aF0, aF1, aF2, aE, aS0, aS1, aS2};
+  block_sum<ST ? 7 : 4, 256>(reinterpret_cast<double(&)[ST ? 7 : 4]>(v), red);
   __syncthreads();
   const double m = block_max<256>(aM, red);
   if (threadIdx.x == 0) {
@@ -1549,9 +1610,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
     p[2] = v[2];
     p[3] = v[3];
     p[4] = m;
-    p[5] = 0;
-    p[6] = 0;
-    p[7] = 0;
+    p[5] = ST ? v[4] : 0.0;
+    p[6] = ST ? v[5] : 0.0;
+    p[7] = ST ? v[6] : 0.0;
   }
 }
 
@@ -1682,8 +1743,8 @@ __global__ __launch_bounds__(NT) void xpass_plain(XArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
-  __shared__ double red[5 * (kNT / 64)];
-  double v[4] = {0, 0, 0, 0};
+  __shared__ double red[8 * (kNT / 64)];
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
   double m = 0;
   for (int p = threadIdx.x; p < a.np; p += kNT) {
     const double* q = a.partials + (long long)p * 8;
@@ -1692,8 +1753,11 @@ __global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
     v[2] += q[2];
     v[3] += q[3];
     m = fmax(m, q[4]);
+    v[4] += q[5];
+    v[5] += q[6];
+    v[6] += q[7];
   }
-  block_sum<4, kNT>(v, red);
+  block_sum<7, kNT>(v, red);
   __syncthreads();
   m = block_max<kNT>(m, red);
   if (threadIdx.x == 0) {
@@ -1719,6 +1783,9 @@ __global__ __launch_bounds__(kNT) void finalize_kernel(FinalArgs a) {
     s->info[5] = dt;
     s->info[6] = bad ? 1.0 : s->info[6];
     s->info[7] = s->t;
+    s->fst[0] = v[4] * a.dV * a.inv_eta;
+    s->fst[1] = v[5] * a.dV * a.inv_eta;
+    s->fst[2] = v[6] * a.dV * a.inv_eta;
   }
 }
 
@@ -2031,24 +2098,31 @@ int xpass_lines(int n) {
   return (n * 6 <= XCfg<T, 2>::MAXE * XCfg<T, 2>::NT) ? 2 : 0;
 }
 
-template <typename T, int L>
+template <typename T, int L, bool ST>
 static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
   constexpr int NT = XCfg<T, L>::NT, M = XCfg<T, L>::MAXE;
   const size_t lds = (size_t)a.n * (PadStride<3 * L>::value + 1) * sizeof(cpx<T>);
-  hipError_t e = set_lds(xpass_fused<T, L, NT, M>, lds);
+  hipError_t e = set_lds(xpass_fused<T, L, NT, M, ST>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((xpass_fused<T, L, NT, M>), dim3(grid), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((xpass_fused<T, L, NT, M, ST>), dim3(grid), dim3(NT), lds, s, a);
   return hipGetLastError();
+}
+
+// the static plane selects its own instantiation: without it the kernels keep
+// their registers and code
+template <typename T, bool ST>
+static hipError_t launch_xfused_st(const XArgs<T>& a, int grid, hipStream_t s) {
+  if (a.n == 512) {
+    hipLaunchKernelGGL((xpass_wave512<T, ST>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4, ST>(a, grid, s);
+  return launch_xfused_l<T, 2, ST>(a, grid, s);
 }
 
 template <typename T>
 hipError_t launch_xfused(const XArgs<T>& a, int grid, hipStream_t s) {
-  if (a.n == 512) {
-    hipLaunchKernelGGL(xpass_wave512<T>, dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-  if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4>(a, grid, s);
-  return launch_xfused_l<T, 2>(a, grid, s);
+  return a.st_chi ? launch_xfused_st<T, true>(a, grid, s) : launch_xfused_st<T, false>(a, grid, s);
 }
 
 // Workgroups of the fused x pass for nlines lines of length n (bounded: each

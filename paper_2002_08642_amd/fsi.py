@@ -42,7 +42,7 @@ EXPORTS = [
     "fsi_set_timing", "fsi_get_pass_times", "fsi_plate_pose", "fsi_get_nonlinear",
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
     "fsi_sample_pressure", "fsi_get_pressure_loads", "fsi_get_pressure_box", "fsi_adjoint_set_pressure_seed",
-    "fsi_get_mask_noalloc", "fsi_eval_pressure",
+    "fsi_get_mask_noalloc", "fsi_eval_pressure", "fsi_set_static_mask", "fsi_get_static_force",
 ]
 NOALLOC_MASK_CELLS = 1 << 20  # FSI_NOALLOC_MASK_CELLS
 
@@ -117,6 +117,8 @@ def load_library():
     lib.fsi_sample_pressure.argtypes = [P, I32, D, D]
     lib.fsi_get_pressure_loads.argtypes = [P, D, D]
     lib.fsi_eval_pressure.argtypes = [P]
+    lib.fsi_set_static_mask.argtypes = [P, D, D, D]
+    lib.fsi_get_static_force.argtypes = [P, D]
     lib.fsi_get_pressure_box.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
     lib.fsi_adjoint_set_pressure_seed.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), D]
     lib.fsi_ms_create.argtypes = [I32, D, ctypes.POINTER(P)]
@@ -322,6 +324,24 @@ class Solver:
         self._check(self.lib.fsi_set_sponge(self.ctx, float(c_sp),
                                             *[None if g is None else _dptr(g) for g in prof]))
         self._sponge_keep = prof
+
+    def set_static_mask(self, chi, us, weight=None):
+        """Static z-independent penalization chi (ny, nx), u_s (3, ny, nx), force
+        weight (ny, nx) or None; chi = None removes it (fsi_set_static_mask)."""
+        nx, ny, _ = self.n
+        if chi is None:
+            self._check(self.lib.fsi_set_static_mask(self.ctx, None, None, None))
+            return
+        c = _f64(chi, (ny, nx))
+        u = _f64(us, (3, ny, nx))
+        w = None if weight is None else _f64(weight, (ny, nx))
+        self._check(self.lib.fsi_set_static_mask(self.ctx, _dptr(c), _dptr(u), _optd(w)))
+
+    def static_force(self):
+        """Weighted force of the static penalization at t^n of the last step."""
+        F = np.zeros(3)
+        self._check(self.lib.fsi_get_static_force(self.ctx, _dptr(F)))
+        return F
 
     def clear_wing(self):
         self._check(self.lib.fsi_set_wing(self.ctx, 0, None, None, 0, None))

@@ -410,3 +410,122 @@ def hinge_plate(ns=41, nc=13, span=3.0, chord=1.0, k_hinge=(1e-2, 1e-2, 1e-2, 1e
                 bend_ijk=np.array(ijk, dtype=np.int32), bend_axis=np.array(axis, dtype=np.int32),
                 bend_group=np.array(group, dtype=np.int32), bend_kb=np.array(kb), clamped=clamped,
                 density=density, scale=scale)
+
+
+# ---------------------------------------------------------------------------
+# channel with a cylinder and a flexible flag (the FSI3-style workload of
+# Sec. 4.2.1): static penalization plane and flag network
+# ---------------------------------------------------------------------------
+
+TUREK_H = 0.41      # channel height
+TUREK_LEN = 2.5     # channel length
+TUREK_R = 0.05      # cylinder radius
+TUREK_C = (0.2, 0.2)  # cylinder centre from the inlet and the lower wall
+TUREK_FLAG = (0.35, 0.02)  # flag length and thickness
+TUREK_UMEAN = 2.0   # mean inflow velocity
+
+
+def _smooth_step(sigma, h):
+    """Solid indicator from a signed distance sigma (> 0 inside the solid),
+    smoothed over |sigma| < h with the cosine shape of the wing mask: 0 at
+    sigma = -h, 1/2 on the surface, 1 at sigma = h."""
+    sig = np.clip(np.asarray(sigma, dtype=np.float64), -h, h)
+    return 0.5 * (1.0 + np.sin(0.5 * np.pi * sig / h))
+
+
+def turek_channel(nx, ny, nz, wall=0.05, inflow=0.2, h_cells=1.0, depth_cells=None):
+    """Quasi-2-D channel of height 0.41 and length 2.5 between penalized walls of
+    thickness `wall`, a penalized inflow layer of width `inflow` upstream of the
+    inlet imposing the Poiseuille profile of mean 2 (periodic box: the outflow
+    re-enters through it), and a cylinder of radius 0.05 centred 0.2 behind
+    the inlet and 0.2 above the lower wall.  Box (2.5 + inflow, 0.41 + 2 wall,
+    nz dx); smoothing half-width h = h_cells dx.  Returns the workload dict with
+    the static plane (chi, u_s [3], weight: 1 on the cylinder) and the flag
+    plate (span along x behind the cylinder, chord along z, normal along y)."""
+    Lx = TUREK_LEN + inflow
+    Ly = TUREK_H + 2 * wall
+    dx = Lx / nx
+    Lz = nz * dx if depth_cells is None else depth_cells * dx
+    h = h_cells * dx
+    x = (np.arange(nx) * dx)[None, :]
+    y = (np.arange(ny) * (Ly / ny))[:, None]
+    # walls: below y = wall and above y = wall + H (periodic in y: one slab)
+    s_wall = np.maximum(wall - y, y - (wall + TUREK_H)) + 0.0 * x
+    chi_wall = _smooth_step(s_wall, h)
+    # inflow layer x in [0, inflow] (distance to its faces, periodic in x)
+    s_in = np.where(x <= inflow, np.minimum(x, inflow - x), -np.minimum(x - inflow, Lx - x)) + 0.0 * y
+    chi_in = _smooth_step(s_in, h)
+    xc, yc = inflow + TUREK_C[0], wall + TUREK_C[1]
+    s_cyl = TUREK_R - np.sqrt((x - xc) ** 2 + (y - yc) ** 2)
+    chi_cyl = _smooth_step(s_cyl, h)
+    chi = np.maximum(np.maximum(chi_wall, chi_in), chi_cyl)
+    us = np.zeros((3, ny, nx))
+    eta_y = np.clip((y - wall) / TUREK_H, 0.0, 1.0)
+    poiseuille = 6.0 * TUREK_UMEAN * eta_y * (1.0 - eta_y)  # mean 2, maximum 3
+    inflow_wins = (chi_in >= chi_wall) & (chi_in >= chi_cyl)
+    us[0] = np.where(inflow_wins, poiseuille + 0.0 * x, 0.0)
+    weight = ((chi_cyl > chi_wall) & (chi_cyl > chi_in)).astype(np.float64)
+    return dict(n=(nx, ny, nz), L=(Lx, Ly, Lz), dx=dx, h=h, static=(chi, us, weight),
+                cylinder=(xc, yc, TUREK_R), wall=wall, inflow=inflow)
+
+
+def turek_inflow_field(ch):
+    """u = (U(y), 0, 0) with the Poiseuille profile of the inflow layer between
+    the walls (mean 2, zero outside the channel): a developed channel flow to
+    start from."""
+    nx, ny, nz = ch["n"]
+    y = np.arange(ny) * (ch["L"][1] / ny)
+    eta_y = np.clip((y - ch["wall"]) / TUREK_H, 0.0, 1.0)
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = (6.0 * TUREK_UMEAN * eta_y * (1.0 - eta_y))[None, :, None]
+    return u
+
+
+def turek_flag(ch, ns=15, nc=4, tw=None, density=0.02, E=5.6e6 / 1000.0, k_ext_scale=1.0):
+    """Mass-spring flag of the channel workload: a plate of length 0.35 behind
+    the cylinder (root inside it), chord along z over the box depth minus the
+    mask support and the pressure stencil at both ends.  Material in units of the fluid density
+    (rho_s = rho_f, E / rho_f): areal density rho_s h / rho_f = 0.02, bending
+    rigidity per unit depth E h^3 / 12, extension E h.  Bending springs along
+    the span on every chordwise row (k^b of Eq. EI_k_relation for that row's
+    share of the depth) and stiff chordwise bending (the flag stays plane in z);
+    the first two span columns (inside the cylinder) are clamped."""
+    xc, yc, R = ch["cylinder"]
+    thick = TUREK_FLAG[1]
+    tw = 0.5 * thick if tw is None else tw
+    rsup = tw + ch["h"]
+    # the pressure box (the 4-point stencils of points within t_w + h of the
+    # mesh) must stay inside the box depth: a margin of t_w + h + 3 dx each side
+    depth = ch["L"][2] - 2.0 * (rsup + 3.0 * ch["dx"])
+    if depth <= 0:
+        raise ValueError("box too shallow for the flag: increase nz")
+    x_root = xc + np.sqrt(R * R - (0.5 * thick) ** 2) - 0.02  # clamped nodes inside the cylinder
+    span = xc + R + TUREK_FLAG[0] - x_root
+    s, c = plate_span_chord(ns, nc, span, depth)
+    tri = grid_triangles(ns, nc)
+    edges = _grid_edges(ns, nc)
+    lens = np.where(np.abs(edges[:, 1] - edges[:, 0]) == 1, span / (ns - 1),
+                    np.where(np.abs(edges[:, 1] - edges[:, 0]) == ns, depth / (nc - 1),
+                             np.hypot(span / (ns - 1), depth / (nc - 1))))
+    k_ext = k_ext_scale * E * thick * depth / lens / nc  # axial stiffness of the strip a spring stands for
+    EI_row = E * thick ** 3 / 12.0 * depth / nc
+    n_b = ns - 2
+    kb_span = EI_row / span * n_b * (2 * n_b + 1) / (2.0 * (n_b + 1))
+    ijk, axis, kb = [], [], []
+    for j in range(nc):
+        for i in range(1, ns - 1):
+            v = j * ns + i
+            ijk.append((v - 1, v, v + 1))
+            axis.append(0)
+            kb.append(kb_span)
+    for i in range(ns):
+        for j in range(1, nc - 1):
+            v = j * ns + i
+            ijk.append((v - ns, v, v + ns))
+            axis.append(1)
+            kb.append(1e3 * kb_span)
+    clamped = np.array([j * ns + i for j in range(nc) for i in (0, 1)], dtype=np.int32)
+    kin = dict(alpha=0.5 * np.pi, omega=0.0, t_ramp=0.0, axis_point=(x_root, yc, 0.5 * ch["L"][2]))
+    wing = dict(span_coord=s, chord_coord=c, tri=tri, ext_ij=edges, ext_k=k_ext, clamped=clamped,
+                density=density)
+    return wing, np.array(ijk, dtype=np.int32), np.array(kb), np.array(axis, dtype=np.int32), kin, tw
