@@ -13,8 +13,10 @@ coupled step n (fluid at t^n, wing q^n = [x^n, v^n]):
     the loads of that pressure on the wing at x^n, root vertices clamped to
     the rigid kinematics at t^{n+1}, bending angles in the wing frame at
     t^{n+1}.
-Masses are lumped from the triangle areas; the wing rests in its initial
-configuration (frame at t = 0).
+Masses are lumped from the triangle areas with a uniform areal density, or
+given per vertex (the functional wing of Sec. 2.2: vein masses spread over the
+vein's vertices, the membrane mass law elsewhere); the wing rests in its
+initial configuration (frame at t = 0).
 
 Pins (tests/test_oracle_coupling.py): with a prescribed pressure field linear
 in space and in time, a free vertex without springs follows the closed-form
@@ -48,7 +50,10 @@ class CoupledOracle:
         self.tri = np.asarray(wing["tri"])
         self.clamped = np.asarray(wing["clamped"])
         x0, v0 = self._root_pose(0.0, None)
-        mass = structure.lumped_masses(x0, self.tri, wing["density"])
+        # masses: given per vertex (functional wing model), else lumped from the
+        # triangle areas with a uniform areal density
+        mass = (np.asarray(wing["mass"], dtype=np.float64) if wing.get("mass") is not None
+                else structure.lumped_masses(x0, self.tri, wing["density"]))
         self.net = structure.rest_network(mass, x0, wing["ext_ij"], wing["ext_k"], bend_ijk, bend_kb, bend_axis,
                                           self.clamped, self._frame(0.0))
         self.q = np.stack([x0, v0])

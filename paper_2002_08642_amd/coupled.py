@@ -42,7 +42,9 @@ class FlexibleWingFSI:
         self.tri = np.asarray(wing["tri"], dtype=np.int32)
         self.clamped = np.asarray(wing["clamped"], dtype=np.int32)
         x0, v0 = self._root_pose(0.0, None)
-        mass = fsi.lumped_masses(x0, self.tri, wing["density"])
+        # per-vertex masses of the functional wing model, else lumped from the areas
+        mass = (np.asarray(wing["mass"], dtype=np.float64) if wing.get("mass") is not None
+                else fsi.lumped_masses(x0, self.tri, wing["density"]))
         ms = fsi.MassSpring(mass)
         ext = np.asarray(wing["ext_ij"])
         ms.add_extension(ext, wing["ext_k"], np.ones(len(ext)))

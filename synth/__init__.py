@@ -529,3 +529,132 @@ def turek_flag(ch, ns=15, nc=4, tw=None, density=0.02, E=5.6e6 / 1000.0, k_ext_s
     wing = dict(span_coord=s, chord_coord=c, tri=tri, ext_ij=edges, ext_k=k_ext, clamped=clamped,
                 density=density)
     return wing, np.array(ijk, dtype=np.int32), np.array(kb), np.array(axis, dtype=np.int32), kin, tw
+
+
+# ---------------------------------------------------------------------------
+# functional bumblebee forewing (Sec. 3): printed vein diameters and masses,
+# membrane mass law, vein stiffness from a Young modulus, on a synthetic
+# planform and vein layout (the measured venation is not available)
+# ---------------------------------------------------------------------------
+
+# Table vein_mass, forewing: (nominal diameter, nominal mass), normalized by the
+# wing length L and by rho_air L^3
+FOREWING_VEINS = [
+    (0.0070, 0.0209), (0.0074, 0.0237), (0.0055, 0.0076), (0.0070, 0.0063), (0.0040, 0.0031),
+    (0.0048, 0.0094), (0.0040, 0.0019), (0.0038, 0.0009), (0.0041, 0.0023), (0.0048, 0.0064),
+    (0.0045, 0.0017), (0.0038, 0.0018), (0.0042, 0.0010), (0.0038, 0.0020), (0.0034, 0.0008),
+    (0.0032, 0.0005), (0.0032, 0.0004), (0.0044, 0.0009), (0.0015, 0.0001), (0.0018, 0.0001),
+    (0.0020, 0.0009),
+]
+RHO_CUTICLE = 1300.0 / 1.2248   # cuticle density over air density (the mass scale 2.817 mg over (13.2 mm)^3)
+E_FLEXIBLE = 1.25e8           # Young modulus of the flexible wing (35 kPa) in the wing's units, Sec. 4.3
+E_HIGHLY_FLEXIBLE = 1.25e7    # highly flexible wing (3.5 kPa)
+
+
+def membrane_mass(x, y):
+    """Mass of a membrane mass point at (x, y) (wing lengths; x spanwise from the
+    root, y chordwise increasing towards the leading edge), Sec. 3.2 bi-linear law."""
+    return 1.75e-4 - 2.83e-4 * np.asarray(x) + 4.91e-4 * np.asarray(y)
+
+
+def functional_wing(ns=31, nc=16, span=3.0, omega=2 * math.pi, E=E_FLEXIBLE, seed=0,
+                    k_membrane_range=(10.0, 100.0), y_le=0.32, root_chord=0.30, tip_chord=0.08):
+    """Forewing of the functional model (Sec. 2.3 vein and membrane models,
+    Sec. 3.2 masses, Sec. 3.3 stiffness) on a synthetic layout.
+
+    Planform (wing lengths): straight leading edge at y = y_le, chord tapering
+    linearly from root_chord to tip_chord; an ns x nc mapped grid, triangulated
+    as grid_triangles.  The 21 veins of the table keep their nominal diameter d
+    and mass m; each vein's length follows from them (a cuticle rod:
+    l = 4 m / (rho_c pi d^2)).  Veins of length >= 0.25 run spanwise from the
+    root along the rows j = nc-1, nc-3, ... (leading edge first); the others
+    are chordwise cross veins from the leading edge down the columns 2, 4, ...
+    (2, 3, ... on a grid too short for that);
+    a vein covers round(l / grid spacing) segments (at least two).  Vein mass is
+    spread evenly over its nodes; every other node takes the membrane mass law.
+    Vein flexural rigidity EI = E pi d^4 / 64 (E dimensionless as printed in
+    Sec. 4.3); each bending spring carries its vein's EI, length l_b and
+    spring count n_b, from which a solver takes k^b by Eq. EI_k_relation.  The
+    vein extension springs only keep the vein's length: their stiffness is an
+    artificial choice, here the rod's axial stiffness E pi d^2 / 4 / (edge
+    length); membrane edges get a seeded stiffness log-uniform in
+    k_membrane_range (no membrane data in the paper).  Units: the wing's
+    (length L, tip speed 1, rho_air) converted to the fluid's (span `span`,
+    angular speed `omega`, density 1): mass x span^3, EI x omega^2 span^6,
+    axial stiffness x omega^2 span^3, lengths x span.  Root columns 0, 1 are
+    clamped."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(ns)
+    j = np.arange(nc)
+    xw = i / (ns - 1.0)
+    chord = root_chord + (tip_chord - root_chord) * xw
+    yw = (y_le - chord)[None, :] + (j / (nc - 1.0))[:, None] * chord[None, :]  # [j][i]
+    X = np.tile(xw, nc)
+    Y = yw.reshape(-1)
+    y_mid = y_le - 0.5 * root_chord
+    s_coord = X * span
+    c_coord = (Y - y_mid) * span
+    tri = grid_triangles(ns, nc)
+    edges = _grid_edges(ns, nc)
+    lengths = [4.0 * m / (RHO_CUTICLE * math.pi * d * d) for d, m in FOREWING_VEINS]
+    order = sorted(range(len(FOREWING_VEINS)), key=lambda v: -lengths[v])
+    veins = [None] * len(FOREWING_VEINS)
+    row, col = nc - 1, 2
+    n_cross = len(FOREWING_VEINS) - min(sum(l >= 0.25 for l in lengths), (nc + 1) // 2)
+    col_step = 2 if 2 + 2 * (n_cross - 1) < ns else 1
+    for v in order:
+        if lengths[v] >= 0.25 and row >= 0:
+            nseg = max(2, min(ns - 1, int(round(lengths[v] * (ns - 1)))))
+            veins[v] = np.array([row * ns + a for a in range(nseg + 1)], dtype=np.int32)
+            row -= 2
+        else:
+            if col >= ns:
+                raise ValueError("grid too small for the cross veins")
+            dy = chord[col] / (nc - 1.0)
+            nseg = max(2, min(nc - 1, int(round(lengths[v] / dy))))
+            veins[v] = np.array([(nc - 1 - b) * ns + col for b in range(nseg + 1)], dtype=np.int32)
+            col += col_step
+    nv = ns * nc
+    mass = np.zeros(nv)
+    in_vein = np.zeros(nv, dtype=bool)
+    for v, nodes in enumerate(veins):
+        mass[nodes] += FOREWING_VEINS[v][1] / len(nodes)
+        in_vein[nodes] = True
+    mem = ~in_vein
+    mass[mem] = membrane_mass(X[mem], Y[mem])
+    if np.any(mass <= 0):
+        raise ValueError("membrane mass law gives a non-positive mass on this planform")
+    mscale, kscale, eiscale = span ** 3, omega ** 2 * span ** 3, omega ** 2 * span ** 6
+    # axial stiffness: vein edges from the vein's cross-section, membrane edges drawn
+    vein_edge = {}
+    for v, nodes in enumerate(veins):
+        for a, b in zip(nodes[:-1], nodes[1:]):
+            vein_edge[(min(a, b), max(a, b))] = v
+    P = np.stack([X, Y], axis=1)
+    klo, khi = np.log(k_membrane_range[0]), np.log(k_membrane_range[1])
+    ext_k = np.exp(klo + (khi - klo) * rng.random(len(edges)))
+    for e, (a, b) in enumerate(edges):
+        v = vein_edge.get((min(int(a), int(b)), max(int(a), int(b))))
+        if v is not None:
+            d = FOREWING_VEINS[v][0]
+            ext_k[e] = E * math.pi * d * d / 4.0 / float(np.linalg.norm(P[a] - P[b]))
+    ext_k = ext_k * kscale
+    # bending springs along each vein with the vein's EI, l_b and n_b
+    ijk, EI, lb, nb, axis, owner = [], [], [], [], [], []
+    for v, nodes in enumerate(veins):
+        d = FOREWING_VEINS[v][0]
+        l_b = float(np.sum(np.linalg.norm(np.diff(P[nodes], axis=0), axis=1))) * span
+        ax = 0 if abs(int(nodes[1]) - int(nodes[0])) == 1 else 1
+        for m in range(1, len(nodes) - 1):
+            ijk.append((nodes[m - 1], nodes[m], nodes[m + 1]))
+            EI.append(E * math.pi * d ** 4 / 64.0 * eiscale)
+            lb.append(l_b)
+            nb.append(len(nodes) - 2)
+            axis.append(ax)
+            owner.append(v)
+    clamped = np.array([jj * ns + ii for jj in range(nc) for ii in (0, 1)], dtype=np.int32)
+    return dict(span_coord=s_coord, chord_coord=c_coord, tri=tri, ext_ij=edges, ext_k=ext_k, clamped=clamped,
+                mass=mass * mscale, density=None, veins=veins, vein_length=[lengths[v] * span for v in range(len(veins))],
+                bend_ijk=np.array(ijk, dtype=np.int32), bend_EI=np.array(EI), bend_lb=np.array(lb),
+                bend_nb=np.array(nb, dtype=np.int32), bend_axis=np.array(axis, dtype=np.int32),
+                bend_owner=np.array(owner, dtype=np.int32), E=E, xw=X, yw=Y, ns=ns, nc=nc, span=span)

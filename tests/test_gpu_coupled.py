@@ -90,3 +90,36 @@ def test_full_flexible_wing_fp32_follows_fp64(n, dt, nsteps):
     print("config-2 wing %d^3: FP32 vs FP64 deflection %.3e force %.3e (max deflection %.3e)"
           % (n, ed, ef, np.max(np.abs(x64 - xr))), flush=True)
     assert ed < 1e-4 and ef < 1e-4
+
+
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+def test_functional_wing_coupled_96(prec):
+    """The functional bumblebee forewing (31 x 16 vertices, the 21 veins of
+    the table with their masses, the membrane mass law elsewhere, vein EI of the
+    flexible wing through Eq. EI_k_relation) revolving in the 96^3 box: GPU
+    fluid + native structure against oracle.coupling, 10 steps of dt = 1e-3."""
+    cfg = synth.revolving_plate(n=96, t_ramp=0.05)
+    w = synth.functional_wing()
+    kb_o = np.array([st.bending_stiffness(e, l, n) for e, l, n in zip(w["bend_EI"], w["bend_lb"], w["bend_nb"])])
+    kb_g = np.array([fsi.bending_stiffness(e, l, n) for e, l, n in zip(w["bend_EI"], w["bend_lb"], w["bend_nb"])])
+    kin = dict(alpha=cfg["alpha"], omega=cfg["omega"], t_ramp=cfg["t_ramp"], axis_point=cfg["axis_point"])
+    print("functional wing 96^3 prec %d" % prec, flush=True)
+    o = CoupledOracle(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], w,
+                      w["bend_ijk"], kb_o, w["bend_axis"], kin, tol=1e-12)
+    o.fluid.set_velocity(np.zeros((3,) + cfg["n"]))
+    s = fsi.Solver(cfg["n"], cfg["L"], cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], prec,
+                   pressure=True)
+    s.set_velocity(np.zeros((3,) + cfg["n"]))
+    g = FlexibleWingFSI(s, w, w["bend_ijk"], kb_g, w["bend_axis"], kin, tol=1e-12)
+    fo, fg = [], []
+    for _ in range(10):
+        fo.append(o.step(1e-3))
+        fg.append(g.step(1e-3))
+    x, v = g.state()
+    xr, _ = o._root_pose(o.t, None)
+    ex, ev, ef = rel(x - xr, o.q[0] - xr), rel(v, o.q[1]), rel(fg, fo)
+    print("functional wing 96^3 prec %d: deflection %.3e velocity %.3e force %.3e (max deflection %.3e, "
+          "Newton its %s)" % (prec, ex, ev, ef, np.max(np.abs(o.q[0] - xr)), g.iters), flush=True)
+    assert np.max(np.abs(o.q[0] - xr)) > 1e-5
+    assert ex < TOL[prec] and ev < TOL[prec] and ef < TOL[prec]
+    assert max(g.iters) <= 10
