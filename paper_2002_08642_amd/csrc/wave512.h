@@ -105,11 +105,49 @@ __device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, cons
   Bfly<T, 8, -1>::run(v);
 }
 
+// One complex value through a buffer resource whose bound is the band
+// [0, nk) of a line: a lane at k >= nk loads zeros and its store is dropped,
+// with no branch, no clamp and no memory traffic; the address is the
+// resource's scalar base plus a 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t band_rsrc(const cpx<T>* line, int nk) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cpx<T>*>(line), (short)0, nk * (int)sizeof(cpx<T>),
+                                           0x00020000);
+}
+// (whole-vector bit casts only: clang reads element 0 for a bit cast of a
+// vector element such as w.y)
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_band(__amdgpu_buffer_rsrc_t r, int k) {
+  const unsigned off = (unsigned)k * (unsigned)sizeof(cpx<T>);
+  typedef T F __attribute__((ext_vector_type(2)));
+  F w;
+  if constexpr (sizeof(T) == 4) w = __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, (FSI_NT & 8) ? 2 : 0));
+  else w = __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, (FSI_NT & 8) ? 2 : 0));
+  return mk<T>(w.x, w.y);
+}
+template <typename T>
+__device__ __forceinline__ void st_band(__amdgpu_buffer_rsrc_t r, int k, cpx<T> v) {
+  const unsigned off = (unsigned)k * (unsigned)sizeof(cpx<T>);
+  typedef T F __attribute__((ext_vector_type(2)));
+  F w;
+  w.x = v.re;
+  w.y = v.im;
+  if constexpr (sizeof(T) == 4) {
+    typedef unsigned V __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), r, off, 0, (FSI_NT & 1) ? 2 : 0);
+  } else {
+    typedef unsigned V __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, w), r, off, 0, (FSI_NT & 1) ? 2 : 0);
+  }
+}
+
 // Unpack the transforms X, Y of the two real signals packed in g (natural layout,
-// g[r] = G[lane + 64 r]) and store X to dx, Y to dy for k <= K (K < 192).
+// g[r] = G[lane + 64 r]) and store X to dx, Y to dy for k <= K (K < 192; the
+// stores beyond K fall outside the lines' band resources and are dropped).
 template <typename T>
 __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, int K, cpx<T>* dx, cpx<T>* dy) {
   const int src = (64 - lane) & 63;
+  const __amdgpu_buffer_rsrc_t rx = band_rsrc(dx, K + 1), ry = band_rsrc(dy, K + 1);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     cpx<T> p;
@@ -117,20 +155,17 @@ __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, 
     p.im = __shfl(g[7 - r].im, src, 64);
     if (lane == 0) p = g[(8 - r) & 7];
     const int k = lane + 64 * r;
-    if (k <= K) {
-      const cpx<T> zc = conj(p);
-      const cpx<T> d = g[r] - zc;
-      st_stream(at_u32(dx, k), scl(g[r] + zc, (T)0.5));
-      st_stream(at_u32(dy, k), mk<T>((T)0.5 * d.im, (T)-0.5 * d.re));
-    }
+    const cpx<T> zc = conj(p);
+    const cpx<T> d = g[r] - zc;
+    st_band(rx, k, scl(g[r] + zc, (T)0.5));
+    st_band(ry, k, mk<T>((T)0.5 * d.im, (T)-0.5 * d.re));
   }
 }
 
 // Raw spectral values a lane needs for one packed signal of one line: A, B at
-// k = lane + 64 r (r = 0, 1, 2).  The Hermitian partners n - k of
-// k = lane + 64 r (r = 5, 6, 7) are the same values held by lane 64 - lane
-// (r = 2, 1, 0) and are fetched across lanes by pack512; slots outside the
-// 2/3 band are zeroed there.
+// k = lane + 64 r (r = 0, 1, 2), zero outside the 2/3 band.  The Hermitian
+// partners n - k of k = lane + 64 r (r = 5, 6, 7) are the same values held by
+// lane 64 - lane (r = 2, 1, 0) and are fetched across lanes by pack512.
 template <typename T>
 struct Raw512 {
   cpx<T> a[3], b[3];
@@ -147,18 +182,18 @@ __device__ __forceinline__ cpx<T>* at_u32(cpx<T>* base, int i) {
   return reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(base) + (unsigned)i * (unsigned)sizeof(cpx<T>));
 }
 
-// The loads are unconditional (slots outside the band read index 0): a load
-// under a branch leaves the number of loads in flight unknown to the compiler,
-// which then waits for all of them, including a prefetch, at the next use.
+// A and B are wave-uniform line bases; the slots beyond the band (k > 170)
+// load zeros from the band resources (unconditional loads: a load under a
+// branch leaves the number of loads in flight unknown to the compiler, which
+// then waits for all of them, including a prefetch, at the next use).
 template <typename T>
 __device__ __forceinline__ void load512(const cpx<T>* A, const cpx<T>* B, int lane, Raw512<T>& w) {
   constexpr int K = 170;
+  const __amdgpu_buffer_rsrc_t ra = band_rsrc(A, K + 1), rb = band_rsrc(B, K + 1);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int k = lane + 64 * q;  // direct slots r = q
-    const int kc = k <= K ? k : 0;
-    w.a[q] = ld_xin(at_u32(A, kc));
-    w.b[q] = ld_xin(at_u32(B, kc));
+    w.a[q] = ld_band<T>(ra, lane + 64 * q);  // direct slots r = q
+    w.b[q] = ld_band<T>(rb, lane + 64 * q);
   }
 }
 
@@ -167,23 +202,23 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src) {
   return mk<T>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 
-// Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout v[r] = Z[lane + 64 r].
+// Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout
+// v[r] = Z[lane + 64 r].  The loads left every slot outside the band zero, so
+// only lane 0's partner of k = 320 (its own slot 2, in the band) is masked.
 template <typename T>
 __device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v)[8]) {
-  constexpr int n = 512, K = 170;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const bool ok = lane + 64 * q <= K, okp = lane + 64 * (5 + q) >= n - K;
-    v[q] = ok ? mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re) : mk<T>(0, 0);
+    v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
     // A[n - k], k = lane + 64 (5 + q): slot 2 - q of lane 64 - lane; lane 0
-    // holds it itself in slot 3 - q (for q = 0 that slot is outside the band)
+    // holds it itself in slot 3 - q (for q = 0, n - k = 192 is outside the band)
     const int src = (64 - lane) & 63;
     cpx<T> pa = shfl_cpx(w.a[2 - q], src), pb = shfl_cpx(w.b[2 - q], src);
-    if (q > 0 && lane == 0) {
-      pa = w.a[3 - q];
-      pb = w.b[3 - q];
+    if (lane == 0) {
+      pa = q > 0 ? w.a[3 - q] : mk<T>(0, 0);
+      pb = q > 0 ? w.b[3 - q] : mk<T>(0, 0);
     }
-    v[5 + q] = okp ? mk<T>(pa.re + pb.im, pb.re - pa.im) : mk<T>(0, 0);
+    v[5 + q] = mk<T>(pa.re + pb.im, pb.re - pa.im);
   }
   if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
   v[3] = mk<T>(0, 0);
