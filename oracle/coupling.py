@@ -73,10 +73,13 @@ class CoupledOracle:
         k = self.kin
         return kinematics.plate_frame(t, k["alpha"], k["omega"], k["t_ramp"], k.get("law", 0))
 
-    def step(self, dt):
+    def step(self, dt=None, cfl=None, c_eta=None, dt_max=None):
+        """One coupled step of size dt, or (dt None) of the fluid's adaptive dt
+        (CFL and penalization rule at t^n), which the structure step then uses."""
         x, v = self.q
         self.fluid.set_wing(x, v, self.tri)
-        self.last = self.fluid.step(dt=dt)  # diagnostics of the fluid step
+        self.last = self.fluid.step(dt=dt, cfl=cfl, c_eta=c_eta, dt_max=dt_max)  # diagnostics of the fluid step
+        dt = self.last["dt"]
         F = self.last["F"]
         if self.order == "paper":
             # p^{n+1} from u^{n+1}; the wing (and so the mask) is still at t^n

@@ -71,10 +71,24 @@ class FlexibleWingFSI:
 
     def step(self, dt):
         """One coupled step of size dt; returns the fluid force F^n."""
+        return self._step(dt, None)
+
+    def step_adaptive(self, cfl, c_eta, dt_max):
+        """One coupled step whose dt the fluid step chooses on the device (CFL
+        and penalization rule at t^n); the structure step uses the same dt.
+        Returns the fluid force F^n (the dt is in self.s.info())."""
+        return self._step(None, (cfl, c_eta, dt_max))
+
+    def _step(self, dt, rule):
         x, v = self.ms.state()
         self.s.set_wing(x, v, self.tri)
-        self.s.step(dt)
-        F = self.s.info()["F"]
+        if rule is None:
+            self.s.step(dt)
+        else:
+            self.s.step_adaptive(*rule)
+        info = self.s.info()
+        dt = info["dt"] if rule is not None else dt
+        F = info["F"]
         if self.order == "paper":
             self.s.eval_pressure()
         loads, _ = self.s.pressure_loads()

@@ -8,7 +8,9 @@ wing geometry and flow data are not used; these inputs stand in with the
 shapes of its revolving-wing runs (Sec. 4.2.2, Sec. 5).
 """
 
+import json
 import math
+import os
 
 import numpy as np
 
@@ -658,3 +660,40 @@ def functional_wing(ns=31, nc=16, span=3.0, omega=2 * math.pi, E=E_FLEXIBLE, see
                 bend_ijk=np.array(ijk, dtype=np.int32), bend_EI=np.array(EI), bend_lb=np.array(lb),
                 bend_nb=np.array(nb, dtype=np.int32), bend_axis=np.array(axis, dtype=np.int32),
                 bend_owner=np.array(owner, dtype=np.int32), E=E, xw=X, yw=Y, ns=ns, nc=nc, span=span)
+
+
+# ---------------------------------------------------------------------------
+# workload files (configs/*.json): parameters and readings of each workload
+# ---------------------------------------------------------------------------
+
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "configs")
+
+
+def load_config(name):
+    """The workload file configs/<name>.json (or a path) as a dict, with the
+    inputs its kind needs built from it: ``case`` holds the revolving-plate
+    parameters (revolving_plate) for the plate and wing kinds, ``wing`` the
+    flexible wing for flexible_wing, ``plate`` the hinge plate for hinge_plate,
+    ``case`` the config0 dict for taylor_green."""
+    path = name if os.path.exists(name) else os.path.join(CONFIG_DIR, name + ".json")
+    with open(path) as f:
+        c = json.load(f)
+    kind = c["kind"]
+    if kind == "taylor_green":
+        c["case"] = config0(True)
+    elif kind in ("revolving_plate", "flexible_wing", "hinge_plate"):
+        c["case"] = revolving_plate(n=int(c["n"]), box=float(c["box"]), t_ramp=float(c["t_ramp"]))
+        if kind == "flexible_wing":
+            w = c["wing"]
+            c["wing_net"] = flexible_wing(ns=w["ns"], nc=w["nc"], n_veins=w["n_veins"], vein_nodes=w["vein_nodes"],
+                                          seed=w["seed"], EI_range=tuple(w["EI_range"]),
+                                          k_membrane_range=tuple(w["k_membrane_range"]), k_vein=w["k_vein"],
+                                          density=w["density"])
+        if kind == "hinge_plate":
+            p = c["plate"]
+            c["plate_net"] = hinge_plate(ns=p["ns"], nc=p["nc"], k_hinge=tuple(c["theta"][1:]), k_ext=p["k_ext"],
+                                         density=p["density"], hinge_columns=tuple(p["hinge_columns"]))
+    elif kind != "throughput":
+        raise ValueError("unknown workload kind %r" % kind)
+    return c
+
