@@ -351,6 +351,15 @@ enum { FSI_NPASS = 7 };
 fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on);
 fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps);
 
+/* Testing aid for the memory layout, not part of the method: writes
+ * (value, value) into the padding columns of every row of the context's
+ * spectral buffers (the columns k_x > Kx up to the 128-byte row pitch, in the
+ * state, its nonlinear term, the work fields, the pressure and sponge
+ * spectra), then synchronizes.  No result of a later call may depend on these
+ * columns: a NaN written there must leave every step bit for bit unchanged.
+ * FSI_EINVAL for a bad context. */
+fsi_status fsi_debug_poison_padding(fsi_ctx* ctx, double value);
+
 /* Rigid revolving-plate pose (Sec. 4.2.2, Eq. (revolving_angle) and
  * Eq. (relative_velocities) without deformation). Host-only, FP64.
  * Inputs: nv vertices with span coordinate s[i] (from the rotation axis) and

@@ -78,8 +78,11 @@ class CoupledOracle:
         (CFL and penalization rule at t^n), which the structure step then uses."""
         x, v = self.q
         self.fluid.set_wing(x, v, self.tri)
-        self.last = self.fluid.step(dt=dt, cfl=cfl, c_eta=c_eta, dt_max=dt_max)  # diagnostics of the fluid step
-        dt = self.last["dt"]
+        # diagnostics of the fluid step
+        self.last = (self.fluid.step(dt=dt) if dt is not None
+                     else self.fluid.step(cfl=cfl, c_eta=c_eta, dt_max=dt_max))
+        if dt is None:
+            dt = self.last["dt"]
         F = self.last["F"]
         if self.order == "paper":
             # p^{n+1} from u^{n+1}; the wing (and so the mask) is still at t^n

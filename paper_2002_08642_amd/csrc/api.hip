@@ -295,6 +295,11 @@ fsi_status fsi_set_timing(fsi_ctx* ctx, int32_t on) {
   return ctx->eng->set_timing(u == 0 ? 0u : (u & FSI_TIME_PASSES) ? (u & all) : all);
 }
 
+fsi_status fsi_debug_poison_padding(fsi_ctx* ctx, double value) {
+  if (guard(ctx) != FSI_OK) return FSI_EINVAL;
+  return ctx->eng->poison_padding(value);
+}
+
 fsi_status fsi_get_pass_times(fsi_ctx* ctx, double ms[FSI_NPASS], int32_t* nsteps) {
   if (guard(ctx) != FSI_OK || !ms) return FSI_EINVAL;
   int n = 0;

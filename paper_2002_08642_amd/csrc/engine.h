@@ -48,6 +48,7 @@ class EngineBase {
   virtual fsi_status pressure_box(int box0[3], int boxn[3], double* p) = 0;
   virtual fsi_status set_pressure_seed(const int box0[3], const int boxn[3], const double* lam) = 0;
   virtual fsi_status set_timing(unsigned pass_mask) = 0;
+  virtual fsi_status poison_padding(double v) = 0;
   virtual fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) = 0;
   std::string err;
 };

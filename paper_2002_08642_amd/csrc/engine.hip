@@ -1492,6 +1492,24 @@ class Engine : public EngineBase {
     return FSI_OK;
   }
 
+  // every buffer whose rows have the padded pitch kxp: spectral state and
+  // its nonlinear term, the z- and y-slab work fields, the helper transform
+  // field, the pressure and sponge spectra, the tapes of the state slots
+  fsi_status poison_padding(double v) override {
+    FSI_TRY(sync_both());
+    const T t = (T)v;
+    FSI_HIP(launch_fill_pad<T>(uh, 3 * clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(nh, 3 * clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(A, 6 * Alen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(B, 6 * Blen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(cwork, clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(pi_, clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(tsp_, 3 * clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(launch_fill_pad<T>(spadj_, 3 * clen / kxp, kx1, kxp, t, s));
+    FSI_HIP(hipStreamSynchronize(s));
+    return FSI_OK;
+  }
+
   fsi_status pass_times(double ms[FSI_NPASS], int* nsteps) override {
     FSI_HIP(hipStreamSynchronize(s));
     if (s2) FSI_HIP(hipStreamSynchronize(s2));

@@ -1896,6 +1896,26 @@ __global__ __launch_bounds__(kNT) void fill_zero(T* p, long long n) {
   for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long long)gridDim.x * kNT) p[i] = (T)0;
 }
 
+// Writes (v, v) into the padding columns kx1 <= c < kxp of `rows` rows of pitch kxp.
+template <typename T>
+__global__ __launch_bounds__(kNT) void fill_pad(cpx<T>* p, long long rows, int kx1, int kxp, T v) {
+  const int w = kxp - kx1;
+  const long long n = rows * w;
+  for (long long i = (long long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long long)gridDim.x * kNT)
+    p[(i / w) * kxp + kx1 + i % w] = mk<T>(v, v);
+}
+
+template <typename T>
+hipError_t launch_fill_pad(cpx<T>* p, long long rows, int kx1, int kxp, T v, hipStream_t s) {
+  if (!p || rows <= 0 || kxp <= kx1) return hipSuccess;
+  long long blocks = (rows * (kxp - kx1) + kNT - 1) / kNT;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_pad<T>, dim3((unsigned)blocks), dim3(kNT), 0, s, p, rows, kx1, kxp, v);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_pad<float>(cpx<float>*, long long, int, int, float, hipStream_t);
+template hipError_t launch_fill_pad<double>(cpx<double>*, long long, int, int, double, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------

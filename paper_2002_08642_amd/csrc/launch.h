@@ -61,6 +61,9 @@ hipError_t launch_mask(const MaskArgs<T>& a, hipStream_t s);
 // gcells of MaskArgs), zeroed first; key1 / key2 may be any scratch of bcells each.
 template <typename T>
 hipError_t launch_mask_grid(const MaskArgs<T>& a, hipStream_t s);
+// (v, v) into the padding columns [kx1, kxp) of rows of pitch kxp (testing aid)
+template <typename T>
+hipError_t launch_fill_pad(cpx<T>* p, long long rows, int kx1, int kxp, T v, hipStream_t s);
 template <typename T>
 hipError_t launch_psample(const PressArgs<T>& a, hipStream_t s);
 template <typename T>

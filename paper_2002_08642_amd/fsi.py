@@ -43,6 +43,7 @@ EXPORTS = [
     "fsi_adjoint_set", "fsi_adjoint_get", "fsi_step_adjoint", "fsi_plate_pose_dalpha",
     "fsi_sample_pressure", "fsi_get_pressure_loads", "fsi_get_pressure_box", "fsi_adjoint_set_pressure_seed",
     "fsi_get_mask_noalloc", "fsi_eval_pressure", "fsi_set_static_mask", "fsi_get_static_force",
+    "fsi_debug_poison_padding",
 ]
 NOALLOC_MASK_CELLS = 1 << 20  # FSI_NOALLOC_MASK_CELLS
 
@@ -106,6 +107,7 @@ def load_library():
     lib.fsi_synchronize.argtypes = [P]
     lib.fsi_set_timing.argtypes = [P, I32]
     lib.fsi_get_pass_times.argtypes = [P, D, ctypes.POINTER(I32)]
+    lib.fsi_debug_poison_padding.argtypes = [P, ctypes.c_double]
     lib.fsi_plate_pose.argtypes = [I32, D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, I32, D, D, D, D]
     lib.fsi_get_nonlinear.argtypes = [P, D]
@@ -448,6 +450,11 @@ class Solver:
             self._check(self.lib.fsi_set_timing(self.ctx, TIME_PASSES | mask))
         else:
             self._check(self.lib.fsi_set_timing(self.ctx, 1 if on else 0))
+
+    def poison_padding(self, value):
+        """Write (value, value) into the padding columns of every spectral
+        buffer (fsi_debug_poison_padding; a layout check for tests)."""
+        self._check(self.lib.fsi_debug_poison_padding(self.ctx, float(value)))
 
     def pass_times(self):
         ms = np.zeros(NPASS)
