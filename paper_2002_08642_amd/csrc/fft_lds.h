@@ -254,17 +254,29 @@ __device__ void fft_lds(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
   }
 }
 
-// Column transform: N = 512 uses three radix-8 stages with compile-time strides
-// (the 512^3 grids), any other N the run-time plan.
+// The transform with a compile-time length: N = 512 runs three radix-8
+// stages, N = 800 the stages 8, 4, 5, 5 (the host plan of 800 = 2^5 5^2), with
+// compile-time strides and index arithmetic; N = 0 the run-time plan.
+template <typename T, int W, int RS, int NT, int MAXE, bool INV, int N>
+__device__ __forceinline__ void fft_n(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
+  if constexpr (N == 512) {
+    fft_stage<T, 8, W, RS, NT, MAXE, INV>(buf, 512, 1, tw);
+    fft_stage<T, 8, W, RS, NT, MAXE, INV>(buf, 512, 8, tw);
+    fft_stage<T, 8, W, RS, NT, MAXE, INV>(buf, 512, 64, tw);
+  } else if constexpr (N == 800) {
+    fft_stage<T, 8, W, RS, NT, MAXE, INV>(buf, 800, 1, tw);
+    fft_stage<T, 4, W, RS, NT, MAXE, INV>(buf, 800, 8, tw);
+    fft_stage<T, 5, W, RS, NT, MAXE, INV>(buf, 800, 32, tw);
+    fft_stage<T, 5, W, RS, NT, MAXE, INV>(buf, 800, 160, tw);
+  } else {
+    fft_lds<T, W, RS, NT, MAXE, INV>(buf, p, tw);
+  }
+}
+
+// Column transform (row stride W).
 template <typename T, int W, int NT, int MAXE, bool INV, int N>
 __device__ __forceinline__ void col_fft(cpx<T>* buf, const FftPlan& p, const cpx<T>* tw) {
-  if constexpr (N == 512) {
-    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 1, tw);
-    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 8, tw);
-    fft_stage<T, 8, W, W, NT, MAXE, INV>(buf, 512, 64, tw);
-  } else {
-    fft_lds<T, W, W, NT, MAXE, INV>(buf, p, tw);
-  }
+  fft_n<T, W, W, NT, MAXE, INV, N>(buf, p, tw);
 }
 
 // fft512_reg with one column per thread and slots at indices j and j + 32

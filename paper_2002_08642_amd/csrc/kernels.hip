@@ -1278,9 +1278,12 @@ __device__ __forceinline__ void penalize_static(const XArgs<T>& a, long long cel
 }
 
 // Fused pass: C2R of (u, omega) for L lines, G = u x omega - (chi/eta)(u - u_s),
-// partial sums of the diagnostics, R2C of G truncated to the x band.
-template <typename T, int L, int NT, int MAXE, bool ST>
-__global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
+// partial sums of the diagnostics, R2C of G truncated to the x band.  N != 0:
+// the line length as a compile-time constant (its plan, band and index
+// arithmetic; fft_n), N = 0: the run-time length and plan.
+template <typename T, int L, int NT, int MAXE, bool ST, int N>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((N == 800 && sizeof(T) == 4) ? 4 : 1)))
+void xpass_fused(XArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   __shared__ double red[8 * (NT / 64)];
@@ -1292,9 +1295,9 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
   constexpr int FI = MAXE / 3 + 2;  // band items (3 L (K+1)) per thread
   static_assert(L % 2 == 0, "L must be even");
   const int tid = threadIdx.x;
-  const int n = a.n, K = a.kx1 - 1;
+  const int n = N ? N : a.n, K = N ? (N - 1) / 3 : a.kx1 - 1, kx1 = K + 1;
   const int ngroups = a.nlines / L;
-  const int nitems = 3 * L * a.kx1;
+  const int nitems = 3 * L * kx1;
   cpx<T>* tws = buf + n * RI;
   for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
@@ -1309,7 +1312,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
       for (int k = 0; k < FI; ++k) {
         const int it = tid + k * NT;
         if (it < nitems) {
-          const int x = it % a.kx1, s = it / a.kx1;
+          const int x = it % kx1, s = it / kx1;
           const int l = s / 3, p = s - 3 * (s / 3);
           const long long off = (long long)(line0 + l) * a.ld + x;
           A[k] = a.spec[(2 * p) * a.sfs + off];
@@ -1320,7 +1323,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
       for (int k = 0; k < FI; ++k) {
         const int it = tid + k * NT;
         if (it < nitems) {
-          const int x = it % a.kx1, s = it / a.kx1;
+          const int x = it % kx1, s = it / kx1;
           if (x == 0) {
             buf[s] = mk<T>(A[k].re, B[k].re);
           } else {
@@ -1336,7 +1339,10 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
       }
     }
     __syncthreads();
-    fft_lds<T, WI, RI, NT, MAXE, true>(buf, a.plan, tws);
+    fft_n<T, WI, RI, NT, MAXE, true, N>(buf, a.plan, tws);
+    // (y, z) of the group's first line (one division per group); line l of the
+    // group is y0 + l, wrapped into the next z plane (L <= ny)
+    const int z0 = line0 / a.ny, y0 = line0 - z0 * a.ny;
 
     // 2) pointwise nonlinear + penalization term and diagnostics
     T g0[PMAX], g1[PMAX], g2[PMAX];
@@ -1353,15 +1359,13 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
         T gy = uz * wx - ux * wz;
         T gz = ux * wy - uy * wx;
         if constexpr (ST) {
-          const int line = line0 + l;
-          const int z = line / a.ny, y = line - z * a.ny;
+          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
           const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
           const bool in = a.bnx > 0 && bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz;
           const long long cell = in ? ((long long)bz * a.bny + by) * a.bnx + bx : -1;
           penalize_static<T>(a, cell, (long long)y * n + x, ux, uy, uz, gx, gy, gz, aF0, aF1, aF2, aS0, aS1, aS2);
         } else if (a.bnx > 0) {
-          const int line = line0 + l;
-          const int z = line / a.ny, y = line - z * a.ny;
+          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
           const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
           if (bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {
             const long long cell = ((long long)bz * a.bny + by) * a.bnx + bx;
@@ -1379,8 +1383,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
           }
         }
         if (a.pnx > 0) {
-          const int line = line0 + l;
-          const int z = line / a.ny, y = line - z * a.ny;
+          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
           const int qx = x - a.px0, qy = y - a.py0, qz = z - a.pz0;
           if (qx >= 0 && qx < a.pnx && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {
             const long long cell = ((long long)qz * a.pny + qy) * a.pnx + qx;
@@ -1409,7 +1412,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
       }
     }
     __syncthreads();
-    fft_lds<T, WF, RF, NT, MAXE, false>(buf, a.plan, tws);
+    fft_n<T, WF, RF, NT, MAXE, false, N>(buf, a.plan, tws);
 
     // 3) unpack the two real transforms of each signal, keep kx <= K
     const int tid3 = opaque((int)threadIdx.x);
@@ -1417,7 +1420,7 @@ __global__ __launch_bounds__(NT) void xpass_fused(XArgs<T> a) {
     for (int k = 0; k < FI; ++k) {
       const int it = tid3 + k * NT;
       if (it < nitems) {
-        const int x = it % a.kx1, s = it / a.kx1;
+        const int x = it % kx1, s = it / kx1;
         const int l = s / 3, f = s - 3 * (s / 3);
         const int sig = (f < 2) ? l : L + (l >> 1);
         const bool second = (f == 1) || (f == 2 && (l & 1));
@@ -2055,12 +2058,20 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   const bool whole = (long long)((a.C + W - 1) / W) * W <= a.ld;
   const bool use512 = k512 && a.n == 512 && a.K == 170 && whole &&
                       (!off32 || (long long)a.n * a.ld * (long long)sizeof(cpx<T>) < (1LL << 32));
+  // the width that holds 800-point columns gets the compile-time 800 plan
+  constexpr bool k800 = (W * 800 <= NT * MAXE) && (2 * W * 800 > NT * MAXE);
+  const bool use800 = k800 && a.n == 800 && a.K == 266;
 #define FSI_COL_CASE(M)                                                                \
   case M:                                                                              \
     if (use512) {                                                                      \
       e = set_lds(col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>, lds);                   \
       if (e != hipSuccess) return e;                                                   \
       hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>), grid, dim3(NT), \
+                         lds, s, a);                                                   \
+    } else if (use800) {                                                               \
+      e = set_lds(col_pass<T, W, NT, MAXE, M, k800 ? 800 : 0>, lds);                   \
+      if (e != hipSuccess) return e;                                                   \
+      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, k800 ? 800 : 0>), grid, dim3(NT), \
                          lds, s, a);                                                   \
     } else {                                                                           \
       e = set_lds(col_pass<T, W, NT, MAXE, M, 0>, lds);                                \
@@ -2118,14 +2129,23 @@ int xpass_lines(int n) {
   return (n * 6 <= XCfg<T, 2>::MAXE * XCfg<T, 2>::NT) ? 2 : 0;
 }
 
-template <typename T, int L, bool ST>
-static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
+template <typename T, int L, bool ST, int N>
+static hipError_t launch_xfused_ln(const XArgs<T>& a, int grid, hipStream_t s) {
   constexpr int NT = XCfg<T, L>::NT, M = XCfg<T, L>::MAXE;
   const size_t lds = (size_t)a.n * (PadStride<3 * L>::value + 1) * sizeof(cpx<T>);
-  hipError_t e = set_lds(xpass_fused<T, L, NT, M, ST>, lds);
+  hipError_t e = set_lds(xpass_fused<T, L, NT, M, ST, N>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((xpass_fused<T, L, NT, M, ST>), dim3(grid), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((xpass_fused<T, L, NT, M, ST, N>), dim3(grid), dim3(NT), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int L, bool ST>
+static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
+  // 800 points (2 lines per workgroup in both precisions): the compile-time plan
+  if constexpr (L == 2) {
+    if (a.n == 800 && a.kx1 == 267) return launch_xfused_ln<T, L, ST, 800>(a, grid, s);
+  }
+  return launch_xfused_ln<T, L, ST, 0>(a, grid, s);
 }
 
 // the static plane selects its own instantiation: without it the kernels keep

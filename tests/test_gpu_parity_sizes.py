@@ -126,6 +126,47 @@ def test_z_pass_512_parity_sponge_off(prec):
     assert ef < FTOL[prec]
 
 
+@pytest.mark.parametrize("prec", [fsi.PREC_FP64, fsi.PREC_FP32])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_800_point_passes_parity(axis, prec):
+    """800 points along one axis select the compile-time 800-point plan of that
+    axis's passes (the fused x pass, the y passes, the update + z-inverse pass):
+    5 steps with a moving plate against the oracle."""
+    n = [20, 18, 20]  # the mask support of the plate must fit inside the thin extents
+    n[axis] = 800
+    n = tuple(n)
+    dx = 0.04
+    L = tuple(dx * m for m in n)
+    nu, eta, tw, h = 0.01, 0.05, 2 * dx, dx
+    print("800-point passes, axis", axis, prec, flush=True)
+    o = ons.OracleNS(n, L, nu, eta, tw, h, 0)
+    s = fsi.Solver(n, L, nu, eta, tw, h, 0, prec)
+    u0 = synth.random_solenoidal(n, L, seed=31 + axis)
+    o.set_velocity(u0)
+    s.set_velocity(u0)
+    c = [Lk / 2 for Lk in L]
+    ua = [(1, 0, 0), (0, 1, 0), (0, 0, 1)][axis]
+    va = [(0, 1, 0), (0, 0, 1), (1, 0, 0)][axis]
+    x, tri = synth.flat_rectangle(tuple(c), ua, va, 0.5, 0.12, 6, 3)
+    v = np.tile(np.array([0.2, -0.1, 0.15]), (len(x), 1))
+    o.set_wing(x, v, tri)
+    s.set_wing(x, v, tri)
+    fo, fg = [], []
+    for k in range(5):
+        dt = 0.01 if k != 2 else 0.007
+        d = o.step(dt=dt)
+        s.step(dt)
+        fo.append(d["F"])
+        fg.append(s.info()["F"])
+    ev = rel_max(s.velocity(), o.velocity())
+    eu = rel_max(s.spectrum(), full_to_compact(o.uh, n))
+    ef = rel_max(np.array(fg), np.array(fo))
+    print("800 axis %d: velocity %.3e spectrum %.3e force %.3e" % (axis, ev, eu, ef), flush=True)
+    assert np.max(np.abs(np.array(fo))) > 1e-3
+    assert ev < VTOL[prec] and eu < VTOL[prec]
+    assert ef < FTOL[prec]
+
+
 R25_SHAPES = [(50, 12, 10), (12, 50, 10), (12, 10, 50), (800, 12, 10), (12, 800, 10), (10, 12, 800)]
 TTOL = {fsi.PREC_FP64: 1e-12, fsi.PREC_FP32: 2e-6}
 
