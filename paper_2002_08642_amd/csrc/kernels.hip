@@ -109,7 +109,8 @@ __device__ __forceinline__ cpx<T> scaled_diff(cpx<T> a, T s, cpx<T> b, T t) {
 }
 
 template <typename T, int W, int NT, int MAXE, int MODE, int N>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void col_pass(ColArgs<T> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : NT / 128))) void col_pass(
+    ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int RSTEP = NT / W;
@@ -2059,25 +2060,33 @@ static hipError_t launch_col_w(int mode, const ColArgs<T>& a, int slices, hipStr
   const bool use512 = k512 && a.n == 512 && a.K == 170 && whole &&
                       (!off32 || (long long)a.n * a.ld * (long long)sizeof(cpx<T>) < (1LL << 32));
   // the width that holds 800-point columns gets the compile-time 800 plan
-  constexpr bool k800 = (W * 800 <= NT * MAXE) && (2 * W * 800 > NT * MAXE);
+  constexpr bool k800 = NT == 1024 && (W * 800 <= NT * MAXE) && (2 * W * 800 > NT * MAXE);
   const bool use800 = k800 && a.n == 800 && a.K == 266;
-#define FSI_COL_CASE(M)                                                                \
-  case M:                                                                              \
-    if (use512) {                                                                      \
-      e = set_lds(col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>, lds);                   \
-      if (e != hipSuccess) return e;                                                   \
-      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, k512 ? 512 : 0>), grid, dim3(NT), \
-                         lds, s, a);                                                   \
-    } else if (use800) {                                                               \
-      e = set_lds(col_pass<T, W, NT, MAXE, M, k800 ? 800 : 0>, lds);                   \
-      if (e != hipSuccess) return e;                                                   \
-      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, k800 ? 800 : 0>), grid, dim3(NT), \
-                         lds, s, a);                                                   \
-    } else {                                                                           \
-      e = set_lds(col_pass<T, W, NT, MAXE, M, 0>, lds);                                \
-      if (e != hipSuccess) return e;                                                   \
-      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, 0>), grid, dim3(NT), lds, s, a); \
-    }                                                                                  \
+#define FSI_COL_CASE(M)                                                                   \
+  case M:                                                                                 \
+    if constexpr (k512) {                                                                 \
+      if (use512) {                                                                       \
+        e = set_lds(col_pass<T, W, NT, MAXE, M, 512>, lds);                               \
+        if (e != hipSuccess) return e;                                                    \
+        hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, 512>), grid, dim3(NT), lds, s, a); \
+        break;                                                                            \
+      }                                                                                   \
+    }                                                                                     \
+    if constexpr (k800) {                                                                 \
+      if (use800) {                                                                       \
+        e = set_lds(col_pass<T, W, NT, MAXE, M, 800>, lds);                               \
+        if (e != hipSuccess) return e;                                                    \
+        hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, 800>), grid, dim3(NT), lds, s, a); \
+        break;                                                                            \
+      }                                                                                   \
+    }                                                                                     \
+    if constexpr (NT == 1024) {                                                           \
+      return hipErrorInvalidValue; /* the wide workgroups serve 800 points only */        \
+    } else {                                                                              \
+      e = set_lds(col_pass<T, W, NT, MAXE, M, 0>, lds);                                   \
+      if (e != hipSuccess) return e;                                                      \
+      hipLaunchKernelGGL((col_pass<T, W, NT, MAXE, M, 0>), grid, dim3(NT), lds, s, a);    \
+    }                                                                                     \
     break;
   switch (mode) {
     FSI_COL_CASE(COL_INV_PLAIN)
@@ -2109,6 +2118,10 @@ int col_width(int n) {
 template <typename T>
 hipError_t launch_col(int mode, const ColArgs<T>& a, int slices, hipStream_t s) {
   constexpr int M = ColCfg<T>::MAXE, NT = ColCfg<T>::NT;
+  // 800-point columns: 128-byte row segments (16 FP32 / 8 FP64 columns, 109 KB
+  // of LDS) over 1024 threads, 13 / 7 rows per thread, the compile-time plan
+  if (a.n == 800 && a.K == 266)
+    return launch_col_w<T, sizeof(T) == 4 ? 16 : 8, 1024, sizeof(T) == 4 ? 13 : 7>(mode, a, slices, s);
   switch (col_width<T>(a.n)) {
     case 64: return launch_col_w<T, 64, NT, M>(mode, a, slices, s);
     case 32: return launch_col_w<T, 32, NT, M>(mode, a, slices, s);
