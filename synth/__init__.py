@@ -491,7 +491,9 @@ def turek_flag(ch, ns=15, nc=4, tw=None, density=0.02, E=5.6e6 / 1000.0, k_ext_s
     rigidity per unit depth E h^3 / 12, extension E h.  Bending springs along
     the span on every chordwise row (k^b of Eq. EI_k_relation for that row's
     share of the depth) and stiff chordwise bending (the flag stays plane in z);
-    the first two span columns (inside the cylinder) are clamped."""
+    the first two span columns (inside the cylinder) are clamped.  Each bending
+    spring carries (EI, l_b, n_b, factor): a solver takes k^b = factor x k^b(EI,
+    l_b, n_b) by Eq. EI_k_relation (factor 1e3 on the chordwise springs)."""
     xc, yc, R = ch["cylinder"]
     thick = TUREK_FLAG[1]
     tw = 0.5 * thick if tw is None else tw
@@ -512,25 +514,27 @@ def turek_flag(ch, ns=15, nc=4, tw=None, density=0.02, E=5.6e6 / 1000.0, k_ext_s
     k_ext = k_ext_scale * E * thick * depth / lens / nc  # axial stiffness of the strip a spring stands for
     EI_row = E * thick ** 3 / 12.0 * depth / nc
     n_b = ns - 2
-    kb_span = EI_row / span * n_b * (2 * n_b + 1) / (2.0 * (n_b + 1))
-    ijk, axis, kb = [], [], []
+    ijk, axis, factor = [], [], []
     for j in range(nc):
         for i in range(1, ns - 1):
             v = j * ns + i
             ijk.append((v - 1, v, v + 1))
             axis.append(0)
-            kb.append(kb_span)
+            factor.append(1.0)
     for i in range(ns):
         for j in range(1, nc - 1):
             v = j * ns + i
             ijk.append((v - ns, v, v + ns))
             axis.append(1)
-            kb.append(1e3 * kb_span)
+            factor.append(1e3)
+    m = len(ijk)
+    bend = dict(EI=np.full(m, EI_row), lb=np.full(m, span), nb=np.full(m, n_b, dtype=np.int32),
+                factor=np.array(factor))
     clamped = np.array([j * ns + i for j in range(nc) for i in (0, 1)], dtype=np.int32)
     kin = dict(alpha=0.5 * np.pi, omega=0.0, t_ramp=0.0, axis_point=(x_root, yc, 0.5 * ch["L"][2]))
     wing = dict(span_coord=s, chord_coord=c, tri=tri, ext_ij=edges, ext_k=k_ext, clamped=clamped,
                 density=density)
-    return wing, np.array(ijk, dtype=np.int32), np.array(kb), np.array(axis, dtype=np.int32), kin, tw
+    return wing, np.array(ijk, dtype=np.int32), bend, np.array(axis, dtype=np.int32), kin, tw
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ FP32 1e-5 / 1e-4; the coupled flag as tests/test_gpu_coupled.py.
 import numpy as np
 import pytest
 
-from oracle import ns as ons
+from oracle import ns as ons, structure as st
 from oracle.coupling import CoupledOracle
 from paper_2002_08642_amd import fsi
 from paper_2002_08642_amd.coupled import FlexibleWingFSI
@@ -110,9 +110,12 @@ def test_static_plane_on_the_512_point_x_pass(prec):
 def test_channel_flag_coupled_parity(prec):
     ch = synth.turek_channel(128, 32, 16)
     nx, ny, nz = ch["n"]
-    wing, ijk, kb, axis, kin, tw = synth.turek_flag(ch)
+    wing, ijk, bend, axis, kin, tw = synth.turek_flag(ch)
+    # k^b of Eq. EI_k_relation on each side
+    kb_o = bend["factor"] * np.array([st.bending_stiffness(e, l, n) for e, l, n in zip(bend["EI"], bend["lb"], bend["nb"])])
+    kb_g = bend["factor"] * np.array([fsi.bending_stiffness(e, l, n) for e, l, n in zip(bend["EI"], bend["lb"], bend["nb"])])
     print("channel flag", prec, flush=True)
-    o = CoupledOracle(ch["n"], ch["L"], NU, ETA, tw, ch["h"], fsi.PROFILE_COS, wing, ijk, kb, axis, kin, tol=1e-12)
+    o = CoupledOracle(ch["n"], ch["L"], NU, ETA, tw, ch["h"], fsi.PROFILE_COS, wing, ijk, kb_o, axis, kin, tol=1e-12)
     # from the developed channel flow: the flag is loaded from the first step
     u0 = synth.turek_inflow_field(ch)
     o.fluid.set_static_mask(*ch["static"])
@@ -120,7 +123,7 @@ def test_channel_flag_coupled_parity(prec):
     s = fsi.Solver(ch["n"], ch["L"], NU, ETA, tw, ch["h"], fsi.PROFILE_COS, prec, pressure=True)
     s.set_static_mask(*ch["static"])
     s.set_velocity(u0)
-    g = FlexibleWingFSI(s, wing, ijk, kb, axis, kin, tol=1e-12)
+    g = FlexibleWingFSI(s, wing, ijk, kb_g, axis, kin, tol=1e-12)
     fo, fg, so, sg = [], [], [], []
     dt = 2.0 / 3.0 * ETA
     for _ in range(10):
