@@ -2134,6 +2134,7 @@ hipError_t launch_col(int mode, const ColArgs<T>& a, int slices, hipStream_t s) 
 
 template <typename T>
 int xpass_lines(int n) {
+  if (n == 800) return X800<T>::L;
   // four lines per workgroup when their 12 packed signals fit the register bound
   // and 64 KB of LDS, else two
   const bool regs = n * 12 <= XCfg<T, 4>::MAXE * XCfg<T, 4>::NT;
@@ -2142,9 +2143,8 @@ int xpass_lines(int n) {
   return (n * 6 <= XCfg<T, 2>::MAXE * XCfg<T, 2>::NT) ? 2 : 0;
 }
 
-template <typename T, int L, bool ST, int N>
+template <typename T, int L, bool ST, int N, int NT = XCfg<T, L>::NT, int M = XCfg<T, L>::MAXE>
 static hipError_t launch_xfused_ln(const XArgs<T>& a, int grid, hipStream_t s) {
-  constexpr int NT = XCfg<T, L>::NT, M = XCfg<T, L>::MAXE;
   const size_t lds = (size_t)a.n * (PadStride<3 * L>::value + 1) * sizeof(cpx<T>);
   hipError_t e = set_lds(xpass_fused<T, L, NT, M, ST, N>, lds);
   if (e != hipSuccess) return e;
@@ -2154,10 +2154,6 @@ static hipError_t launch_xfused_ln(const XArgs<T>& a, int grid, hipStream_t s) {
 
 template <typename T, int L, bool ST>
 static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
-  // 800 points (2 lines per workgroup in both precisions): the compile-time plan
-  if constexpr (L == 2) {
-    if (a.n == 800 && a.kx1 == 267) return launch_xfused_ln<T, L, ST, 800>(a, grid, s);
-  }
   return launch_xfused_ln<T, L, ST, 0>(a, grid, s);
 }
 
@@ -2169,6 +2165,9 @@ static hipError_t launch_xfused_st(const XArgs<T>& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((xpass_wave512<T, ST>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
   }
+  // 800 points: the compile-time plan with its own workgroup shape
+  if (a.n == 800 && a.kx1 == 267)
+    return launch_xfused_ln<T, X800<T>::L, ST, 800, X800<T>::NT, X800<T>::MAXE>(a, grid, s);
   if (xpass_lines<T>(a.n) == 4) return launch_xfused_l<T, 4, ST>(a, grid, s);
   return launch_xfused_l<T, 2, ST>(a, grid, s);
 }

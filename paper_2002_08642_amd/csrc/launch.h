@@ -40,6 +40,19 @@ struct XCfg<double, 2> {
   static constexpr int NT = 512, MAXE = 10;
 };
 
+// The fused x pass at 800 points (compile-time plan): lines per workgroup,
+// threads, and the per-thread element bound (3 L 800 / NT rounded up).
+template <typename T>
+struct X800;
+template <>
+struct X800<float> {
+  static constexpr int L = 2, NT = 512, MAXE = 20;
+};
+template <>
+struct X800<double> {
+  static constexpr int L = 2, NT = 512, MAXE = 10;
+};
+
 // Columns per workgroup of a column pass of length n (0 if n is too long).
 template <typename T>
 int col_width(int n);
