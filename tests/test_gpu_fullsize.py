@@ -176,15 +176,16 @@ def _band_to_half(c, n):
     return h, iz, iy
 
 
-def test_fullsize_nonlinear_elementwise():
-    """The nonlinear term of the bench workload's first step at 512^3 (FP32),
-    every stored mode: against u x omega - (chi/eta)(u - u_s), 2/3-truncated and
-    projected, computed in FP64 from the same stored spectrum and the device's
-    mask with scipy's FFTs (an independent transform library)."""
+@pytest.mark.parametrize("N", [512, 800])
+def test_fullsize_nonlinear_elementwise(N):
+    """The nonlinear term of the bench workload's first step at 512^3 and at
+    800^3 (FP32), every stored mode: against u x omega - (chi/eta)(u - u_s),
+    2/3-truncated and projected, computed in FP64 from the same stored spectrum
+    and the device's mask with scipy's FFTs (an independent transform library)."""
     import scipy.fft as sfft
     cfg = bench.workload(N)
     n, L = cfg["n"], cfg["L"]
-    print("512^3 nonlinear term, element by element", flush=True)
+    print("%d^3 nonlinear term, element by element" % N, flush=True)
     s = fsi.Solver(n, L, cfg["nu"], cfg["eta"], cfg["tw"], cfg["h"], cfg["profile"], fsi.PREC_FP32)
     s.set_spectrum(synth.random_solenoidal_compact(n, L, seed=0))
     x, v, _ = fsi.plate_pose(cfg["span_coord"], cfg["chord_coord"], 0.0, cfg["alpha"], cfg["omega"], 0.0,
