@@ -37,24 +37,10 @@ struct cpx2f {
   cpx<float> a, b;
 };
 typedef float v4f __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ cpx2f ld_stream2(const cpx<float>* p) {
-  const v4f w = (FSI_NT & 2) ? __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p))
-                             : *reinterpret_cast<const v4f*>(p);
-  return cpx2f{mk<float>(w.x, w.y), mk<float>(w.z, w.w)};
-}
-__device__ __forceinline__ void st_stream2(cpx<float>* p, cpx2f v) {
-  v4f w;
-  w.x = v.a.re;
-  w.y = v.a.im;
-  w.z = v.b.re;
-  w.w = v.b.im;
-  if (FSI_NT & 1) __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
-  else *reinterpret_cast<v4f*>(p) = w;
-}
-// The same accesses through a buffer resource (a wave-uniform base and byte
-// bound): a lane whose byte offset is at or beyond the bound loads zeros and
-// its store is dropped, with no memory traffic and no branch (a branch around
-// stores would make the next wait for prefetched loads wait for the stores).
+// Moved through a buffer resource (a wave-uniform base and byte bound): a lane
+// whose byte offset is at or beyond the bound loads zeros and its store is
+// dropped, with no memory traffic and no branch (a branch around stores would
+// make the next wait for prefetched loads wait for the stores).
 // kOOB marks such lanes; every bound used here is below 2^31 bytes.
 constexpr unsigned kOOB = 0x80000000u;
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -505,20 +491,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     // rp + 64 m (m <= 2) or rp + 64 m - 171 (m >= 5)
     constexpr int WP = W / 2;
     cpx2f RA[6], RB[6];
+    // buffer loads (a field of a z slab is below 2^31 bytes): rows out of the
+    // band and column pairs wholly in the kx padding or past the last column
+    // load zeros with no memory traffic
     auto load_into = [&](int lq, cpx2f(&R)[6]) __attribute__((always_inline)) {
       const int tq = opaque((int)threadIdx.x);
       const int cq = blockIdx.x * W + 2 * (tq % WP), rq = tq / WP;
-      // uniform base and 32-bit element offsets within the slice (scalar-base
-      // addressing; a 512-row slice of a y pass is far below 4 GB)
-      const cpx<float>* in = reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs + ib;
-      const int cc = cq < a.C ? cq : 0;
+      const __amdgpu_buffer_rsrc_t rin = buf_rsrc(reinterpret_cast<const cpx<float>*>(a.in) + lq * a.in_fs,
+                                                  (long long)a.in_fs * 8);
+      const bool cin = cq < a.C && (cq % a.kxp) < a.kx1;
+      const unsigned base = (unsigned)(ib + cq) * 8u;
 #pragma unroll
       for (int e = 0; e < 6; ++e) {
         const int m = e < 3 ? e : e + 2;
-        // rows out of the band are loaded from row 0 (one line for the whole
-        // wave) and replaced by zero
-        const bool inb = (m == 2) ? rq <= 42 : (m == 5) ? rq >= 22 : true;
-        R[e] = ld_stream2(at_u32(in, (inb ? (m <= 2 ? rq + 64 * m : rq + 64 * m - 171) : 0) * a.ld + cc));
+        const bool inb = cin && ((m == 2) ? rq <= 42 : (m == 5) ? rq >= 22 : true);
+        const int i = m <= 2 ? rq + 64 * m : rq + 64 * m - 171;
+        R[e] = ld_buf2(rin, inb ? base + (unsigned)(i * a.ld) * 8u : kOOB);
       }
     };
     auto step = [&](auto oc) __attribute__((always_inline)) {
@@ -563,13 +551,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         }
       }
       fft512_reg<float, W, true>(v0, v1, reinterpret_cast<cpx<float>*>(buf), reinterpret_cast<const cpx<float>*>(tws));
-      cpx<float>* out = reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs + ob;
-      // unconditional stores (columns out of the band, padding included, carry
-      // zeros; the launcher keeps the workgroup's columns within the row pitch):
-      // a store under a branch makes the next wait for the prefetched field
-      // wait for these stores as well
+      // unconditional stores of whole 128-byte row segments (columns out of the
+      // band, padding included, carry zeros; the launcher keeps the workgroup's
+      // columns within the row pitch): a store under a branch makes the next
+      // wait for the prefetched field wait for these stores as well, and
+      // dropping the padding columns' stores leaves partial lines (measured
+      // 0.70 -> 0.73 ms)
+      const __amdgpu_buffer_rsrc_t rout =
+          buf_rsrc(reinterpret_cast<cpx<float>*>(a.out) + fo * a.out_fs, (long long)a.out_fs * 8);
+      const unsigned base = (unsigned)(ob + c) * 8u;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) st_stream2(at_u32(out, (rp + 64 * m) * a.ld + c), cpx2f{v0[m], v1[m]});
+      for (int m = 0; m < 8; ++m) st_buf2(rout, base + (unsigned)((rp + 64 * m) * a.ld) * 8u, cpx2f{v0[m], v1[m]});
     };
     load_into(0, RA);
     static_for<0, 6>([&](auto oc) { step(oc); });
@@ -703,7 +695,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       const unsigned base = (unsigned)(ob + c) * 8u;
       const float sc = (float)a.scale;
       // stores without a branch: rows out of the band (m = 2 with rp > 42,
-      // m = 5 with rp < 22) and padding pairs take the dropped offset
+      // m = 5 with rp < 22) and padding pairs take the dropped offset (storing
+      // the padding pairs as well, for whole 128-byte lines, measured the same)
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         if (m == 3 || m == 4) continue;
