@@ -952,6 +952,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       }
       const bool b5 = r0 <= 10, b10 = r0 >= 22;
       const int cl = c < a.C ? c : 0;
+      // the state through buffer resources bounded by a compact field (far
+      // below 2^31 bytes at 512 points): slots out of the band, and the previous
+      // nonlinear term on the first step, load zeros with no memory traffic
+      constexpr int kOut = 1 << 28;  // an element index beyond every compact field
       // band slots in chunks of two: every load of a chunk before its first
       // store (a load after a store that may alias it waits for that store)
       constexpr int KCZ = 2;
@@ -962,13 +966,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
 #pragma unroll
         for (int kk = 0; kk < KCZ; ++kk) {
           const int m = band_slot512(e0 + kk);
-          // 32-bit element offsets from uniform field bases (one compact field
-          // at 512 points is far below 4 GB)
+          const bool inb = (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
           const int idx = (m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            uo[kk][q] = ld_state(at_u32(a.uh + q * a.cfs, idx));
-            po[kk][q] = ld_state(at_u32(a.nh + q * a.cfs, idx));  // unused on the first step
+            uo[kk][q] = ld_band<T>(band_rsrc(a.uh + q * a.cfs, (int)a.cfs), inb ? idx : kOut);
+            po[kk][q] = ld_band<T>(band_rsrc(a.nh + q * a.cfs, (int)a.cfs), (inb && !a.first) ? idx : kOut);
           }
         }
 #pragma unroll
@@ -1029,7 +1032,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
 #pragma unroll
           for (int e = 0; e < NST; ++e) {
             const int m = band_slot512(e);
-            U[1][e] = ld_state(at_u32(a.uh + a.cfs, (m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl));
+            const bool inb = (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
+            U[1][e] = ld_band<T>(band_rsrc(a.uh + a.cfs, (int)a.cfs),
+                                 inb ? (m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171) * a.ld + cl : kOut);
           }
         }
         static_for<0, 16>([&](auto mc) __attribute__((always_inline)) {
