@@ -974,46 +974,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
             po[kk][q] = ld_band<T>(band_rsrc(a.nh + q * a.cfs, (int)a.cfs), (inb && !a.first) ? idx : kOut);
           }
         }
+        // every lane computes its slots; slots out of the band and columns out
+        // of it take the dropped offset of the buffer stores (no branch around
+        // the stores) and leave zeros in U
 #pragma unroll
         for (int kk = 0; kk < KCZ; ++kk) {
           const int e = e0 + kk, m = band_slot512(e);
-          const bool inb = (m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10;
-          U[0][e] = mk<T>(0, 0);
-          U[2][e] = mk<T>(0, 0);
-          if (cok && inb) {
-            const int i = m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171;
-            const T kz = a.kfz * (T)band_mode(i, K);
-            cpx<T> n0 = st[0][e], n1 = st[1][e];
-            cpx<T> n2 = scl(buf[(r0l + 32 * m) * W + col], a.scale);
-            const T k2 = kx * kx + ky * ky + kz * kz;
-            const int idx = i * a.ld + c;
-            if (a.tsp) {  // vorticity sponge (solenoidal: the projection keeps it)
-              n0 = n0 + *at_u32(a.tsp, idx);
-              n1 = n1 + *at_u32(a.tsp + a.cfs, idx);
-              n2 = n2 + *at_u32(a.tsp + 2 * a.cfs, idx);
-            }
-            if (k2 > (T)0) {
-              const T ik2 = (T)1 / k2;
-              cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
-              n0 = n0 - scl(sp, kx);
-              n1 = n1 - scl(sp, ky);
-              n2 = n2 - scl(sp, kz);
-              if (a.pi) *at_u32(a.pi, idx) = mk<T>(sp.im, -sp.re);  // -i (k.N') / |k|^2
-            } else if (a.pi) {
-              *at_u32(a.pi, idx) = mk<T>(0, 0);
-            }
-            const T en = dev_exp<T>(-a.nu * k2 * dtn);
-            const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
-            const cpx<T> nn[3] = {n0, n1, n2};
+          const bool ok = cok && ((m <= 4 || m >= 11) ? true : (m == 5) ? b5 : b10);
+          const int i = m <= 5 ? r0l + 32 * m : r0l + 32 * m - 171;
+          const T kz = a.kfz * (T)band_mode(i, K);
+          cpx<T> n0 = st[0][e], n1 = st[1][e];
+          cpx<T> n2 = scl(buf[(r0l + 32 * m) * W + col], a.scale);
+          const T k2 = kx * kx + ky * ky + kz * kz;
+          const int idx = ok ? i * a.ld + c : kOut;
+          if (a.tsp) {  // vorticity sponge (solenoidal: the projection keeps it)
+            n0 = n0 + ld_band<T>(band_rsrc(a.tsp, (int)a.cfs), idx);
+            n1 = n1 + ld_band<T>(band_rsrc(a.tsp + a.cfs, (int)a.cfs), idx);
+            n2 = n2 + ld_band<T>(band_rsrc(a.tsp + 2 * a.cfs, (int)a.cfs), idx);
+          }
+          const T ik2 = k2 > (T)0 ? (T)1 / k2 : (T)0;  // the projection is the identity at k = 0
+          const cpx<T> sp = scl(scl(n0, kx) + scl(n1, ky) + scl(n2, kz), ik2);
+          n0 = n0 - scl(sp, kx);
+          n1 = n1 - scl(sp, ky);
+          n2 = n2 - scl(sp, kz);
+          if (a.pi) st_band<T>(band_rsrc(a.pi, (int)a.cfs), idx, mk<T>(sp.im, -sp.re));  // -i (k.N') / |k|^2
+          const T en = dev_exp<T>(-a.nu * k2 * dtn);
+          const T c2e = c2 * en * dev_exp<T>(-a.nu * k2 * dtp);
+          const cpx<T> nn[3] = {n0, n1, n2};
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              const cpx<T> u1 = scl(uo[kk][q] + scl(nn[q], c1), en);
-              // first step: Euler, the stored previous term is not read
-              const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
-              st_stream(at_u32(a.uh + q * a.cfs, idx), u2);
-              st_stream(at_u32(a.nh + q * a.cfs, idx), nn[q]);
-              if (q != 1) U[q][e] = u2;
-            }
+          for (int q = 0; q < 3; ++q) {
+            const cpx<T> u1 = scl(uo[kk][q] + scl(nn[q], c1), en);
+            // first step: Euler, the stored previous term is not read
+            const cpx<T> u2 = a.first ? u1 : u1 - scl(po[kk][q], c2e);
+            st_band<T>(band_rsrc(a.uh + q * a.cfs, (int)a.cfs), idx, u2);
+            st_band<T>(band_rsrc(a.nh + q * a.cfs, (int)a.cfs), idx, nn[q]);
+            if (q != 1) U[q][e] = mk<T>(ok ? u2.re : (T)0, ok ? u2.im : (T)0);
           }
         }
       });
