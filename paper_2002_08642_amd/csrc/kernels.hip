@@ -1285,13 +1285,15 @@ void xpass_fused(XArgs<T> a) {
   constexpr int WF = 3 * L / 2;  // forward: (Gx,Gy) per line, (Gz,Gz') per line pair
   constexpr int RI = PadStride<WI>::value;
   constexpr int RF = PadStride<WF>::value;
-  constexpr int PMAX = (MAXE + 2) / 3;
-  constexpr int FI = MAXE / 3 + 2;  // band items (3 L (K+1)) per thread
   static_assert(L % 2 == 0, "L must be even");
+  // per-thread slots of a line: XI along the band (K + 1 <= XI NT), XP along
+  // the line (n <= XP NT); an instantiation serves n <= MAXE NT / (3 L)
+  constexpr int NMAX = N ? N : MAXE * NT / (3 * L);
+  constexpr int XI = ((NMAX - 1) / 3 + 1 + NT - 1) / NT;
+  constexpr int XP = (NMAX + NT - 1) / NT;
   const int tid = threadIdx.x;
   const int n = N ? N : a.n, K = N ? (N - 1) / 3 : a.kx1 - 1, kx1 = K + 1;
   const int ngroups = a.nlines / L;
-  const int nitems = 3 * L * kx1;
   cpx<T>* tws = buf + n * RI;
   for (int i = tid; i < n; i += NT) tws[i] = a.tw[i];
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
@@ -1299,30 +1301,37 @@ void xpass_fused(XArgs<T> a) {
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int tid = opaque((int)threadIdx.x);
     const int line0 = g * L;
-    // 1) Hermitian-extended packed spectra: batched loads, then LDS writes
+    // 1) Hermitian-extended packed spectra, signal s = 3 l + p: a wave-uniform
+    //    line base per field and 32-bit offsets x (no 64-bit vector address
+    //    arithmetic); every load issued before the LDS writes
     {
-      cpx<T> A[FI], B[FI];
+      cpx<T> A[WI][XI], B[WI][XI];
 #pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        const int it = tid + k * NT;
-        if (it < nitems) {
-          const int x = it % kx1, s = it / kx1;
-          const int l = s / 3, p = s - 3 * (s / 3);
-          const long long off = (long long)(line0 + l) * a.ld + x;
-          A[k] = a.spec[(2 * p) * a.sfs + off];
-          B[k] = a.spec[(2 * p + 1) * a.sfs + off];
+      for (int s = 0; s < WI; ++s) {
+        const int l = s / 3, p = s % 3;
+        const cpx<T>* ab = a.spec + (2 * p) * a.sfs + (long long)(line0 + l) * a.ld;
+        const cpx<T>* bb = a.spec + (2 * p + 1) * a.sfs + (long long)(line0 + l) * a.ld;
+#pragma unroll
+        for (int k = 0; k < XI; ++k) {
+          const int x = tid + k * NT;
+          const int xc = x < kx1 ? x : 0;  // unconditional loads (see load512)
+          A[s][k] = *at_u32(ab, xc);
+          B[s][k] = *at_u32(bb, xc);
         }
       }
 #pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        const int it = tid + k * NT;
-        if (it < nitems) {
-          const int x = it % kx1, s = it / kx1;
-          if (x == 0) {
-            buf[s] = mk<T>(A[k].re, B[k].re);
-          } else {
-            buf[x * RI + s] = mk<T>(A[k].re - B[k].im, A[k].im + B[k].re);
-            buf[(n - x) * RI + s] = mk<T>(A[k].re + B[k].im, B[k].re - A[k].im);
+      for (int s = 0; s < WI; ++s) {
+#pragma unroll
+        for (int k = 0; k < XI; ++k) {
+          const int x = tid + k * NT;
+          if (x < kx1) {
+            const cpx<T> av = A[s][k], bv = B[s][k];
+            if (x == 0) {
+              buf[s] = mk<T>(av.re, bv.re);
+            } else {
+              buf[x * RI + s] = mk<T>(av.re - bv.im, av.im + bv.re);
+              buf[(n - x) * RI + s] = mk<T>(av.re + bv.im, bv.re - av.im);
+            }
           }
         }
       }
@@ -1338,31 +1347,37 @@ void xpass_fused(XArgs<T> a) {
     // group is y0 + l, wrapped into the next z plane (L <= ny)
     const int z0 = line0 / a.ny, y0 = line0 - z0 * a.ny;
 
-    // 2) pointwise nonlinear + penalization term and diagnostics
-    T g0[PMAX], g1[PMAX], g2[PMAX];
+    // 2) pointwise nonlinear + penalization term and diagnostics, line by line
+    //    (the line's y, z and its rows of the mask sub-box once per line)
+    T g0[L][XP], g1[L][XP], g2[L][XP];
     const int tid2 = opaque((int)threadIdx.x);
 #pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      const int it = tid2 + k * NT;
-      if (it < n * L) {
-        const int x = it % n, l = it / n;
-        const cpx<T> z1 = buf[x * RI + 3 * l], z2 = buf[x * RI + 3 * l + 1], z3 = buf[x * RI + 3 * l + 2];
-        const T ux = z1.re, uy = z1.im, uz = z2.re;
-        const T wx = z2.im, wy = z3.re, wz = z3.im;
-        T gx = uy * wz - uz * wy;
-        T gy = uz * wx - ux * wz;
-        T gz = ux * wy - uy * wx;
-        if constexpr (ST) {
-          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
-          const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
-          const bool in = a.bnx > 0 && bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz;
-          const long long cell = in ? ((long long)bz * a.bny + by) * a.bnx + bx : -1;
-          penalize_static<T>(a, cell, (long long)y * n + x, ux, uy, uz, gx, gy, gz, aF0, aF1, aF2, aS0, aS1, aS2);
-        } else if (a.bnx > 0) {
-          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
-          const int bx = x - a.bx0, by = y - a.by0, bz = z - a.bz0;
-          if (bx >= 0 && bx < a.bnx && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz) {
-            const long long cell = ((long long)bz * a.bny + by) * a.bnx + bx;
+    for (int l = 0; l < L; ++l) {
+      const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
+      const int by = y - a.by0, bz = z - a.bz0;
+      const bool lbox = a.bnx > 0 && by >= 0 && by < a.bny && bz >= 0 && bz < a.bnz;  // uniform
+      const long long rowcell = lbox ? ((long long)bz * a.bny + by) * a.bnx : 0;
+      const int qy = y - a.py0, qz = z - a.pz0;
+      const bool lpbox = a.pnx > 0 && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz;  // uniform
+      const long long prow = lpbox ? ((long long)qz * a.pny + qy) * a.pnx : 0;
+#pragma unroll
+      for (int k = 0; k < XP; ++k) {
+        const int x = tid2 + k * NT;
+        g0[l][k] = g1[l][k] = g2[l][k] = (T)0;
+        if (x < n) {
+          const cpx<T> z1 = buf[x * RI + 3 * l], z2 = buf[x * RI + 3 * l + 1], z3 = buf[x * RI + 3 * l + 2];
+          const T ux = z1.re, uy = z1.im, uz = z2.re;
+          const T wx = z2.im, wy = z3.re, wz = z3.im;
+          T gx = uy * wz - uz * wy;
+          T gy = uz * wx - ux * wz;
+          T gz = ux * wy - uy * wx;
+          const int bx = x - a.bx0;
+          if constexpr (ST) {
+            const long long cell = (lbox && bx >= 0 && bx < a.bnx) ? rowcell + bx : -1;
+            penalize_static<T>(a, cell, (long long)y * n + x, ux, uy, uz, gx, gy, gz, aF0, aF1, aF2, aS0, aS1,
+                               aS2);
+          } else if (lbox && bx >= 0 && bx < a.bnx) {
+            const long long cell = rowcell + bx;
             const T ch = a.chi[cell];
             if (ch != (T)0) {
               const T sx = ux - a.us[cell], sy = uy - a.us[a.bcells + cell], sz = uz - a.us[2 * a.bcells + cell];
@@ -1375,58 +1390,63 @@ void xpass_fused(XArgs<T> a) {
               aF2 += (double)(ch * sz);
             }
           }
-        }
-        if (a.pnx > 0) {
-          const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
-          const int qx = x - a.px0, qy = y - a.py0, qz = z - a.pz0;
-          if (qx >= 0 && qx < a.pnx && qy >= 0 && qy < a.pny && qz >= 0 && qz < a.pnz) {
-            const long long cell = ((long long)qz * a.pny + qy) * a.pnx + qx;
+          const int qx = x - a.px0;
+          if (lpbox && qx >= 0 && qx < a.pnx) {
+            const long long cell = prow + qx;
             a.up[cell] = ux;
             a.up[a.pcells + cell] = uy;
             a.up[2 * a.pcells + cell] = uz;
           }
+          const double u2 = (double)(ux * ux + uy * uy + uz * uz);
+          aE += u2;
+          aM = fmax(aM, u2);
+          g0[l][k] = gx;
+          g1[l][k] = gy;
+          g2[l][k] = gz;
         }
-        const double u2 = (double)(ux * ux + uy * uy + uz * uz);
-        aE += u2;
-        aM = fmax(aM, u2);
-        g0[k] = gx;
-        g1[k] = gy;
-        g2[k] = gz;
       }
     }
     __syncthreads();
     T* bufr = reinterpret_cast<T*>(buf);
 #pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      const int it = tid2 + k * NT;
-      if (it < n * L) {
-        const int x = it % n, l = it / n;
-        buf[x * RF + l] = mk<T>(g0[k], g1[k]);
-        bufr[2 * (x * RF + L + (l >> 1)) + (l & 1)] = g2[k];
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+      for (int k = 0; k < XP; ++k) {
+        const int x = tid2 + k * NT;
+        if (x < n) {
+          buf[x * RF + l] = mk<T>(g0[l][k], g1[l][k]);
+          bufr[2 * (x * RF + L + (l >> 1)) + (l & 1)] = g2[l][k];
+        }
       }
     }
     __syncthreads();
     fft_n<T, WF, RF, NT, MAXE, false, N>(buf, a.plan, tws);
 
-    // 3) unpack the two real transforms of each signal, keep kx <= K
+    // 3) unpack the two real transforms of each signal, keep kx <= K; field f
+    //    of line l through a wave-uniform base and 32-bit offsets
     const int tid3 = opaque((int)threadIdx.x);
 #pragma unroll
-    for (int k = 0; k < FI; ++k) {
-      const int it = tid3 + k * NT;
-      if (it < nitems) {
-        const int x = it % kx1, s = it / kx1;
-        const int l = s / 3, f = s - 3 * (s / 3);
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
         const int sig = (f < 2) ? l : L + (l >> 1);
         const bool second = (f == 1) || (f == 2 && (l & 1));
-        const cpx<T> z = buf[x * RF + sig];
-        const cpx<T> zc = conj(buf[((n - x) % n) * RF + sig]);
-        cpx<T> r;
-        if (!second) r = scl(z + zc, (T)0.5);
-        else {
-          const cpx<T> d = z - zc;
-          r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+        cpx<T>* ob = a.gout + f * a.sfs + (long long)(line0 + l) * a.ld;
+#pragma unroll
+        for (int k = 0; k < XI; ++k) {
+          const int x = tid3 + k * NT;
+          if (x < kx1) {
+            const cpx<T> zv = buf[x * RF + sig];
+            const cpx<T> zc = conj(buf[(x == 0 ? 0 : n - x) * RF + sig]);
+            cpx<T> r;
+            if (!second) r = scl(zv + zc, (T)0.5);
+            else {
+              const cpx<T> d = zv - zc;
+              r = mk<T>((T)0.5 * d.im, (T)-0.5 * d.re);
+            }
+            *at_u32(ob, x) = r;
+          }
         }
-        a.gout[f * a.sfs + (long long)(line0 + l) * a.ld + x] = r;
       }
     }
     __syncthreads();
