@@ -1484,9 +1484,9 @@ __device__ __forceinline__ void load512_sig(const XArgs<T>& a, int line, int p, 
 // diagnostics, R2C of (Gx, Gy) stored; returns Gz in the physical layout.
 // On entry pf holds the line's first packed signal; on exit it holds the first
 // signal of line `next` (if next >= 0), loaded while this line is transformed.
-template <typename T, bool ST>
+template <typename T, bool ST, typename TW>
 __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int next, int lane, cpx<T>* X,
-                                             const cpx<T>* tIB, const cpx<T>* tC, const cpx<T>* tFB, Raw512<T>& pf,
+                                             const TW& tw, Raw512<T>& pf,
                                              T (&gz)[8], double& aF0, double& aF1, double& aF2, double& aE,
                                              double& aM, double& aS0, double& aS1, double& aS2) {
   constexpr int K = 170;  // the 2/3 band of 512 points: 3 * 170 < 512
@@ -1496,7 +1496,7 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
     cpx<T> v[8];
     pack512<T>(pf, lane, v);
     if (p < 2) load512_sig<T>(a, line, p + 1, lane, pf);  // prefetch: in flight during the transform
-    inv512<T>(v, X, lane, tIB, tC);
+    inv512<T>(v, X, lane, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) P[p][j] = v[j];
   }
@@ -1566,16 +1566,20 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  fwd512<T>(g, X, lane, tC, tFB);
+  fwd512<T>(g, X, lane, tw);
   unpack_store512<T>(g, lane, K, a.gout + (long long)line * a.ld, a.gout + a.sfs + (long long)line * a.ld);
 }
 
-template <typename T, bool ST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void xpass_wave512(XArgs<T> a) {
+// RT: the per-lane twiddle sets held in registers (44 VGPRs, 3 waves per SIMD)
+// instead of read from LDS in every transform (4 waves per SIMD): no twiddle
+// reads (9 transforms x 14 complex values per lane and line pair), a fifth of
+// the pass's LDS instructions
+template <typename T, bool ST, bool RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RT ? 3 : 4))) void xpass_wave512(XArgs<T> a) {
   __shared__ cpx<T> xbuf[4][kXBuf];
   // per-lane twiddle sets, [j][lane]: exp(+2 pi i lane j / 512), exp(-2 pi i lo j / 64),
   // exp(-2 pi i (lo + 8 j) hi / 512) with lo = lane & 7, hi = lane >> 3
-  __shared__ cpx<T> tws[3][512];
+  __shared__ cpx<T> tws[RT ? 1 : 3][RT ? 1 : 512];
   __shared__ double red[8 * 4];
   // Gz of the first line of a pair waits here (lane-private slots) while the
   // second line is transformed: registers are what limits the waves per SIMD
@@ -1585,11 +1589,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cpx<T>* X = xbuf[wv];
   constexpr int K = 170;
-  wave512_twiddles<T, 256>(tws, a.tw);
-  __syncthreads();
-  const cpx<T>* tIB = tws[0];
-  const cpx<T>* tC = tws[1];
-  const cpx<T>* tFB = tws[2];
+  using TW = std::conditional_t<RT, Tw512Reg<T>, Tw512Lds<T>>;
+  TW tw;
+  if constexpr (RT) {
+    tw.load(a.tw, lane);
+  } else {
+    wave512_twiddles<T, 256>(tws, a.tw);
+    __syncthreads();
+    tw = TW{tws[0], tws[1], tws[2], opaque(lane)};
+  }
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
   const int npairs = a.nlines / 2;
   Raw512<T> pf;
@@ -1599,20 +1607,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void x
   for (int pr = pr0; pr < npairs; pr += gridDim.x * 4) {
     const int nxt = (pr + gridDim.x * 4 < npairs) ? 2 * (pr + gridDim.x * 4) : -1;
     const int ln = opaque(lane);
+    if constexpr (!RT) tw.lane = ln;
     {
       T gza[8];
-      wave512_line<T, ST>(a, 2 * pr, 2 * pr + 1, ln, X, tIB, tC, tFB, pf, gza, aF0, aF1, aF2, aE, aM, aS0, aS1, aS2);
+      wave512_line<T, ST>(a, 2 * pr, 2 * pr + 1, ln, X, tw, pf, gza, aF0, aF1, aF2, aE, aM, aS0, aS1, aS2);
 #pragma unroll
       for (int j = 0; j < 8; ++j) gzs[wv][j][lane] = gza[j];
     }
     T gzb[8];
-    wave512_line<T, ST>(a, 2 * pr + 1, nxt, opaque(lane), X, tIB, tC, tFB, pf, gzb, aF0, aF1, aF2, aE, aM, aS0, aS1,
-                        aS2);
+    const int l2 = opaque(lane);
+    if constexpr (!RT) tw.lane = l2;
+    wave512_line<T, ST>(a, 2 * pr + 1, nxt, l2, X, tw, pf, gzb, aF0, aF1, aF2, aE, aM, aS0, aS1, aS2);
     cpx<T> g[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) g[j] = mk<T>(gzs[wv][j][lane], gzb[j]);
     const int l3 = opaque(lane);
-    fwd512<T>(g, X, l3, tC, tFB);
+    if constexpr (!RT) tw.lane = l3;
+    fwd512<T>(g, X, l3, tw);
     unpack_store512<T>(g, l3, K, a.gout + 2 * a.sfs + (long long)(2 * pr) * a.ld,
                        a.gout + 2 * a.sfs + (long long)(2 * pr + 1) * a.ld);
   }
@@ -2175,7 +2186,10 @@ static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
 template <typename T, bool ST>
 static hipError_t launch_xfused_st(const XArgs<T>& a, int grid, hipStream_t s) {
   if (a.n == 512) {
-    hipLaunchKernelGGL((xpass_wave512<T, ST>), dim3(grid), dim3(256), 0, s, a);
+    // FP32 without the static plane: twiddles in registers (168 VGPRs, 3 waves
+    // per SIMD; 6 % faster than in LDS).  FP64 would need twice the registers,
+    // and the static plane's instantiation spills at either count: LDS twiddles
+    hipLaunchKernelGGL((xpass_wave512<T, ST, sizeof(T) == 4 && !ST>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
   }
   // 800 points: the compile-time plan with its own workgroup shape

@@ -54,14 +54,48 @@ __device__ __forceinline__ void bfly8_inv_zero34(cpx<T> (&v)[8]) {
   v[7] = e3 - w3;
 }
 
+// Twiddle sources of the transforms below: IB(j) = exp(-2 pi i lane j / 512) and
+// C(j) = exp(+2 pi i lo j / 64) for j = 1..7, FB(j) = exp(+2 pi i (lo + 8 j) hi
+// / 512) for j = 0..7, lo = lane & 7, hi = lane >> 3.  Tw512Lds reads the
+// per-lane sets a workgroup keeps in LDS ([j][lane], wave512_twiddles);
+// Tw512Reg holds them in 44 VGPRs of the lane, loaded once from the axis table
+// tw[m] = exp(+2 pi i m / 512).
+template <typename T>
+struct Tw512Lds {
+  const cpx<T>* ib;
+  const cpx<T>* c;
+  const cpx<T>* fb;
+  int lane;
+  __device__ __forceinline__ cpx<T> IB(int j) const { return ib[64 * j + lane]; }
+  __device__ __forceinline__ cpx<T> C(int j) const { return c[64 * j + lane]; }
+  __device__ __forceinline__ cpx<T> FB(int j) const { return fb[64 * j + lane]; }
+};
+template <typename T>
+struct Tw512Reg {
+  cpx<T> ib[7], c[7], fb[8];
+  __device__ __forceinline__ void load(const cpx<T>* tw, int lane) {
+    const int lo = lane & 7, hi = lane >> 3;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+      ib[j - 1] = conj(tw[(lane * j) & 511]);
+      c[j - 1] = tw[(8 * lo * j) & 511];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fb[j] = tw[((lo + 8 * j) * hi) & 511];
+  }
+  __device__ __forceinline__ cpx<T> IB(int j) const { return ib[j - 1]; }
+  __device__ __forceinline__ cpx<T> C(int j) const { return c[j - 1]; }
+  __device__ __forceinline__ cpx<T> FB(int j) const { return fb[j]; }
+};
+
 // inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1;
 // v[3], v[4] must be zero on entry (pack512 leaves them so)
-template <typename T>
-__device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tIB, const cpx<T>* tC) {
+template <typename T, typename TW>
+__device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const TW& tw) {
   const int hi = lane >> 3, lo = lane & 7;
   bfly8_inv_zero34<T>(v);
 #pragma unroll
-  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tIB[64 * j + lane]);
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tw.IB(j));
 #pragma unroll
   for (int j = 0; j < 8; ++j) X[xslot1(j, lane)] = v[j];
   wave_sync();
@@ -70,7 +104,7 @@ __device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, cons
   wave_sync();
   Bfly<T, 8, 1>::run(v);
 #pragma unroll
-  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], conj(tC[64 * j + lane]));
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], conj(tw.C(j)));
 #pragma unroll
   for (int j = 0; j < 8; ++j) X[xslot2(hi, j, lo)] = v[j];
   wave_sync();
@@ -79,14 +113,18 @@ __device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, cons
   wave_sync();
   Bfly<T, 8, 1>::run(v);
 }
+template <typename T>
+__device__ __forceinline__ void inv512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tIB, const cpx<T>* tC) {
+  inv512<T>(v, X, lane, Tw512Lds<T>{tIB, tC, nullptr, lane});
+}
 
 // forward: v[y2] = g[x1 + 8 y1 + 64 y2]  ->  v[r] = G[lane + 64 r] (unnormalized)
-template <typename T>
-__device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tC, const cpx<T>* tFB) {
+template <typename T, typename TW>
+__device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, const TW& tw) {
   const int hi = lane >> 3, lo = lane & 7;
   Bfly<T, 8, -1>::run(v);
 #pragma unroll
-  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tC[64 * j + lane]);
+  for (int j = 1; j < 8; ++j) v[j] = cmul(v[j], tw.C(j));
 #pragma unroll
   for (int j = 0; j < 8; ++j) X[xslot2(hi, lo, j)] = v[j];
   wave_sync();
@@ -95,7 +133,7 @@ __device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, cons
   wave_sync();
   Bfly<T, 8, -1>::run(v);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = cmul(v[j], tFB[64 * j + lane]);
+  for (int j = 0; j < 8; ++j) v[j] = cmul(v[j], tw.FB(j));
 #pragma unroll
   for (int j = 0; j < 8; ++j) X[xslot1(hi, lo + 8 * j)] = v[j];
   wave_sync();
@@ -103,6 +141,10 @@ __device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, cons
   for (int j = 0; j < 8; ++j) v[j] = X[xslot1(j, lane)];
   wave_sync();
   Bfly<T, 8, -1>::run(v);
+}
+template <typename T>
+__device__ __forceinline__ void fwd512(cpx<T> (&v)[8], cpx<T>* X, int lane, const cpx<T>* tC, const cpx<T>* tFB) {
+  fwd512<T>(v, X, lane, Tw512Lds<T>{nullptr, tC, tFB, lane});
 }
 
 // One complex value through a buffer resource whose bound is the band
