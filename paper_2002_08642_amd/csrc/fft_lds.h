@@ -95,6 +95,15 @@ __device__ __forceinline__ int opaque(int x) {
   __asm__ volatile("" : "+v"(x));
   return x;
 }
+// The thread index through opaque(), with its range restated: the compiler
+// then drops the bounds tests of work items that every thread has (and the
+// code of items that none has), which it cannot see through the asm barrier.
+template <int NT>
+__device__ __forceinline__ int opaque_tid() {
+  const int t = opaque((int)threadIdx.x);
+  __builtin_assume(t >= 0 && t < NT);
+  return t;
+}
 
 constexpr int kMaxStages = 16;
 
@@ -201,7 +210,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int n, int Ns, const cpx<
   const int tstride = n / (Ns * R);
   // An opaque copy of the thread id keeps the compiler from hoisting the LDS
   // addresses of every radix variant out of the stage loop (that costs ~100 VGPRs).
-  const int tid = opaque((int)threadIdx.x);
+  const int tid = opaque_tid<NT>();
   cpx<T> v[KB][R];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     // it is in flight while output o is transformed.
     // unconditional loads (clamped rows and columns), zeroed when written to LDS
     auto load_into = [&](int lq, cpx<T>(&R)[MAXO]) __attribute__((always_inline)) {
-      const int tq = opaque((int)threadIdx.x);
+      const int tq = opaque_tid<NT>();
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
       const cpx<T>* in = a.in + lq * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         into_b = (o == 1 || o == 5) ? 1 : 0;
       }
       if (lq < 0) return;
-      const int tq = opaque((int)threadIdx.x);
+      const int tq = opaque_tid<NT>();
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
       // unconditional loads from clamped rows and columns: a load under a branch
       // makes the compiler wait for it where the branches join, which would end
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       // the load issued after this output is in LDS: field and set
       constexpr int nlq = CURLM ? ((o == 0) ? 2 : (o == 2) ? 1 : (o == 4) ? 0 : -1) : (o + 1 < NO ? o + 1 : -1);
       constexpr bool nb_set = CURLM ? (o == 0 || o == 4) : ((o + 1) & 1);
-      const int tid = opaque((int)threadIdx.x);
+      const int tid = opaque_tid<NT>();
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
       const int ix = c % a.kxp, iy = c / a.kxp;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     auto generic = [&]() {
       load_for(0);
       for (int o = 0; o < nout; ++o) {
-        const int tid = opaque((int)threadIdx.x);
+        const int tid = opaque_tid<NT>();
         const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
         const bool cok = c < a.C && (c % a.kxp) < a.kx1;
         // output field and combination: o = 0 ux = A; 1 wy = i(kz A - kx B); 2 uz = B;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       __syncthreads();
       auto mstep = [&](auto oc) {
         constexpr int o = decltype(oc)::value;
-        const int tid = opaque((int)threadIdx.x);
+        const int tid = opaque_tid<NT>();
         const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
         const bool cok = c < a.C && (c % a.kxp) < a.kx1;
 #pragma unroll
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     constexpr bool Z5 = (MODE == COL_INV_CURL5);
     cpx<T> RA[MAXO], RB[MAXO];
     auto load_into = [&](int lq, cpx<T>(&R)[MAXO]) {
-      const int tq = opaque((int)threadIdx.x);
+      const int tq = opaque_tid<NT>();
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
       // unconditional loads (clamped rows and columns), zeroed when written to
       // LDS: a load under a branch would also be waited for where the branches join
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       constexpr int src = Z5 ? ((o == 2) ? 1 : (o == 1 || o == 3) ? 2 : 0) : ((o == 1 || o == 4) ? 1 : (o == 2) ? 2 : 0);
       constexpr int lq = Z5 ? ((o == 0) ? 2 : (o == 2) ? 1 : -1) : ((o == 0) ? 1 : (o == 2) ? 2 : (o == 3) ? 3 : (o == 4) ? 4 : -1);
       constexpr bool to_b = Z5 ? (o == 0) : (o == 0 || o == 3);
-      const int tid = opaque((int)threadIdx.x);
+      const int tid = opaque_tid<NT>();
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       const bool cok = c < a.C && (c % a.kxp) < a.kx1;
       const int ix = c % a.kxp, iy = c / a.kxp;
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     // rows of field f into tmp: unconditional loads (clamped row and column);
     // columns outside the band are transformed but never stored
     auto load_field = [&](int f) __attribute__((always_inline)) {
-      const int tq = opaque((int)threadIdx.x);
+      const int tq = opaque_tid<NT>();
       const int cq = blockIdx.x * W + tq % W, rq = tq / W;
       const cpx<T>* in = a.in + f * a.in_fs + ib + (cq < a.C ? cq : 0);
 #pragma unroll
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     // field f from tmp: LDS, transform, band rows out (or stashed); with
     // prefetch, the loads of field f + 1 are in flight during the transform
     auto field = [&](int f, bool prefetch) __attribute__((always_inline)) {
-      const int tid = opaque((int)threadIdx.x);
+      const int tid = opaque_tid<NT>();
       const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
       if constexpr (REGZ) {
         // the loaded rows r0 + 32 m are the inputs of the span-1 butterflies
@@ -1170,7 +1170,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         auto zstep = [&](auto oc) {
           constexpr int o = decltype(oc)::value;
           constexpr int fo = (o == 1) ? 4 : (o == 4) ? 1 : o;
-          const int tid = opaque((int)threadIdx.x);
+          const int tid = opaque_tid<NT>();
           const int col = tid % W, r0 = tid / W, c = blockIdx.x * W + col;
           const bool cok = c < a.C && (c % a.kxp) < a.kx1;
 #pragma unroll
@@ -1299,7 +1299,7 @@ void xpass_fused(XArgs<T> a) {
   double aF0 = 0, aF1 = 0, aF2 = 0, aE = 0, aM = 0, aS0 = 0, aS1 = 0, aS2 = 0;
 
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const int tid = opaque((int)threadIdx.x);
+    const int tid = opaque_tid<NT>();
     const int line0 = g * L;
     // 1) Hermitian-extended packed spectra, signal s = 3 l + p: a wave-uniform
     //    line base per field and 32-bit offsets x (no 64-bit vector address
@@ -1350,7 +1350,7 @@ void xpass_fused(XArgs<T> a) {
     // 2) pointwise nonlinear + penalization term and diagnostics, line by line
     //    (the line's y, z and its rows of the mask sub-box once per line)
     T g0[L][XP], g1[L][XP], g2[L][XP];
-    const int tid2 = opaque((int)threadIdx.x);
+    const int tid2 = opaque_tid<NT>();
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int yl = y0 + l, wrap = yl >= a.ny, y = yl - (wrap ? a.ny : 0), z = z0 + wrap;
@@ -1424,7 +1424,7 @@ void xpass_fused(XArgs<T> a) {
 
     // 3) unpack the two real transforms of each signal, keep kx <= K; field f
     //    of line l through a wave-uniform base and 32-bit offsets
-    const int tid3 = opaque((int)threadIdx.x);
+    const int tid3 = opaque_tid<NT>();
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
 #pragma unroll
