@@ -186,16 +186,20 @@ __device__ __forceinline__ void st_band(__amdgpu_buffer_rsrc_t r, int k, cpx<T> 
 // Unpack the transforms X, Y of the two real signals packed in g (natural layout,
 // g[r] = G[lane + 64 r]) and store X to dx, Y to dy for k <= K (K < 192; the
 // stores beyond K fall outside the lines' band resources and are dropped).
+// The partner n - k of slot r is slot 7 - r of lane 64 - lane; lane 0, which is
+// its own source, offers its slot (8 - r) mod 8 instead, so no lane needs a
+// select after the exchange (one would wait for every exchange in flight).
 template <typename T>
 __device__ __forceinline__ void unpack_store512(const cpx<T> (&g)[8], int lane, int K, cpx<T>* dx, cpx<T>* dy) {
   const int src = (64 - lane) & 63;
+  const bool l0 = lane == 0;
   const __amdgpu_buffer_rsrc_t rx = band_rsrc(dx, K + 1), ry = band_rsrc(dy, K + 1);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
+    const cpx<T> sv = l0 ? g[(8 - r) & 7] : g[7 - r];
     cpx<T> p;
-    p.re = __shfl(g[7 - r].re, src, 64);
-    p.im = __shfl(g[7 - r].im, src, 64);
-    if (lane == 0) p = g[(8 - r) & 7];
+    p.re = __shfl(sv.re, src, 64);
+    p.im = __shfl(sv.im, src, 64);
     const int k = lane + 64 * r;
     const cpx<T> zc = conj(p);
     const cpx<T> d = g[r] - zc;
@@ -245,24 +249,26 @@ __device__ __forceinline__ cpx<T> shfl_cpx(cpx<T> v, int src) {
 }
 
 // Z[k] = A[k] + i B[k] with the Hermitian partners, in the natural layout
-// v[r] = Z[lane + 64 r].  The loads left every slot outside the band zero, so
-// only lane 0's partner of k = 320 (its own slot 2, in the band) is masked.
+// v[r] = Z[lane + 64 r].  The loads left every slot outside the band zero.  The
+// partner A[n - k] of k = lane + 64 (5 + q) is slot 2 - q of lane 64 - lane;
+// lane 0, which is its own source, offers its slot 3 - q instead (zero for
+// q = 0: n - k = 192 lies outside the band), so no lane needs a select after
+// the exchange.  At k = 0 lane 0 takes the real parts of A and B: its imaginary
+// parts enter as +0 and -0, for which x - (+0) = x and (-0) + x = x exactly.
 template <typename T>
 __device__ __forceinline__ void pack512(const Raw512<T>& w, int lane, cpx<T> (&v)[8]) {
+  const int src = (64 - lane) & 63;
+  const bool l0 = lane == 0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
-    // A[n - k], k = lane + 64 (5 + q): slot 2 - q of lane 64 - lane; lane 0
-    // holds it itself in slot 3 - q (for q = 0, n - k = 192 is outside the band)
-    const int src = (64 - lane) & 63;
-    cpx<T> pa = shfl_cpx(w.a[2 - q], src), pb = shfl_cpx(w.b[2 - q], src);
-    if (lane == 0) {
-      pa = q > 0 ? w.a[3 - q] : mk<T>(0, 0);
-      pb = q > 0 ? w.b[3 - q] : mk<T>(0, 0);
-    }
+    const cpx<T> oa = q > 0 ? w.a[3 - q] : mk<T>(0, 0), ob = q > 0 ? w.b[3 - q] : mk<T>(0, 0);
+    const cpx<T> pa = shfl_cpx(l0 ? oa : w.a[2 - q], src), pb = shfl_cpx(l0 ? ob : w.b[2 - q], src);
     v[5 + q] = mk<T>(pa.re + pb.im, pb.re - pa.im);
   }
-  if (lane == 0) v[0] = mk<T>(w.a[0].re, w.b[0].re);  // k = 0 of two real signals
+  const T bim0 = l0 ? (T)0 : w.b[0].im, aim0 = l0 ? (T)-0.0 : w.a[0].im;
+  v[0] = mk<T>(w.a[0].re - bim0, aim0 + w.b[0].re);
+#pragma unroll
+  for (int q = 1; q < 3; ++q) v[q] = mk<T>(w.a[q].re - w.b[q].im, w.a[q].im + w.b[q].re);
   v[3] = mk<T>(0, 0);
   v[4] = mk<T>(0, 0);
 }
