@@ -1570,12 +1570,14 @@ __device__ __forceinline__ void wave512_line(const XArgs<T>& a, int line, int ne
   unpack_store512<T>(g, lane, K, a.gout + (long long)line * a.ld, a.gout + a.sfs + (long long)line * a.ld);
 }
 
-// RT: the per-lane twiddle sets held in registers (44 VGPRs, 3 waves per SIMD)
-// instead of read from LDS in every transform (4 waves per SIMD): no twiddle
-// reads (9 transforms x 14 complex values per lane and line pair), a fifth of
-// the pass's LDS instructions
-template <typename T, bool ST, bool RT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RT ? 3 : 4))) void xpass_wave512(XArgs<T> a) {
+// TM = 1: the per-lane twiddle sets held in registers (44 VGPRs, 3 waves per
+// SIMD) instead of read from LDS in every transform (4 waves per SIMD): no
+// twiddle reads (9 transforms x 14 complex values per lane and line pair), a
+// fifth of the pass's LDS instructions; TM = 2: only the set C in registers;
+// TM = 0: all sets from LDS
+template <typename T, bool ST, int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 1 ? 3 : 4))) void xpass_wave512(XArgs<T> a) {
+  constexpr bool RT = TM == 1;
   __shared__ cpx<T> xbuf[4][kXBuf];
   // per-lane twiddle sets, [j][lane]: exp(+2 pi i lane j / 512), exp(-2 pi i lo j / 64),
   // exp(-2 pi i (lo + 8 j) hi / 512) with lo = lane & 7, hi = lane >> 3
@@ -1589,10 +1591,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RT ? 3 : 4)
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cpx<T>* X = xbuf[wv];
   constexpr int K = 170;
-  using TW = std::conditional_t<RT, Tw512Reg<T>, Tw512Lds<T>>;
+  using TW = std::conditional_t<RT, Tw512Reg<T>, std::conditional_t<TM == 2, Tw512Mix<T>, Tw512Lds<T>>>;
   TW tw;
   if constexpr (RT) {
     tw.load(a.tw, lane);
+  } else if constexpr (TM == 2) {
+    wave512_twiddles<T, 256>(tws, a.tw);
+    __syncthreads();
+    tw.ib = tws[0];
+    tw.fb = tws[2];
+    tw.lane = opaque(lane);
+#pragma unroll
+    for (int j = 1; j < 8; ++j) tw.c[j - 1] = tws[1][64 * j + lane];
   } else {
     wave512_twiddles<T, 256>(tws, a.tw);
     __syncthreads();
@@ -2186,10 +2196,12 @@ static hipError_t launch_xfused_l(const XArgs<T>& a, int grid, hipStream_t s) {
 template <typename T, bool ST>
 static hipError_t launch_xfused_st(const XArgs<T>& a, int grid, hipStream_t s) {
   if (a.n == 512) {
-    // FP32 without the static plane: twiddles in registers (168 VGPRs, 3 waves
-    // per SIMD; 6 % faster than in LDS).  FP64 would need twice the registers,
-    // and the static plane's instantiation spills at either count: LDS twiddles
-    hipLaunchKernelGGL((xpass_wave512<T, ST, sizeof(T) == 4 && !ST>), dim3(grid), dim3(256), 0, s, a);
+    // Without the static plane, FP32 holds all twiddles in registers (166
+    // VGPRs, 3 waves per SIMD; 6 % faster than in LDS) and FP64 the set used by
+    // every transform (242 VGPRs, the 2 waves per SIMD it has anyway; 1 %
+    // faster); the static plane's instantiations keep the LDS sets
+    constexpr int tm = ST ? 0 : (sizeof(T) == 4 ? 1 : 2);
+    hipLaunchKernelGGL((xpass_wave512<T, ST, tm>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
   }
   // 800 points: the compile-time plan with its own workgroup shape

@@ -88,6 +88,18 @@ struct Tw512Reg {
   __device__ __forceinline__ cpx<T> FB(int j) const { return fb[j]; }
 };
 
+// IB and FB from the LDS sets, C (used by every transform) held by the lane
+template <typename T>
+struct Tw512Mix {
+  const cpx<T>* ib;
+  const cpx<T>* fb;
+  int lane;
+  cpx<T> c[7];
+  __device__ __forceinline__ cpx<T> IB(int j) const { return ib[64 * j + lane]; }
+  __device__ __forceinline__ cpx<T> C(int j) const { return c[j - 1]; }
+  __device__ __forceinline__ cpx<T> FB(int j) const { return fb[64 * j + lane]; }
+};
+
 // inverse: v[r] = Z[lane + 64 r]  ->  v[y2] = z[x1 + 8 y1 + 64 y2], lane = 8 x1 + y1;
 // v[3], v[4] must be zero on entry (pack512 leaves them so)
 template <typename T, typename TW>
