@@ -1661,15 +1661,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 1 ? 3
 // line and (wz of line 0 + i wz of line 1), three inverse and three forward
 // transforms per pair; every input of a pair is read before its outputs are
 // stored, so the pass runs in place.
+// FP32 holds the twiddle sets in registers (the kernel stays within 128 VGPRs),
+// FP64 reads them from LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void xsponge_wave512(XArgs<T> a, const T* g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void xsponge_wave512(
+    XArgs<T> a, const T* g) {
+  constexpr bool RT = sizeof(T) == 4;
   __shared__ cpx<T> xbuf[4][kXBuf];
-  __shared__ cpx<T> tws[3][512];
+  __shared__ cpx<T> tws[RT ? 1 : 3][RT ? 1 : 512];
   __shared__ T gxs[512];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cpx<T>* X = xbuf[wv];
   constexpr int K = 170;
-  wave512_twiddles<T, 256>(tws, a.tw);
+  using TW = std::conditional_t<RT, Tw512Reg<T>, Tw512Lds<T>>;
+  TW tw;
+  if constexpr (RT) tw.load(a.tw, lane);
+  else {
+    wave512_twiddles<T, 256>(tws, a.tw);
+    tw = TW{tws[0], tws[1], tws[2], lane};
+  }
   for (int i = threadIdx.x; i < 512; i += 256) gxs[i] = g[i];
   __syncthreads();
   const T* gy = g + 512;
@@ -1688,25 +1698,25 @@ __global__ __launch_bounds__(256) void xsponge_wave512(XArgs<T> a, const T* g) {
     cpx<T> v[8];
     // lane holds the grid points x = (lane >> 3) + 8 (lane & 7) + 64 j
     pack512<T>(w0, lane, v);
-    inv512<T>(v, X, lane, tws[0], tws[1]);
+    inv512<T>(v, X, lane, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = scl(v[j], fmax(gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j], m0));
-    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    fwd512<T>(v, X, lane, tw);
     unpack_store512<T>(v, lane, K, a.spec + 3 * a.sfs + o0, a.spec + 4 * a.sfs + o0);
     pack512<T>(w1, lane, v);
-    inv512<T>(v, X, lane, tws[0], tws[1]);
+    inv512<T>(v, X, lane, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = scl(v[j], fmax(gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j], m1));
-    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    fwd512<T>(v, X, lane, tw);
     unpack_store512<T>(v, lane, K, a.spec + 3 * a.sfs + o1, a.spec + 4 * a.sfs + o1);
     pack512<T>(w2, lane, v);
-    inv512<T>(v, X, lane, tws[0], tws[1]);
+    inv512<T>(v, X, lane, tw);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const T gxv = gxs[(lane >> 3) + 8 * (lane & 7) + 64 * j];
       v[j] = mk<T>(v[j].re * fmax(gxv, m0), v[j].im * fmax(gxv, m1));
     }
-    fwd512<T>(v, X, lane, tws[1], tws[2]);
+    fwd512<T>(v, X, lane, tw);
     unpack_store512<T>(v, lane, K, a.spec + 5 * a.sfs + o0, a.spec + 5 * a.sfs + o1);
   }
 }
